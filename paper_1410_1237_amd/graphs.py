@@ -1,0 +1,233 @@
+"""Seeded synthetic input graphs (SBM, R-MAT, weighted Chung-Lu) and the
+named workloads built from them.
+
+This module holds none of the community-detection arithmetic: it only makes
+inputs, through the C generator in ``graphgen.c`` (Philox4x32-10 counter-based
+draws, thread-count independent).  Both the oracle tests and the GPU path take
+their inputs from here.
+
+The families stand in for the shapes of the paper's inputs (Table 1):
+internet/social graphs -> R-MAT, citation/collaboration graphs -> planted
+SBM, weighted metagenomic similarity graphs -> weighted Chung-Lu.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "_graphgen.so")
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            raise RuntimeError(f"graph generator library not built: {_LIB} (run __graft_entry__.build())")
+        lib = ctypes.CDLL(_LIB)
+        vp, i64, i32, u64, u32, dbl = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                       ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double)
+        lib.gg_sbm.restype = vp
+        lib.gg_sbm.argtypes = [i64, i32, dbl, dbl, i32, u64, u32]
+        lib.gg_rmat.restype = vp
+        lib.gg_rmat.argtypes = [i32, i64, dbl, dbl, dbl, i32, u64, i64]
+        lib.gg_chung_lu.restype = vp
+        lib.gg_chung_lu.argtypes = [i64, dbl, dbl, dbl, i64, i32, u64]
+        lib.gg_info.argtypes = [vp, ctypes.POINTER(i64)]
+        lib.gg_copy.argtypes = [vp, vp, vp, vp]
+        lib.gg_free.argtypes = [vp]
+        lib.gg_uniform4.argtypes = [u64, u32, u64, ctypes.POINTER(dbl)]
+        lib.gg_philox4x32_10.argtypes = [ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class CSR:
+    """Undirected graph as a symmetric CSR: int64 offsets[n+1], int32 cols[nnz]
+    (sorted, unique per row), int32 weights[nnz] or None for unit weights."""
+    n: int
+    offsets: np.ndarray
+    cols: np.ndarray
+    weights: Optional[np.ndarray]
+    name: str = ""
+
+    @property
+    def nnz(self) -> int:
+        return int(self.offsets[-1]) if self.n >= 0 else 0
+
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+    def describe(self) -> dict:
+        d = self.degrees()
+        nz = d[d > 0]
+        return {
+            "name": self.name, "n": self.n, "nnz": self.nnz,
+            "max_deg": int(d.max()) if self.n else 0,
+            "avg_deg": float(d.mean()) if self.n else 0.0,
+            "deg_rsd": float(d.std() / d.mean()) if self.n and d.mean() > 0 else 0.0,
+            "isolated": int((d == 0).sum()), "deg1": int((d == 1).sum()),
+            "weighted": self.weights is not None,
+            "nonempty_rows": int(nz.size),
+        }
+
+
+def _take(h) -> CSR:
+    lib = _load()
+    info = (ctypes.c_int64 * 3)()
+    lib.gg_info(h, info)
+    n, nnz, has_w = int(info[0]), int(info[1]), bool(info[2])
+    off = np.empty(n + 1, dtype=np.int64)
+    col = np.empty(max(nnz, 1), dtype=np.int32)
+    w = np.empty(max(nnz, 1), dtype=np.int32) if has_w else None
+    lib.gg_copy(h, off.ctypes.data, col.ctypes.data, w.ctypes.data if w is not None else None)
+    lib.gg_free(h)
+    return CSR(n, off, col[:nnz], w[:nnz] if w is not None else None)
+
+
+def sbm(n: int, blocks: int, p_in: float, p_out: float, wmax: int = 1, seed: int = 1,
+        stream: int = 0) -> CSR:
+    """Planted-partition SBM: contiguous near-equal blocks, every within-block
+    pair an edge with probability p_in, every cross pair with p_out (geometric
+    skip sampling), weights uniform in [1, wmax] (unit if wmax <= 1)."""
+    g = _take(_load().gg_sbm(n, blocks, p_in, p_out, wmax, seed, stream))
+    g.name = f"sbm(n={n},B={blocks},p_in={p_in:g},p_out={p_out:g},wmax={wmax},seed={seed},stream={stream})"
+    return g
+
+
+def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+         wmax: int = 1, seed: int = 2, n_keep: int = 0) -> CSR:
+    """R-MAT with edge_factor * 2^scale samples, seeded id permutation,
+    self-loops dropped, duplicates merged, symmetrized."""
+    g = _take(_load().gg_rmat(scale, edge_factor, a, b, c, wmax, seed, n_keep))
+    g.name = f"rmat(scale={scale},ef={edge_factor},a={a},b={b},c={c},wmax={wmax},seed={seed},n_keep={n_keep})"
+    return g
+
+
+def chung_lu(n: int, gamma: float, w_top: float, w_sum: float, m_edges: int, wmax: int = 100,
+             seed: int = 4) -> CSR:
+    """Weighted Chung-Lu: power-law expected degrees (exponent gamma, top
+    expected degree w_top, total w_sum), exactly m_edges distinct undirected
+    non-loop edges, weights uniform in [1, wmax]."""
+    g = _take(_load().gg_chung_lu(n, gamma, w_top, w_sum, m_edges, wmax, seed))
+    g.name = f"chung_lu(n={n},gamma={gamma},w_top={w_top:g},w_sum={w_sum:g},m={m_edges},wmax={wmax},seed={seed})"
+    return g
+
+
+def uniform4(seed: int, stream: int, index: int) -> tuple:
+    out = (ctypes.c_double * 4)()
+    _load().gg_uniform4(seed, stream, index, out)
+    return tuple(out)
+
+
+def philox4x32_10(ctr, key) -> tuple:
+    c = (ctypes.c_uint32 * 4)(*ctr)
+    k = (ctypes.c_uint32 * 2)(*key)
+    o = (ctypes.c_uint32 * 4)()
+    _load().gg_philox4x32_10(c, k, o)
+    return tuple(o)
+
+
+# ---------------------------------------------------------------------------
+# named workloads
+# ---------------------------------------------------------------------------
+
+def sbm_1000() -> CSR:
+    """Planted-partition SBM: 1,000 vertices, 10 blocks of 100, p_in 0.10,
+    p_out 0.002, unit weights."""
+    g = sbm(1000, 10, 0.10, 0.002, wmax=1, seed=1)
+    g.name = "sbm_n1000_b10"
+    return g
+
+
+def rmat_scale(scale: int, seed: int) -> CSR:
+    """R-MAT, edge factor 16, (a, b, c, d) = (0.57, 0.19, 0.19, 0.05), unit weights."""
+    g = rmat(scale, 16, 0.57, 0.19, 0.19, wmax=1, seed=seed)
+    g.name = f"rmat_s{scale}_ef16"
+    return g
+
+
+def rmat20() -> CSR:
+    return rmat_scale(20, 2)
+
+
+def rmat24() -> CSR:
+    return rmat_scale(24, 3)
+
+
+def chung_lu_8m() -> CSR:
+    """Weighted Chung-Lu: 8,000,000 vertices, 100,000,000 undirected edges,
+    degree exponent 2.1, top expected degree 50,000, weights uniform in [1, 100]."""
+    g = chung_lu(8_000_000, 2.1, 50_000.0, 2.0e8, 100_000_000, wmax=100, seed=4)
+    g.name = "chunglu_n8M_m100M"
+    return g
+
+
+def batch_sbm_params(i: int, seed: int = 5) -> dict:
+    """Parameters of graph i of the batched SBM mix: n log-uniform in
+    [64, 65536], B uniform in {4..64} clamped to n // 8, average degree
+    uniform in [8, 32], p_out/p_in uniform in [0.01, 0.2], weights in [1, 10]."""
+    u = uniform4(seed, 100, i)
+    n = int(round(math.exp(math.log(64) + u[0] * (math.log(65536) - math.log(64)))))
+    n = min(max(n, 64), 65536)
+    B = 4 + min(int(u[1] * 61), 60)
+    B = max(1, min(B, n // 8))
+    d = 8.0 + 24.0 * u[2]
+    r = 0.01 + 0.19 * u[3]
+    s = n / B
+    p_in = min(1.0, d / ((s - 1) + r * (n - s)))
+    return {"n": n, "blocks": B, "p_in": p_in, "p_out": r * p_in, "wmax": 10}
+
+
+def batch_sbm(i: int, seed: int = 5) -> CSR:
+    p = batch_sbm_params(i, seed)
+    g = sbm(p["n"], p["blocks"], p["p_in"], p["p_out"], wmax=p["wmax"], seed=seed, stream=1000 + i)
+    g.name = f"batch_sbm[{i}]"
+    return g
+
+
+def served_job_params(i: int, seed: int = 6) -> dict:
+    """Job i of the served mix: n log-uniform in [1e3, 2e6]; half SBM (average
+    degree 16, B in {4..64}, p_out/p_in in [0.01, 0.2]), half R-MAT (scale
+    ceil(log2 n), first n ids of the permutation, edge factor in {8..32});
+    unit or [1, 100] weights with equal odds."""
+    u = uniform4(seed, 200, i)
+    v = uniform4(seed, 201, i)
+    n = int(round(math.exp(math.log(1e3) + u[0] * (math.log(2e6) - math.log(1e3)))))
+    kind = "sbm" if u[1] < 0.5 else "rmat"
+    wmax = 1 if u[2] < 0.5 else 100
+    if kind == "sbm":
+        B = 4 + min(int(u[3] * 61), 60)
+        B = max(1, min(B, n // 8))
+        r = 0.01 + 0.19 * v[0]
+        s = n / B
+        p_in = min(1.0, 16.0 / ((s - 1) + r * (n - s)))
+        return {"kind": kind, "n": n, "blocks": B, "p_in": p_in, "p_out": r * p_in, "wmax": wmax}
+    ef = 8 + min(int(u[3] * 25), 24)
+    return {"kind": kind, "n": n, "scale": int(math.ceil(math.log2(n))), "edge_factor": ef, "wmax": wmax}
+
+
+def served_job(i: int, seed: int = 6) -> CSR:
+    p = served_job_params(i, seed)
+    if p["kind"] == "sbm":
+        g = sbm(p["n"], p["blocks"], p["p_in"], p["p_out"], wmax=p["wmax"], seed=seed, stream=2000 + i)
+    else:
+        g = rmat(p["scale"], p["edge_factor"], 0.57, 0.19, 0.19, wmax=p["wmax"],
+                 seed=(seed << 20) + i, n_keep=p["n"])
+    g.name = f"served_job[{i}]"
+    return g
+
+
+WORKLOADS = {
+    "sbm_n1000": sbm_1000,
+    "rmat_s20": rmat20,
+    "rmat_s24": rmat24,
+    "chunglu_8m": chung_lu_8m,
+}
