@@ -1,0 +1,1148 @@
+// Host runtime and C ABI of liblouvain.so: the handle (device arena, stream,
+// phase state), the phase driver of the paper's parallel algorithm
+// (Sec. 5.4: vertex following, coloring, phases of synchronous sweeps,
+// rebuild) with the coloring schedule and thresholds of Sec. 6.1, and exact
+// 128-bit host arithmetic for modularity and thresholds.
+#include "louvain.h"
+#include "lv.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using lv::i128;
+using lv::u128;
+
+// ---------------------------------------------------------------------------
+// process-wide caching pool of device buffers (reused across handles of equal
+// sizes so that repeated ingest/run/destroy cycles do not re-allocate)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Pool {
+    std::mutex mu;
+    std::map<std::pair<int, size_t>, std::vector<void *>> free_;
+    size_t cached = 0;
+    static constexpr size_t CAP = (size_t)96 << 30;
+
+    hipError_t get(void **p, size_t bytes, int dev)
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto it = free_.find({dev, bytes});
+            if (it != free_.end() && !it->second.empty()) {
+                *p = it->second.back();
+                it->second.pop_back();
+                cached -= bytes;
+                return hipSuccess;
+            }
+        }
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            trim(dev);
+            e = hipMalloc(p, bytes);
+        }
+        return e;
+    }
+    void put(void *p, size_t bytes, int dev)
+    {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu);
+        if (cached + bytes > CAP) {
+            (void)hipFree(p);
+            return;
+        }
+        free_[{dev, bytes}].push_back(p);
+        cached += bytes;
+    }
+    void trim(int dev)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &kv : free_) {
+            if (kv.first.first != dev) continue;
+            for (void *p : kv.second) {
+                (void)hipFree(p);
+                cached -= kv.first.second;
+            }
+            kv.second.clear();
+        }
+    }
+};
+Pool &pool()
+{
+    static Pool *p = new Pool(); // never destroyed: buffers live until process end
+    return *p;
+}
+
+std::string g_init_error;
+
+// ---- exact host arithmetic ---------------------------------------------------
+u128 mag(i128 x) { return x < 0 ? (u128)0 - (u128)x : (u128)x; }
+
+// x*p < y*q with x, y < 2^127 and p, q < 2^64, by 64-bit limbs
+bool prod_less(u128 x, uint64_t p, u128 y, uint64_t q)
+{
+    auto mul = [](u128 a, uint64_t b, uint64_t out[3]) {
+        const u128 lo = (u128)(uint64_t)a * b;
+        const u128 hi = (u128)(uint64_t)(a >> 64) * b + (lo >> 64);
+        out[0] = (uint64_t)lo;
+        out[1] = (uint64_t)hi;
+        out[2] = (uint64_t)(hi >> 64);
+    };
+    uint64_t a[3], b[3];
+    mul(x, p, a);
+    mul(y, q, b);
+    for (int t = 2; t >= 0; --t)
+        if (a[t] != b[t]) return a[t] < b[t];
+    return false;
+}
+
+// net gain below theta: (now - before) < theta * ref, ref = |before| (relative) or D (absolute)
+bool below_threshold(i128 now, i128 before, i128 D, louvain_ratio th, int mode)
+{
+    if (now < before) return true;
+    const u128 gain = (u128)(now - before);
+    const u128 ref = mode == 0 ? mag(before) : (u128)D;
+    return prod_less(gain, (uint64_t)th.den, ref, (uint64_t)th.num);
+}
+
+// correctly rounded (ties to even) double of N / D, 0 < D, |N| <= D
+double exact_ratio(i128 N, i128 D)
+{
+    if (N == 0) return 0.0;
+    const bool neg = N < 0;
+    u128 num = mag(N);
+    const u128 den = (u128)D;
+    // scale num by 2^s (s <= 0) so that den <= num < 2 den; |N| <= D keeps num < 2^127
+    int s = 0;
+    while (num < den) {
+        num <<= 1;
+        --s;
+    }
+    // 53 significant bits + guard bit by restoring division
+    uint64_t q = 0;
+    u128 r = num;
+    for (int b = 0; b < 54; ++b) {
+        q <<= 1;
+        if (r >= den) {
+            q |= 1;
+            r -= den;
+        }
+        r <<= 1;
+    }
+    // q holds 54 bits: value = q * 2^(s - 53)
+    const bool guard = q & 1;
+    q >>= 1;
+    int e = s - 52;
+    if (guard && (r != 0 || (q & 1))) {
+        ++q;
+        if (q == (1ull << 53)) {
+            q >>= 1;
+            ++e;
+        }
+    }
+    double v = std::ldexp((double)q, e);
+    return neg ? -v : v;
+}
+
+louvain_i128 to_abi(i128 v)
+{
+    louvain_i128 r;
+    r.lo = (uint64_t)(u128)v;
+    r.hi = (int64_t)(v >> 64);
+    return r;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+int bits_for(int64_t n)
+{
+    int b = 1;
+    while (((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+struct ProfRec {
+    const char *name;
+    int64_t launches = 0;
+    double ms = 0, bytes = 0, entries = 0;
+};
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// the handle
+// ---------------------------------------------------------------------------
+struct louvain_graph_s {
+    hipStream_t st = nullptr;
+    int dev = 0;
+    std::string err;
+    bool poisoned = false;
+    std::vector<std::pair<void *, size_t>> owned;
+
+    // input graph (level 0)
+    int64_t n0 = 0, nnz0 = 0, two_m = 0, kmax0 = 0, self0 = 0;
+    int64_t *off0 = nullptr, *k0 = nullptr;
+    int32_t *col0 = nullptr, *w0 = nullptr;
+    // coarse graph buffers (ping-pong)
+    int64_t *off_b[2] = {nullptr, nullptr}, *w_b[2] = {nullptr, nullptr};
+    int32_t *col_b[2] = {nullptr, nullptr};
+    int cur_buf = -1; // -1: level 0
+    int level = 0;
+    lv::Csr cur;
+    int64_t kmax = 0, self = 0;
+
+    // phase state
+    int64_t *k = nullptr, *a = nullptr;
+    int32_t *comm_prev = nullptr, *comm_next = nullptr, *size = nullptr, *orig_map = nullptr;
+    int64_t sigma_in = 0; // internal weight of the current partition (step API)
+    int64_t swept_entries = 0; // entries gathered by every sweep of the current run
+
+    // coloring
+    int32_t *color = nullptr, *jp_cnt = nullptr, *front_a = nullptr, *front_b = nullptr, *counters = nullptr;
+    int32_t num_colors = 0;
+    bool colored = false;
+
+    // binning
+    uint64_t *keys = nullptr, *keys_alt = nullptr;
+    int64_t *vals = nullptr, *vals_alt = nullptr, *run = nullptr;
+    int32_t *bin_verts = nullptr, *bin_hist = nullptr;
+    int64_t bin_hist_cap = 0;
+    std::vector<int64_t> bin_off; // (group*16 + bin) -> start in bin_verts; size 16*groups + 1
+    int bin_groups = 0;
+    bool bins_valid = false;
+    bool bins_colored = false;
+    int64_t *hoff = nullptr, *htmp = nullptr;
+    int32_t *hkey = nullptr;
+    uint64_t *hval = nullptr;
+    int64_t hcap = 0;
+
+    // coarsening
+    int32_t *flag = nullptr, *new_id = nullptr;
+    lv::Scratch scratch;
+    lv::SweepStats *stats = nullptr; // NBINS slots
+    int64_t *dscal = nullptr;        // 16 device scalars
+    int32_t *vflag = nullptr;
+
+    // results
+    std::vector<louvain_phase_stats> phases;
+    std::vector<louvain_iter_stats> iters;
+
+    // profiling
+    bool prof = false;
+    std::vector<ProfRec> recs;
+    struct Pending {
+        hipEvent_t a, b;
+        int rec;
+        double bytes, entries;
+        int stat_slot;
+        bool from_stats;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+typedef louvain_graph_s G;
+
+louvain_status fail(G *g, louvain_status s, const std::string &msg)
+{
+    if (g) g->err = msg;
+    else g_init_error = msg;
+    return s;
+}
+
+louvain_status hip_fail(G *g, hipError_t e, const char *where)
+{
+    g->poisoned = true;
+    return fail(g, LOUVAIN_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(g, call)                                                                                        \
+    do {                                                                                                       \
+        hipError_t e_ = (call);                                                                                \
+        if (e_ != hipSuccess) return hip_fail(g, e_, #call);                                                   \
+    } while (0)
+
+template <typename T> louvain_status alloc(G *g, T **p, int64_t count)
+{
+    const size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
+    void *q = nullptr;
+    if (pool().get(&q, bytes, g->dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(g, LOUVAIN_E_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    g->owned.push_back({q, bytes});
+    *p = (T *)q;
+    return LOUVAIN_OK;
+}
+
+void release_all(G *g)
+{
+    if (g->st) (void)hipStreamSynchronize(g->st);
+    for (auto &b : g->owned) pool().put(b.first, b.second, g->dev);
+    g->owned.clear();
+    for (auto ev : g->event_pool) (void)hipEventDestroy(ev);
+    for (auto &p : g->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    g->event_pool.clear();
+    g->pending.clear();
+}
+
+louvain_status sync(G *g)
+{
+    HIPCHK(g, hipStreamSynchronize(g->st));
+    HIPCHK(g, hipGetLastError());
+    return LOUVAIN_OK;
+}
+
+// ---- profiling ----------------------------------------------------------------
+const char *kNames[] = {"sweep_bin1_d4",    "sweep_bin2_d8",   "sweep_bin3_d16",  "sweep_bin4_d32",
+                        "sweep_bin5_d64",   "sweep_bin6_d256", "sweep_bin7_d1024", "sweep_bin8_d2048",
+                        "sweep_bin9_hub",   "commit",          "coarsen",          "color"};
+enum { PR_COMMIT = 9, PR_COARSEN = 10, PR_COLOR = 11, PR_COUNT = 12 };
+
+hipEvent_t take_event(G *g)
+{
+    if (!g->event_pool.empty()) {
+        hipEvent_t e = g->event_pool.back();
+        g->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+struct ProfScope {
+    G *g;
+    int rec;
+    hipEvent_t a{}, b{};
+    double bytes, entries;
+    int slot;
+    bool from_stats;
+    ProfScope(G *g_, int rec_, double bytes_ = 0, double entries_ = 0, int slot_ = -1)
+        : g(g_), rec(rec_), bytes(bytes_), entries(entries_), slot(slot_), from_stats(slot_ >= 0)
+    {
+        if (g->prof) {
+            a = take_event(g);
+            (void)hipEventRecord(a, g->st);
+        }
+    }
+    ~ProfScope()
+    {
+        if (!g->prof) return;
+        b = take_event(g);
+        (void)hipEventRecord(b, g->st);
+        g->pending.push_back({a, b, rec, bytes, entries, slot, from_stats});
+    }
+};
+
+// after a stream sync: fold pending event pairs into the records; sweep
+// launches take entries and pairs from their stats slot (slot -> bytes)
+void prof_collect(G *g, const lv::SweepStats *host_stats, int wb)
+{
+    if (!g->prof) return;
+    bool slot_done[lv::NBINS] = {false};
+    for (auto &p : g->pending) {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, p.a, p.b);
+        ProfRec &r = g->recs[p.rec];
+        r.launches += 1;
+        r.ms += ms;
+        if (p.from_stats && host_stats) {
+            // per vertex: list entry 4, offsets 16, comm 4, k 8, a[A] 8, sizes 8, comm_next 4
+            // per entry: column 4 + weight wb + comm of the neighbour 4; per distinct community: a 8
+            // (a slot sums all launches of its bin since the last read: counted once)
+            r.bytes += 52.0 * p.bytes;
+            if (!slot_done[p.stat_slot]) {
+                const lv::SweepStats &s = host_stats[p.stat_slot];
+                r.bytes += (8.0 + wb) * (double)s.entries + 8.0 * (double)s.pairs;
+                r.entries += (double)s.entries;
+                slot_done[p.stat_slot] = true;
+            }
+        } else {
+            r.bytes += p.bytes;
+            r.entries += p.entries;
+        }
+        g->event_pool.push_back(p.a);
+        g->event_pool.push_back(p.b);
+    }
+    g->pending.clear();
+}
+
+// ---- graph / state helpers ------------------------------------------------------
+int wbytes(const lv::Csr &c) { return c.wk == lv::W_UNIT ? 0 : (c.wk == lv::W_I32 ? 4 : 8); }
+
+louvain_status init_state(G *g)
+{
+    const int64_t n = g->cur.n;
+    lv::iota_i32(g->comm_prev, n, g->st);
+    lv::iota_i32(g->comm_next, n, g->st);
+    lv::fill<int32_t>(g->size, 1, n, g->st);
+    if (n) HIPCHK(g, hipMemcpyAsync(g->a, g->k, n * sizeof(int64_t), hipMemcpyDeviceToDevice, g->st));
+    g->sigma_in = g->self;
+    g->colored = false;
+    g->num_colors = 0;
+    g->bins_valid = false;
+    return LOUVAIN_OK;
+}
+
+louvain_status reset_level0(G *g)
+{
+    g->cur.n = g->n0;
+    g->cur.nnz = g->nnz0;
+    g->cur.off = g->off0;
+    g->cur.col = g->col0;
+    g->cur.w = g->w0;
+    g->cur.wk = g->w0 ? lv::W_I32 : lv::W_UNIT;
+    g->cur_buf = -1;
+    g->level = 0;
+    g->kmax = g->kmax0;
+    g->self = g->self0;
+    if (g->n0) HIPCHK(g, hipMemcpyAsync(g->k, g->k0, g->n0 * sizeof(int64_t), hipMemcpyDeviceToDevice, g->st));
+    lv::iota_i32(g->orig_map, g->n0, g->st);
+    return init_state(g);
+}
+
+bool wide_gains(const G *g) { return (i128)g->two_m * (i128)g->kmax >= ((i128)1 << 62); }
+
+// sorts the current graph's vertices by (group, degree bin); group = colour or none
+louvain_status build_bins(G *g, bool by_color)
+{
+    const int64_t n = g->cur.n;
+    const int groups = by_color ? g->num_colors : 1;
+    const int64_t hist_n = 16 * (int64_t)groups;
+    if (hist_n > g->bin_hist_cap) return fail(g, LOUVAIN_E_STATE, "bin histogram capacity exceeded");
+    lv::fill<int32_t>(g->bin_hist, 0, hist_n, g->st);
+    lv::bin_keys(g->cur, by_color ? g->color : nullptr, g->keys, g->vals, g->bin_hist, g->st);
+    lv::radix_sort(g->keys, g->keys_alt, g->vals, g->vals_alt, n, 4 + (by_color ? bits_for(groups) : 0), g->scratch,
+                   g->st);
+    lv::narrow_ids(g->vals, g->bin_verts, n, g->st);
+    std::vector<int32_t> h(hist_n);
+    if (hist_n) HIPCHK(g, hipMemcpyAsync(h.data(), g->bin_hist, hist_n * sizeof(int32_t), hipMemcpyDeviceToHost, g->st));
+    // hub tables for every hub position of bin_verts
+    int64_t total = lv::hub_tables(g->cur, g->bin_verts, n, g->hoff, g->htmp, g->scratch, g->st);
+    louvain_status s = sync(g);
+    if (s) return s;
+    g->bin_off.assign(hist_n + 1, 0);
+    for (int64_t t = 0; t < hist_n; ++t) g->bin_off[t + 1] = g->bin_off[t] + h[t];
+    if (total > g->hcap) {
+        for (auto it = g->owned.begin(); it != g->owned.end();) {
+            if (it->first == g->hkey || it->first == g->hval) {
+                pool().put(it->first, it->second, g->dev);
+                it = g->owned.erase(it);
+            } else ++it;
+        }
+        int64_t cap = total + total / 4;
+        if ((s = alloc(g, &g->hkey, cap))) return s;
+        if ((s = alloc(g, &g->hval, cap))) return s;
+        g->hcap = cap;
+        lv::fill<int32_t>(g->hkey, -1, cap, g->st);
+        lv::fill<uint64_t>(g->hval, 0, cap, g->st);
+    }
+    g->bin_groups = groups;
+    g->bins_colored = by_color;
+    g->bins_valid = true;
+    return LOUVAIN_OK;
+}
+
+// launches the sweep kernels of one group (all bins); per-bin stats slots
+void sweep_group(G *g, int group, int singlet)
+{
+    lv::SweepArgs a;
+    a.g = g->cur;
+    a.comm_prev = g->comm_prev;
+    a.comm_next = g->comm_next;
+    a.a = g->a;
+    a.size = g->size;
+    a.k = g->k;
+    a.two_m = g->two_m;
+    a.singlet = singlet;
+    a.hkey = g->hkey;
+    a.hval = g->hval;
+    const bool wide = wide_gains(g);
+    for (int b = 1; b < lv::NBINS; ++b) {
+        const int64_t s = g->bin_off[group * 16 + b], e = g->bin_off[group * 16 + b + 1];
+        if (e <= s) continue;
+        a.verts = g->bin_verts + s;
+        a.count = e - s;
+        a.hoff = g->hoff + s;
+        a.stats = g->stats + b;
+        ProfScope ps(g, b - 1, (double)(e - s), 0, b);
+        lv::sweep_bin(b, a, wide, g->st);
+    }
+}
+
+// sweep statistics summed over bins
+struct SweepSum {
+    int64_t moves = 0, sigma_prev = 0, dsigma = 0, pairs = 0, entries = 0;
+};
+
+louvain_status read_stats(G *g, SweepSum &out, lv::SweepStats *host)
+{
+    HIPCHK(g, hipMemcpyAsync(host, g->stats, lv::NBINS * sizeof(lv::SweepStats), hipMemcpyDeviceToHost, g->st));
+    louvain_status s = sync(g);
+    if (s) return s;
+    out = SweepSum();
+    for (int b = 0; b < lv::NBINS; ++b) {
+        out.moves += host[b].moves;
+        out.sigma_prev += host[b].sigma_prev;
+        out.dsigma += host[b].dsigma;
+        out.pairs += host[b].pairs;
+        out.entries += host[b].entries;
+    }
+    return LOUVAIN_OK;
+}
+
+louvain_status read_i128(G *g, const int64_t *dptr, i128 &v)
+{
+    int64_t h[2];
+    HIPCHK(g, hipMemcpyAsync(h, dptr, sizeof(h), hipMemcpyDeviceToHost, g->st));
+    louvain_status s = sync(g);
+    if (s) return s;
+    v = (i128)(((u128)(uint64_t)h[1] << 64) | (u128)(uint64_t)h[0]);
+    return LOUVAIN_OK;
+}
+
+louvain_status sum_sq(G *g, const int64_t *x, int64_t n, i128 &out)
+{
+    lv::sum_squares(x, n, g->dscal + 4, g->scratch, g->st);
+    return read_i128(g, g->dscal + 4, out);
+}
+
+louvain_status commit_all(G *g)
+{
+    ProfScope ps(g, PR_COMMIT, 8.0 * (double)g->cur.n, 0);
+    lv::commit(nullptr, g->cur.n, g->comm_prev, g->comm_next, g->k, g->a, g->size, g->st);
+    return LOUVAIN_OK;
+}
+
+// colored iteration: classes in ascending colour, each synchronous on the
+// state after the classes before it (Sec. 5.4 step 3)
+louvain_status colored_iteration(G *g, int singlet, SweepSum &sum, lv::SweepStats *host)
+{
+    lv::clear_stats(g->stats, lv::NBINS, g->st);
+    for (int c = 0; c < g->num_colors; ++c) {
+        sweep_group(g, c, singlet);
+        const int64_t s = g->bin_off[c * 16], e = g->bin_off[c * 16 + 16];
+        ProfScope ps(g, PR_COMMIT, 8.0 * (double)(e - s), 0);
+        lv::commit(g->bin_verts + s, e - s, g->comm_prev, g->comm_next, g->k, g->a, g->size, g->st);
+    }
+    louvain_status st = read_stats(g, sum, host);
+    prof_collect(g, host, wbytes(g->cur));
+    return st;
+}
+
+// rebuild the community graph of the current partition (Sec. 5.4 step 4)
+louvain_status coarsen_current(G *g, const int32_t *comm, int64_t &n_new)
+{
+    const int dst = g->cur_buf == 0 ? 1 : 0;
+    lv::CoarsenBufs b{g->flag, g->new_id, g->keys, g->keys_alt, g->vals, g->vals_alt, g->run};
+    int64_t nnz_new = 0;
+    {
+        ProfScope ps(g, PR_COARSEN, 0, (double)g->cur.nnz);
+        lv::coarsen(g->cur, comm, g->orig_map, g->n0, b, g->off_b[dst], g->col_b[dst], g->w_b[dst], &n_new, &nnz_new,
+                    g->scratch, g->st);
+    }
+    g->cur.n = n_new;
+    g->cur.nnz = nnz_new;
+    g->cur.off = g->off_b[dst];
+    g->cur.col = g->col_b[dst];
+    g->cur.w = g->w_b[dst];
+    g->cur.wk = lv::W_I64;
+    g->cur_buf = dst;
+    g->level += 1;
+    lv::degrees(g->cur, g->k, g->dscal, g->st);
+    int64_t h[3];
+    HIPCHK(g, hipMemcpyAsync(h, g->dscal, sizeof(h), hipMemcpyDeviceToHost, g->st));
+    louvain_status s = sync(g);
+    if (s) return s;
+    prof_collect(g, nullptr, 0);
+    if (h[0] != g->two_m) return fail(g, LOUVAIN_E_STATE, "internal error: 2m changed by coarsening");
+    g->kmax = h[1];
+    g->self = h[2];
+    return init_state(g);
+}
+
+louvain_status do_color(G *g, uint64_t seed)
+{
+    {
+        ProfScope ps(g, PR_COLOR, 0, (double)g->cur.nnz);
+        g->num_colors = lv::color_jp(g->cur, seed, g->color, g->jp_cnt, g->front_a, g->front_b, g->counters, g->st);
+    }
+    louvain_status s = sync(g);
+    if (s) return s;
+    prof_collect(g, nullptr, 0);
+    if ((int64_t)16 * g->num_colors > g->bin_hist_cap) {
+        for (auto it = g->owned.begin(); it != g->owned.end();) {
+            if (it->first == g->bin_hist) {
+                pool().put(it->first, it->second, g->dev);
+                it = g->owned.erase(it);
+            } else ++it;
+        }
+        g->bin_hist_cap = (int64_t)16 * g->num_colors + 16;
+        if ((s = alloc(g, &g->bin_hist, g->bin_hist_cap))) return s;
+    }
+    g->colored = true;
+    g->bins_valid = false;
+    return LOUVAIN_OK;
+}
+
+louvain_status check_handle(G *g)
+{
+    if (!g) return LOUVAIN_E_INVALID_ARG;
+    if (g->poisoned) return fail(g, LOUVAIN_E_HIP, "handle unusable after an earlier HIP error");
+    HIPCHK(g, hipSetDevice(g->dev));
+    return LOUVAIN_OK;
+}
+
+louvain_status check_params(G *g, const louvain_params *p)
+{
+    if (!p) return fail(g, LOUVAIN_E_INVALID_ARG, "params is NULL");
+    if (p->theta_color.den <= 0 || p->theta_final.den <= 0 || p->theta_color.num < 0 || p->theta_final.num < 0)
+        return fail(g, LOUVAIN_E_INVALID_ARG, "thresholds need num >= 0 and den > 0");
+    if (p->max_iter < 1 || p->max_phases < 1) return fail(g, LOUVAIN_E_INVALID_ARG, "max_iter and max_phases must be >= 1");
+    if (p->threshold_mode != 0 && p->threshold_mode != 1) return fail(g, LOUVAIN_E_INVALID_ARG, "threshold_mode is 0 or 1");
+    if (p->reserved != 0) return fail(g, LOUVAIN_E_INVALID_ARG, "reserved must be 0");
+    return LOUVAIN_OK;
+}
+
+louvain_status copy_out(G *g, void *dst, const void *src, size_t bytes, uint32_t on_device)
+{
+    if (!dst || !bytes) return LOUVAIN_OK;
+    HIPCHK(g, hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, g->st));
+    return sync(g);
+}
+
+// ---- one uncolored phase with the look-ahead modularity --------------------------
+// Sweep s reads C_{s-1}, so its gather also yields the internal weight of
+// C_{s-1} and hence Q_{s-1}; the stop test for iteration s-1 is therefore
+// taken after sweep s, whose moves are discarded if iteration s-1 was the last.
+louvain_status run_phase_plain(G *g, const louvain_params *p, louvain_ratio th, louvain_phase_stats &ph, i128 N0)
+{
+    lv::SweepStats host[lv::NBINS];
+    std::vector<i128> S2;     // S2[t] = sum a^2 after iteration t
+    std::vector<i128> N;      // N[t]
+    std::vector<int64_t> mv;  // moves[t]
+    i128 s2_0;
+    louvain_status s = sum_sq(g, g->k, g->cur.n, s2_0);
+    if (s) return s;
+    S2.push_back(s2_0);
+    N.push_back(N0);
+    mv.push_back(0);
+    const i128 D = (i128)g->two_m * g->two_m;
+    int t_end = 0;
+    for (int s_idx = 1;; ++s_idx) {
+        lv::clear_stats(g->stats, lv::NBINS, g->st);
+        sweep_group(g, 0, p->singlet_rule);
+        SweepSum sum;
+        if ((s = read_stats(g, sum, host))) return s;
+        prof_collect(g, host, wbytes(g->cur));
+        g->swept_entries += sum.entries;
+        louvain_iter_stats rec{};
+        if (s_idx >= 2) {
+            N[s_idx - 1] = (i128)g->two_m * sum.sigma_prev - S2[s_idx - 1];
+            g->iters.back().q_num = to_abi(N[s_idx - 1]);
+            if (s_idx - 1 >= 2 && below_threshold(N[s_idx - 1], N[s_idx - 2], D, th, p->threshold_mode)) {
+                t_end = s_idx - 1;
+                break;
+            }
+            if (s_idx - 1 >= p->max_iter) { // only reached when the cap needed N of the last iteration
+                ph.hit_max_iter = 1;
+                t_end = s_idx - 1;
+                break;
+            }
+        }
+        mv.push_back(sum.moves);
+        N.push_back(0);
+        S2.push_back(0);
+        rec.moves = sum.moves;
+        rec.pairs = sum.pairs;
+        rec.entries = sum.entries;
+        g->iters.push_back(rec);
+        if (sum.moves == 0) {
+            N[s_idx] = N[s_idx - 1];
+            S2[s_idx] = S2[s_idx - 1];
+            g->iters.back().q_num = to_abi(N[s_idx]);
+            t_end = s_idx;
+            break;
+        }
+        commit_all(g);
+        lv::sum_squares(g->a, g->cur.n, g->dscal + 4, g->scratch, g->st);
+        if ((s = read_i128(g, g->dscal + 4, S2[s_idx]))) return s;
+        prof_collect(g, nullptr, 0);
+        // at the iteration cap, one more sweep (whose moves are discarded) yields N[s_idx]
+    }
+    ph.iterations = t_end;
+    ph.q_num = to_abi(N[t_end]);
+    // drop the look-ahead record if it was pushed
+    while ((int64_t)g->iters.size() > ph.first_iter + t_end) g->iters.pop_back();
+    // comm_next may hold a discarded look-ahead; resync it with comm_prev
+    if (g->cur.n)
+        HIPCHK(g, hipMemcpyAsync(g->comm_next, g->comm_prev, g->cur.n * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                 g->st));
+    return LOUVAIN_OK;
+}
+
+louvain_status run_phase_colored(G *g, const louvain_params *p, louvain_ratio th, louvain_phase_stats &ph, i128 N0)
+{
+    lv::SweepStats host[lv::NBINS];
+    const i128 D = (i128)g->two_m * g->two_m;
+    i128 N_prev = N0, N_t = N0;
+    int64_t sigma = g->self;
+    louvain_status s;
+    int t = 0;
+    for (;;) {
+        ++t;
+        SweepSum sum;
+        if ((s = colored_iteration(g, p->singlet_rule, sum, host))) return s;
+        g->swept_entries += sum.entries;
+        i128 S2;
+        if ((s = sum_sq(g, g->a, g->cur.n, S2))) return s;
+        sigma += sum.dsigma;
+        N_t = (i128)g->two_m * sigma - S2;
+        louvain_iter_stats rec{};
+        rec.moves = sum.moves;
+        rec.q_num = to_abi(N_t);
+        rec.pairs = sum.pairs;
+        rec.entries = sum.entries;
+        g->iters.push_back(rec);
+        if (sum.moves == 0) break;
+        if (t >= 2 && below_threshold(N_t, N_prev, D, th, p->threshold_mode)) break;
+        if (t >= p->max_iter) {
+            ph.hit_max_iter = 1;
+            break;
+        }
+        N_prev = N_t;
+    }
+    ph.iterations = t;
+    ph.q_num = to_abi(N_t);
+    return LOUVAIN_OK;
+}
+
+} // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void louvain_params_default(louvain_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->vf = 0;
+    p->color = 0;
+    p->singlet_rule = 1;
+    p->threshold_mode = 0;
+    p->color_first_phase_only = 0;
+    p->max_iter = 1000;
+    p->max_phases = 100;
+    p->theta_color = {1, 100};
+    p->theta_final = {1, 1000000};
+    p->color_cutoff = 100000;
+    p->color_seed = 0x4C4F5556ull;
+}
+
+const char *louvain_last_error(louvain_graph_t g) { return g ? g->err.c_str() : g_init_error.c_str(); }
+
+louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                                const int32_t *weights, uint32_t flags, void *hip_stream, louvain_graph_t *out)
+{
+    g_init_error.clear();
+    if (!out) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 0 || nnz < 0) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "negative size");
+    if (n >= ((int64_t)1 << 31) - 1) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "n must be below 2^31 - 1");
+    if (!offsets) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "offsets is NULL");
+    if (nnz > 0 && !cols) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "cols is NULL");
+    if (flags & ~(LOUVAIN_DEVICE_PTRS | LOUVAIN_VALIDATE)) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "unknown flags");
+    const bool dev_ptrs = flags & LOUVAIN_DEVICE_PTRS;
+    if (!dev_ptrs) {
+        if (offsets[0] != 0 || offsets[n] != nnz)
+            return fail(nullptr, LOUVAIN_E_BAD_CSR, "offsets[0] must be 0 and offsets[n] must equal nnz");
+    }
+    G *g = new G();
+    g->st = (hipStream_t)hip_stream;
+    if (hipGetDevice(&g->dev) != hipSuccess) {
+        delete g;
+        return fail(nullptr, LOUVAIN_E_HIP, "hipGetDevice failed");
+    }
+    louvain_status s = LOUVAIN_OK;
+    auto bail = [&](louvain_status st) {
+        g_init_error = g->err;
+        release_all(g);
+        delete g;
+        return st;
+    };
+    g->n0 = n;
+    g->nnz0 = nnz;
+    const int64_t big = (nnz > n ? nnz : n) + 1;
+    if ((s = alloc(g, &g->off0, n + 1)) || (s = alloc(g, &g->col0, nnz)) || (s = alloc(g, &g->k0, n)) ||
+        (weights && (s = alloc(g, &g->w0, nnz))))
+        return bail(s);
+    for (int b = 0; b < 2; ++b)
+        if ((s = alloc(g, &g->off_b[b], n + 1)) || (s = alloc(g, &g->col_b[b], nnz)) ||
+            (s = alloc(g, &g->w_b[b], nnz)))
+            return bail(s);
+    if ((s = alloc(g, &g->k, n)) || (s = alloc(g, &g->a, n)) || (s = alloc(g, &g->comm_prev, n)) ||
+        (s = alloc(g, &g->comm_next, n)) || (s = alloc(g, &g->size, n)) || (s = alloc(g, &g->orig_map, n)) ||
+        (s = alloc(g, &g->color, n)) || (s = alloc(g, &g->jp_cnt, 2 * n)) || (s = alloc(g, &g->front_a, n)) ||
+        (s = alloc(g, &g->front_b, n)) || (s = alloc(g, &g->counters, 16)) || (s = alloc(g, &g->keys, big)) ||
+        (s = alloc(g, &g->keys_alt, big)) || (s = alloc(g, &g->vals, big)) || (s = alloc(g, &g->vals_alt, big)) ||
+        (s = alloc(g, &g->run, big)) || (s = alloc(g, &g->bin_verts, n)) || (s = alloc(g, &g->hoff, n + 1)) ||
+        (s = alloc(g, &g->htmp, n)) || (s = alloc(g, &g->flag, n + 1)) || (s = alloc(g, &g->new_id, n + 1)) ||
+        (s = alloc(g, &g->stats, lv::NBINS)) || (s = alloc(g, &g->dscal, 16)) || (s = alloc(g, &g->vflag, 4)))
+        return bail(s);
+    g->bin_hist_cap = 16 * 64;
+    if ((s = alloc(g, &g->bin_hist, g->bin_hist_cap))) return bail(s);
+    const int64_t part = lv::radix_partials_needed(big) + lv::scan_partials_needed(256 * (big / 4096 + 1)) +
+                         lv::scan_partials_needed(big) + 4096;
+    if ((s = alloc(g, &g->scratch.part, part))) return bail(s);
+    g->scratch.part_cap = part;
+    if ((s = alloc(g, &g->scratch.scalar, 8))) return bail(s);
+    g->recs.resize(PR_COUNT);
+    for (int r = 0; r < PR_COUNT; ++r) g->recs[r].name = kNames[r];
+
+    const hipMemcpyKind kind = dev_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (hipMemcpyAsync(g->off0, offsets, (n + 1) * sizeof(int64_t), kind, g->st) != hipSuccess ||
+        (nnz && hipMemcpyAsync(g->col0, cols, nnz * sizeof(int32_t), kind, g->st) != hipSuccess) ||
+        (weights && nnz && hipMemcpyAsync(g->w0, weights, nnz * sizeof(int32_t), kind, g->st) != hipSuccess)) {
+        (void)hipGetLastError();
+        g->err = "copy of the input CSR failed";
+        return bail(LOUVAIN_E_HIP);
+    }
+    lv::Csr in;
+    in.n = n;
+    in.nnz = nnz;
+    in.off = g->off0;
+    in.col = g->col0;
+    in.w = g->w0;
+    in.wk = g->w0 ? lv::W_I32 : lv::W_UNIT;
+    {
+        // offsets and column range are always checked (kernels index with them);
+        // order, weights and symmetry only with LOUVAIN_VALIDATE
+        int32_t code = 0;
+        lv::validate_csr(in, g->vflag, g->st);
+        if (hipMemcpyAsync(&code, g->vflag, sizeof(code), hipMemcpyDeviceToHost, g->st) != hipSuccess ||
+            hipStreamSynchronize(g->st) != hipSuccess) {
+            g->err = "validation failed to run";
+            return bail(LOUVAIN_E_HIP);
+        }
+        if (code == 0) {
+            lv::validate_entries(in, (flags & LOUVAIN_VALIDATE) != 0, g->vflag, g->st);
+            if (hipMemcpyAsync(&code, g->vflag, sizeof(code), hipMemcpyDeviceToHost, g->st) != hipSuccess ||
+                hipStreamSynchronize(g->st) != hipSuccess) {
+                g->err = "validation failed to run";
+                return bail(LOUVAIN_E_HIP);
+            }
+        }
+        static const char *why[] = {"", "offsets not monotone or not spanning [0, nnz]", "column out of range",
+                                    "columns not strictly ascending within a row", "weight below 1",
+                                    "graph not symmetric (missing mirror entry or different weight)"};
+        if (code != 0) {
+            g->err = std::string("invalid CSR: ") + why[code > 0 && code < 6 ? code : 0];
+            return bail(LOUVAIN_E_BAD_CSR);
+        }
+    }
+    lv::degrees(in, g->k0, g->dscal, g->st);
+    int64_t h[3];
+    if (hipMemcpyAsync(h, g->dscal, sizeof(h), hipMemcpyDeviceToHost, g->st) != hipSuccess ||
+        hipStreamSynchronize(g->st) != hipSuccess) {
+        g->err = "degree computation failed";
+        return bail(LOUVAIN_E_HIP);
+    }
+    g->two_m = h[0];
+    g->kmax0 = h[1];
+    g->self0 = h[2];
+    if (g->two_m < 0 || g->two_m >= ((int64_t)1 << 62)) {
+        g->err = "2m >= 2^62";
+        return bail(LOUVAIN_E_OVERFLOW);
+    }
+    if ((s = reset_level0(g)) || (s = sync(g))) return bail(s);
+    *out = g;
+    return LOUVAIN_OK;
+}
+
+void louvain_destroy(louvain_graph_t g)
+{
+    if (!g) return;
+    (void)hipSetDevice(g->dev);
+    release_all(g);
+    delete g;
+}
+
+louvain_status louvain_vf(louvain_graph_t g, int64_t *n_new_out)
+{
+    louvain_status s = check_handle(g);
+    if (s) return s;
+    if (g->level != 0) return fail(g, LOUVAIN_E_STATE, "vertex following applies to the input graph only");
+    lv::vf_map(g->cur, g->comm_prev, g->st);
+    int64_t n_new = 0;
+    if ((s = coarsen_current(g, g->comm_prev, n_new))) return s;
+    if (n_new_out) *n_new_out = n_new;
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_color(louvain_graph_t g, uint64_t seed, int32_t *num_colors_out)
+{
+    louvain_status s = check_handle(g);
+    if (s) return s;
+    if ((s = do_color(g, seed))) return s;
+    if (num_colors_out) *num_colors_out = g->num_colors;
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_sweep(louvain_graph_t g, const louvain_params *p, louvain_iter_stats *out)
+{
+    louvain_status s = check_handle(g);
+    if (s) return s;
+    if (!p) return fail(g, LOUVAIN_E_INVALID_ARG, "params is NULL");
+    const bool colored = p->color && g->colored;
+    if (!g->bins_valid || g->bins_colored != colored)
+        if ((s = build_bins(g, colored))) return s;
+    lv::SweepStats host[lv::NBINS];
+    SweepSum sum;
+    if (colored) {
+        if ((s = colored_iteration(g, p->singlet_rule, sum, host))) return s;
+    } else {
+        lv::clear_stats(g->stats, lv::NBINS, g->st);
+        sweep_group(g, 0, p->singlet_rule);
+        if ((s = read_stats(g, sum, host))) return s;
+        prof_collect(g, host, wbytes(g->cur));
+        commit_all(g);
+    }
+    i128 S2;
+    if ((s = sum_sq(g, g->a, g->cur.n, S2))) return s;
+    lv::internal_weight(g->cur, g->comm_prev, g->dscal + 8, g->st);
+    int64_t sigma = 0;
+    HIPCHK(g, hipMemcpyAsync(&sigma, g->dscal + 8, sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
+    if ((s = sync(g))) return s;
+    prof_collect(g, nullptr, 0);
+    g->sigma_in = sigma;
+    if (out) {
+        std::memset(out, 0, sizeof(*out));
+        out->moves = sum.moves;
+        out->pairs = sum.pairs;
+        out->entries = sum.entries;
+        out->q_num = to_abi(g->two_m ? (i128)g->two_m * sigma - S2 : (i128)0);
+    }
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_coarsen(louvain_graph_t g, int64_t *n_new_out)
+{
+    louvain_status s = check_handle(g);
+    if (s) return s;
+    int64_t n_new = 0;
+    if ((s = coarsen_current(g, g->comm_prev, n_new))) return s;
+    if (n_new_out) *n_new_out = n_new;
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_run(louvain_graph_t g, const louvain_params *p, int32_t *labels_out, uint32_t labels_on_device,
+                           louvain_result *out)
+{
+    louvain_status s = check_handle(g);
+    if (s) return s;
+    if ((s = check_params(g, p))) return s;
+    const auto t_start = std::chrono::steady_clock::now();
+    g->phases.clear();
+    g->iters.clear();
+    g->swept_entries = 0;
+    if ((s = reset_level0(g))) return s;
+    louvain_result res;
+    std::memset(&res, 0, sizeof(res));
+    res.n_orig = g->n0;
+    double ms_vf = 0, ms_color = 0, ms_sweep = 0, ms_coarsen = 0;
+    const i128 D = (i128)g->two_m * g->two_m;
+    i128 N_final = 0, N0 = 0;
+    int64_t K = g->n0;
+    if (g->two_m > 0) {
+        if (p->vf) {
+            const auto t0 = std::chrono::steady_clock::now();
+            int64_t nv = 0;
+            lv::vf_map(g->cur, g->comm_prev, g->st);
+            if ((s = coarsen_current(g, g->comm_prev, nv))) return s;
+            ms_vf = ms_since(t0);
+        }
+        res.n_vf = g->cur.n;
+        i128 s2;
+        if ((s = sum_sq(g, g->k, g->cur.n, s2))) return s;
+        N0 = (i128)g->two_m * g->self - s2;
+        i128 Q_prev = N0;
+        bool still_coloring = p->color != 0;
+        for (int ph_idx = 1;; ++ph_idx) {
+            const bool colored = still_coloring && g->cur.n >= p->color_cutoff;
+            const louvain_ratio th = colored ? p->theta_color : p->theta_final;
+            louvain_phase_stats ph;
+            std::memset(&ph, 0, sizeof(ph));
+            ph.n = g->cur.n;
+            ph.nnz = g->cur.nnz;
+            ph.colored = colored;
+            ph.first_iter = (int64_t)g->iters.size();
+            auto t0 = std::chrono::steady_clock::now();
+            if (colored) {
+                if ((s = do_color(g, p->color_seed))) return s;
+                ph.num_colors = g->num_colors;
+            }
+            ph.ms_color = ms_since(t0);
+            ms_color += ph.ms_color;
+            t0 = std::chrono::steady_clock::now();
+            if ((s = build_bins(g, colored))) return s;
+            // the phase starts from singletons: its Q_0 is the previous phase's Q
+            if (colored) s = run_phase_colored(g, p, th, ph, Q_prev);
+            else s = run_phase_plain(g, p, th, ph, Q_prev);
+            if (s) return s;
+            ph.ms_sweep = ms_since(t0);
+            ms_sweep += ph.ms_sweep;
+            const i128 Np = (i128)(((u128)(uint64_t)ph.q_num.hi << 64) | (u128)ph.q_num.lo);
+            t0 = std::chrono::steady_clock::now();
+            const int64_t n_before = g->cur.n;
+            int64_t n_after = 0;
+            if ((s = coarsen_current(g, g->comm_prev, n_after))) return s;
+            ph.ms_coarsen = ms_since(t0);
+            ms_coarsen += ph.ms_coarsen;
+            g->phases.push_back(ph);
+            bool stop;
+            if (colored) {
+                if (n_after < p->color_cutoff || n_after == n_before || p->color_first_phase_only ||
+                    below_threshold(Np, Q_prev, D, p->theta_color, 0))
+                    still_coloring = false;
+                stop = ph_idx >= p->max_phases;
+            } else {
+                stop = n_after == n_before || ph_idx >= p->max_phases ||
+                       below_threshold(Np, Q_prev, D, p->theta_final, 0);
+            }
+            Q_prev = Np;
+            if (stop) break;
+        }
+        N_final = Q_prev;
+        K = g->cur.n;
+    } else {
+        res.n_vf = g->n0;
+    }
+    if (labels_out && g->n0)
+        if ((s = copy_out(g, labels_out, g->orig_map, g->n0 * sizeof(int32_t), labels_on_device))) return s;
+    if ((s = sync(g))) return s;
+    if (out) {
+        res.num_communities = K;
+        res.phases = (int64_t)g->phases.size();
+        res.iterations = (int64_t)g->iters.size();
+        res.q_num = to_abi(g->two_m > 0 ? N_final : (i128)0);
+        res.q_den = to_abi(g->two_m > 0 ? D : (i128)1);
+        res.q0_num = to_abi(N0);
+        res.q = g->two_m > 0 ? exact_ratio(N_final, D) : 0.0;
+        res.sweep_entries = g->swept_entries;
+        res.ms_total = ms_since(t_start);
+        res.ms_vf = ms_vf;
+        res.ms_color = ms_color;
+        res.ms_sweep = ms_sweep;
+        res.ms_coarsen = ms_coarsen;
+        res.phase = g->phases.data();
+        res.iter = g->iters.data();
+        *out = res;
+    }
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_get_info(louvain_graph_t g, int64_t *out)
+{
+    louvain_status s = check_handle(g);
+    if (s) return s;
+    if (!out) return fail(g, LOUVAIN_E_INVALID_ARG, "out is NULL");
+    out[0] = g->cur.n;
+    out[1] = g->cur.nnz;
+    out[2] = g->two_m;
+    out[3] = g->n0;
+    out[4] = g->colored ? g->num_colors : 0;
+    out[5] = g->cur.wk;
+    out[6] = g->kmax;
+    out[7] = g->level;
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_get_state(louvain_graph_t g, int32_t *comm, int64_t *a, int32_t *size, int64_t *k,
+                                 uint32_t on_device)
+{
+    louvain_status s = check_handle(g);
+    if (s) return s;
+    const int64_t n = g->cur.n;
+    if ((s = copy_out(g, comm, g->comm_prev, n * sizeof(int32_t), on_device))) return s;
+    if ((s = copy_out(g, a, g->a, n * sizeof(int64_t), on_device))) return s;
+    if ((s = copy_out(g, size, g->size, n * sizeof(int32_t), on_device))) return s;
+    return copy_out(g, k, g->k, n * sizeof(int64_t), on_device);
+}
+
+louvain_status louvain_get_graph(louvain_graph_t g, int64_t *offsets, int32_t *cols, int64_t *weights,
+                                 uint32_t on_device)
+{
+    louvain_status s = check_handle(g);
+    if (s) return s;
+    if ((s = copy_out(g, offsets, g->cur.off, (g->cur.n + 1) * sizeof(int64_t), on_device))) return s;
+    if ((s = copy_out(g, cols, g->cur.col, g->cur.nnz * sizeof(int32_t), on_device))) return s;
+    if (weights && g->cur.nnz) {
+        if (g->cur.wk == lv::W_I64) return copy_out(g, weights, g->cur.w, g->cur.nnz * sizeof(int64_t), on_device);
+        lv::weights_i64(g->cur, (int64_t *)g->vals, g->st);
+        return copy_out(g, weights, g->vals, g->cur.nnz * sizeof(int64_t), on_device);
+    }
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_get_colors(louvain_graph_t g, int32_t *color, uint32_t on_device)
+{
+    louvain_status s = check_handle(g);
+    if (s) return s;
+    if (!g->colored) return fail(g, LOUVAIN_E_STATE, "the current graph is not colored");
+    return copy_out(g, color, g->color, g->cur.n * sizeof(int32_t), on_device);
+}
+
+louvain_status louvain_get_map(louvain_graph_t g, int32_t *orig_map, uint32_t on_device)
+{
+    louvain_status s = check_handle(g);
+    if (s) return s;
+    return copy_out(g, orig_map, g->orig_map, g->n0 * sizeof(int32_t), on_device);
+}
+
+louvain_status louvain_profile(louvain_graph_t g, int32_t enable)
+{
+    louvain_status s = check_handle(g);
+    if (s) return s;
+    if ((s = sync(g))) return s;
+    prof_collect(g, nullptr, 0);
+    g->prof = enable != 0;
+    for (auto &r : g->recs) {
+        r.launches = 0;
+        r.ms = r.bytes = r.entries = 0;
+    }
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_profile_get(louvain_graph_t g, int32_t idx, const char **name, int64_t *launches,
+                                   double *total_ms, double *bytes, double *entries)
+{
+    if (!g) return LOUVAIN_E_INVALID_ARG;
+    if (idx < 0 || idx >= (int32_t)g->recs.size()) return LOUVAIN_E_INVALID_ARG;
+    const ProfRec &r = g->recs[idx];
+    if (name) *name = r.name;
+    if (launches) *launches = r.launches;
+    if (total_ms) *total_ms = r.ms;
+    if (bytes) *bytes = r.bytes;
+    if (entries) *entries = r.entries;
+    return LOUVAIN_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,420 @@
+// Graph-level kernels: input validation, weighted degrees (Sec. 2), exact
+// modularity pieces (Eq. 3), vertex following (Sec. 5.3) and the community
+// graph rebuild between phases (Sec. 5.4 step 4) by radix sort of packed
+// (C(u), C(v)) keys, run-length reduction and prefix-sum renumbering.
+#include "lv.h"
+
+namespace lv {
+
+__device__ __forceinline__ int64_t wave_sum(int64_t v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        int lo = __shfl_xor((int)(uint32_t)v, d, 64);
+        int hi = __shfl_xor((int)(v >> 32), d, 64);
+        v += (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    }
+    return v;
+}
+
+__device__ __forceinline__ int64_t block_total(int64_t v, int64_t *s)
+{
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int64_t t = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) t += s[w];
+    __syncthreads();
+    return t;
+}
+
+// ---- validation ---------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_validate_offsets(const int64_t *off, int64_t n, int64_t nnz, int32_t *flag)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        if (off[i + 1] < off[i]) atomicCAS(flag, 0, 1);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        if (off[0] != 0 || off[n] != nnz) atomicCAS(flag, 0, 1);
+}
+
+template <int WK>
+__global__ __launch_bounds__(BLOCK) void k_validate_entries(Csr g, int full, int32_t *flag)
+{
+    __shared__ int64_t s_off[ROWCAP + 1];
+    __shared__ int64_t s_meta[2];
+    const int64_t e0 = (int64_t)blockIdx.x * ETILE;
+    const int64_t e1 = min(e0 + ETILE, g.nnz) - 1;
+    TileRows t = tile_rows(g.off, g.n, e0, e1, s_off, s_meta);
+    for (int r = 0; r < EITEMS; ++r) {
+        const int64_t e = e0 + r * BLOCK + threadIdx.x;
+        if (e > e1) break;
+        const int64_t u = tile_row(t, g.off, s_off, e);
+        const int32_t v = g.col[e];
+        const int64_t w = WLoad<WK>::at(g.w, e);
+        if (v < 0 || v >= g.n) { atomicCAS(flag, 0, 2); continue; }
+        if (!full) continue;
+        if (e > tile_off(t, g.off, s_off, u) && g.col[e - 1] >= v) atomicCAS(flag, 0, 3);
+        if (w < 1) atomicCAS(flag, 0, 4);
+        // mirror (v, u) with the same weight: binary search in row v
+        int64_t lo = g.off[v], hi = g.off[v + 1];
+        bool ok = false;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            int32_t c = g.col[mid];
+            if (c == u) { ok = WLoad<WK>::at(g.w, mid) == w; break; }
+            if (c < u) lo = mid + 1; else hi = mid;
+        }
+        if (!ok) atomicCAS(flag, 0, 5);
+    }
+}
+
+void validate_csr(const Csr &g, int32_t *flag, hipStream_t st)
+{
+    fill<int32_t>(flag, 0, 1, st);
+    unsigned gv = grid_for(g.n, BLOCK * 8);
+    if (gv > 65536) gv = 65536;
+    k_validate_offsets<<<gv, BLOCK, 0, st>>>(g.off, g.n, g.nnz, flag);
+}
+
+void validate_entries(const Csr &g, bool full, int32_t *flag, hipStream_t st)
+{
+    if (g.nnz == 0) return;
+    unsigned ge = grid_for(g.nnz, ETILE);
+    switch (g.wk) {
+    case W_UNIT: k_validate_entries<W_UNIT><<<ge, BLOCK, 0, st>>>(g, full, flag); break;
+    case W_I32: k_validate_entries<W_I32><<<ge, BLOCK, 0, st>>>(g, full, flag); break;
+    default: k_validate_entries<W_I64><<<ge, BLOCK, 0, st>>>(g, full, flag); break;
+    }
+}
+
+// ---- degrees -----------------------------------------------------------------
+// each thread sums EITEMS consecutive entries, flushing per row with an atomic
+template <int WK>
+__global__ __launch_bounds__(BLOCK) void k_degrees(Csr g, int64_t *k, int64_t *stats)
+{
+    __shared__ int64_t s_off[ROWCAP + 1];
+    __shared__ int64_t s_meta[2];
+    __shared__ int64_t s_red[BLOCK / 64];
+    const int64_t e0 = (int64_t)blockIdx.x * ETILE;
+    const int64_t e1 = min(e0 + ETILE, g.nnz) - 1;
+    TileRows t = tile_rows(g.off, g.n, e0, e1, s_off, s_meta);
+    const int64_t b = e0 + (int64_t)threadIdx.x * EITEMS;
+    const int64_t e_end = min(b + EITEMS, e1 + 1);
+    int64_t tot = 0, self = 0;
+    if (b <= e1) {
+        int64_t row = tile_row(t, g.off, s_off, b);
+        int64_t next = tile_off(t, g.off, s_off, row + 1);
+        int64_t acc = 0;
+        for (int64_t e = b; e < e_end; ++e) {
+            while (e >= next) {
+                if (acc) atomicAdd((unsigned long long *)&k[row], (unsigned long long)acc);
+                acc = 0;
+                ++row;
+                next = tile_off(t, g.off, s_off, row + 1);
+            }
+            const int64_t w = WLoad<WK>::at(g.w, e);
+            acc += w;
+            tot += w;
+            if (g.col[e] == row) self += w;
+        }
+        if (acc) atomicAdd((unsigned long long *)&k[row], (unsigned long long)acc);
+    }
+    tot = block_total(tot, s_red);
+    self = block_total(self, s_red);
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long *)&stats[0], (unsigned long long)tot);
+        atomicAdd((unsigned long long *)&stats[2], (unsigned long long)self);
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_max(const int64_t *k, int64_t n, int64_t *out)
+{
+    __shared__ int64_t s[BLOCK / 64];
+    int64_t m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        m = max(m, k[i]);
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        int lo = __shfl_xor((int)(uint32_t)m, d, 64);
+        int hi = __shfl_xor((int)(m >> 32), d, 64);
+        m = max(m, (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+    }
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int w = 0; w < BLOCK / 64; ++w) t = max(t, s[w]);
+        atomicMax((unsigned long long *)out, (unsigned long long)t);
+    }
+}
+
+void degrees(const Csr &g, int64_t *k, int64_t *stats, hipStream_t st)
+{
+    fill<int64_t>(k, 0, g.n, st);
+    fill<int64_t>(stats, 0, 3, st);
+    if (g.nnz > 0) {
+        unsigned ge = grid_for(g.nnz, ETILE);
+        switch (g.wk) {
+        case W_UNIT: k_degrees<W_UNIT><<<ge, BLOCK, 0, st>>>(g, k, stats); break;
+        case W_I32: k_degrees<W_I32><<<ge, BLOCK, 0, st>>>(g, k, stats); break;
+        default: k_degrees<W_I64><<<ge, BLOCK, 0, st>>>(g, k, stats); break;
+        }
+    }
+    if (g.n > 0) {
+        unsigned gm = grid_for(g.n, BLOCK * 16);
+        if (gm > 4096) gm = 4096;
+        k_max<<<gm, BLOCK, 0, st>>>(k, g.n, stats + 1);
+    }
+}
+
+// ---- sum of squares (128-bit) ------------------------------------------------
+constexpr int SQ_GRID = 1024;
+
+__global__ __launch_bounds__(BLOCK) void k_sumsq(const int64_t *a, int64_t n, u128 *part)
+{
+    __shared__ u128 s[BLOCK];
+    u128 acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        const int64_t x = a[i];
+        acc += (u128)((i128)x * x);
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = BLOCK / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_sumsq_final(const u128 *part, int nparts, int64_t *out)
+{
+    __shared__ u128 s[BLOCK];
+    u128 acc = 0;
+    for (int i = threadIdx.x; i < nparts; i += BLOCK) acc += part[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = BLOCK / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = (int64_t)(uint64_t)s[0];
+        out[1] = (int64_t)(uint64_t)(s[0] >> 64);
+    }
+}
+
+void sum_squares(const int64_t *a, int64_t n, int64_t *out, Scratch &s, hipStream_t st)
+{
+    u128 *part = (u128 *)s.part;
+    unsigned gq = grid_for(n, BLOCK * 4);
+    if (gq > SQ_GRID) gq = SQ_GRID;
+    k_sumsq<<<gq, BLOCK, 0, st>>>(a, n, part);
+    k_sumsq_final<<<1, BLOCK, 0, st>>>(part, (int)gq, out);
+}
+
+// ---- internal weight of a partition -----------------------------------------
+template <int WK>
+__global__ __launch_bounds__(BLOCK) void k_internal(Csr g, const int32_t *comm, int64_t *out)
+{
+    __shared__ int64_t s_off[ROWCAP + 1];
+    __shared__ int64_t s_meta[2];
+    __shared__ int64_t s_red[BLOCK / 64];
+    const int64_t e0 = (int64_t)blockIdx.x * ETILE;
+    const int64_t e1 = min(e0 + ETILE, g.nnz) - 1;
+    TileRows t = tile_rows(g.off, g.n, e0, e1, s_off, s_meta);
+    int64_t acc = 0;
+    for (int r = 0; r < EITEMS; ++r) {
+        const int64_t e = e0 + r * BLOCK + threadIdx.x;
+        if (e > e1) break;
+        const int64_t u = tile_row(t, g.off, s_off, e);
+        if (comm[u] == comm[g.col[e]]) acc += WLoad<WK>::at(g.w, e);
+    }
+    acc = block_total(acc, s_red);
+    if (threadIdx.x == 0 && acc) atomicAdd((unsigned long long *)out, (unsigned long long)acc);
+}
+
+void internal_weight(const Csr &g, const int32_t *comm, int64_t *out, hipStream_t st)
+{
+    fill<int64_t>(out, 0, 1, st);
+    if (g.nnz == 0) return;
+    unsigned ge = grid_for(g.nnz, ETILE);
+    switch (g.wk) {
+    case W_UNIT: k_internal<W_UNIT><<<ge, BLOCK, 0, st>>>(g, comm, out); break;
+    case W_I32: k_internal<W_I32><<<ge, BLOCK, 0, st>>>(g, comm, out); break;
+    default: k_internal<W_I64><<<ge, BLOCK, 0, st>>>(g, comm, out); break;
+    }
+}
+
+// ---- vertex following -----------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_vf(const int64_t *off, const int32_t *col, int64_t n, int32_t *map)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        int32_t m = (int32_t)i;
+        const int64_t b = off[i];
+        if (off[i + 1] - b == 1 && col[b] != i) {
+            const int32_t j = col[b];
+            const bool j_single = (off[j + 1] - off[j] == 1); // its one entry is (j, i)
+            m = j_single ? min((int32_t)i, j) : j;
+        }
+        map[i] = m;
+    }
+}
+
+void vf_map(const Csr &g, int32_t *map, hipStream_t st)
+{
+    if (g.n == 0) return;
+    unsigned gv = grid_for(g.n, BLOCK * 4);
+    if (gv > 65536) gv = 65536;
+    k_vf<<<gv, BLOCK, 0, st>>>(g.off, g.col, g.n, map);
+}
+
+// ---- coarsening ---------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_mark(const int32_t *comm, int64_t n, int32_t *flag)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        flag[comm[i]] = 1;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_compose(int32_t *orig_map, int64_t n_orig, const int32_t *comm,
+                                                   const int32_t *new_id)
+{
+    for (int64_t x = (int64_t)blockIdx.x * BLOCK + threadIdx.x; x < n_orig; x += (int64_t)gridDim.x * BLOCK)
+        orig_map[x] = new_id[comm[orig_map[x]]];
+}
+
+template <int WK, bool HV>
+__global__ __launch_bounds__(BLOCK) void k_coarse_keys(Csr g, const int32_t *comm, const int32_t *new_id, int bits,
+                                                       uint64_t *keys, int64_t *vals)
+{
+    __shared__ int64_t s_off[ROWCAP + 1];
+    __shared__ int64_t s_meta[2];
+    const int64_t e0 = (int64_t)blockIdx.x * ETILE;
+    const int64_t e1 = min(e0 + ETILE, g.nnz) - 1;
+    TileRows t = tile_rows(g.off, g.n, e0, e1, s_off, s_meta);
+    for (int r = 0; r < EITEMS; ++r) {
+        const int64_t e = e0 + r * BLOCK + threadIdx.x;
+        if (e > e1) break;
+        const int64_t u = tile_row(t, g.off, s_off, e);
+        const uint64_t cu = (uint32_t)new_id[comm[u]];
+        const uint64_t cv = (uint32_t)new_id[comm[g.col[e]]];
+        keys[e] = (cu << bits) | cv;
+        if (HV) vals[e] = WLoad<WK>::at(g.w, e);
+    }
+}
+
+// heads of sorted key runs: run r starts at rstart[r]; column and row of r
+__global__ __launch_bounds__(BLOCK) void k_runs(const uint64_t *keys, const int64_t *run, int64_t nnz, int bits,
+                                                int64_t *rstart, int32_t *col_out)
+{
+    const uint64_t mask = (bits >= 64) ? ~0ull : ((1ull << bits) - 1);
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * BLOCK) {
+        if (e == 0 || keys[e] != keys[e - 1]) {
+            const int64_t r = run[e];
+            rstart[r] = e;
+            col_out[r] = (int32_t)(keys[e] & mask);
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_run_weights(const int64_t *rstart, int64_t nruns, const int64_t *pref,
+                                                       int64_t *w_out)
+{
+    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < nruns; r += (int64_t)gridDim.x * BLOCK)
+        w_out[r] = pref ? pref[rstart[r + 1]] - pref[rstart[r]] : rstart[r + 1] - rstart[r];
+}
+
+// coarse row offsets: off[c] = first run whose row is >= c
+__global__ __launch_bounds__(BLOCK) void k_row_offsets(const uint64_t *keys, const int64_t *rstart, int64_t nruns,
+                                                       int bits, int64_t n_new, int64_t *off_out)
+{
+    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r <= nruns; r += (int64_t)gridDim.x * BLOCK) {
+        const int64_t prev = (r == 0) ? -1 : (int64_t)(keys[rstart[r - 1]] >> bits);
+        const int64_t cur = (r == nruns) ? n_new : (int64_t)(keys[rstart[r]] >> bits);
+        for (int64_t c = prev + 1; c <= cur; ++c) off_out[c] = r;
+    }
+}
+
+static int bits_for(int64_t n)
+{
+    int b = 1;
+    while (((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_orig, CoarsenBufs &b,
+             int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *n_new, int64_t *nnz_new, Scratch &s,
+             hipStream_t st)
+{
+    const int64_t n = g.n, nnz = g.nnz;
+    // renumber non-empty communities in ascending id
+    fill<int32_t>(b.flag, 0, n + 1, st);
+    unsigned gv = grid_for(n, BLOCK * 4);
+    if (gv > 65536) gv = 65536;
+    if (n > 0) k_mark<<<gv, BLOCK, 0, st>>>(comm, n, b.flag);
+    scan_i32_to_i32(b.flag, b.new_id, n, s.scalar, s, st);
+    int64_t nn = 0;
+    hipMemcpyAsync(&nn, s.scalar, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    unsigned gx = grid_for(n_orig, BLOCK * 4);
+    if (gx > 65536) gx = 65536;
+    if (n_orig > 0) k_compose<<<gx, BLOCK, 0, st>>>(orig_map, n_orig, comm, b.new_id);
+    *n_new = nn;
+    if (nnz == 0) {
+        fill<int64_t>(off_out, 0, nn + 1, st);
+        *nnz_new = 0;
+        return;
+    }
+    const int bits = bits_for(nn > 1 ? nn : 2);
+    const bool hv = g.wk != W_UNIT;
+    unsigned ge = grid_for(nnz, ETILE);
+    switch (g.wk) {
+    case W_UNIT: k_coarse_keys<W_UNIT, false><<<ge, BLOCK, 0, st>>>(g, comm, b.new_id, bits, b.keys, nullptr); break;
+    case W_I32: k_coarse_keys<W_I32, true><<<ge, BLOCK, 0, st>>>(g, comm, b.new_id, bits, b.keys, b.vals); break;
+    default: k_coarse_keys<W_I64, true><<<ge, BLOCK, 0, st>>>(g, comm, b.new_id, bits, b.keys, b.vals); break;
+    }
+    radix_sort(b.keys, b.keys_alt, hv ? b.vals : nullptr, b.vals_alt, nnz, 2 * bits, s, st);
+    scan_heads(b.keys, b.run, nnz, s.scalar, s, st);
+    int64_t nruns = 0;
+    hipMemcpyAsync(&nruns, s.scalar, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    int64_t *rstart = b.vals_alt; // free after the sort; nnz + 1 entries
+    unsigned gr = grid_for(nnz, BLOCK * 4);
+    if (gr > 65536) gr = 65536;
+    k_runs<<<gr, BLOCK, 0, st>>>(b.keys, b.run, nnz, bits, rstart, col_out);
+    fill<int64_t>(rstart + nruns, nnz, 1, st);
+    int64_t *pref = nullptr;
+    if (hv) {
+        pref = (int64_t *)b.keys_alt; // exclusive prefix of the sorted weights, nnz + 1 entries
+        scan_i64(b.vals, pref, nnz, pref + nnz, s, st);
+    }
+    unsigned gw = grid_for(nruns, BLOCK * 4);
+    if (gw > 65536) gw = 65536;
+    k_run_weights<<<gw, BLOCK, 0, st>>>(rstart, nruns, pref, w_out);
+    unsigned go = grid_for(nruns + 1, BLOCK * 4);
+    if (go > 65536) go = 65536;
+    k_row_offsets<<<go, BLOCK, 0, st>>>(b.keys, rstart, nruns, bits, nn, off_out);
+    *nnz_new = nruns;
+}
+
+template <int WK>
+__global__ __launch_bounds__(BLOCK) void k_w64(const void *w, int64_t nnz, int64_t *out)
+{
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * BLOCK)
+        out[e] = WLoad<WK>::at(w, e);
+}
+
+void weights_i64(const Csr &g, int64_t *w_out, hipStream_t st)
+{
+    if (g.nnz == 0) return;
+    unsigned gw = grid_for(g.nnz, BLOCK * 4);
+    if (gw > 65536) gw = 65536;
+    switch (g.wk) {
+    case W_UNIT: k_w64<W_UNIT><<<gw, BLOCK, 0, st>>>(g.w, g.nnz, w_out); break;
+    case W_I32: k_w64<W_I32><<<gw, BLOCK, 0, st>>>(g.w, g.nnz, w_out); break;
+    default: k_w64<W_I64><<<gw, BLOCK, 0, st>>>(g.w, g.nnz, w_out); break;
+    }
+}
+
+} // namespace lv

@@ -1,0 +1,239 @@
+// Internal declarations of the gfx950 Louvain library: device graph views,
+// launch helpers and the host-side entry points of each kernel family.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace lv {
+
+typedef __int128 i128;
+typedef unsigned __int128 u128;
+
+// weight kinds of a CSR: unit weights (no array), int32 input weights, int64 coarse weights
+enum WeightKind : int { W_UNIT = 0, W_I32 = 1, W_I64 = 2 };
+
+struct Csr {
+    int64_t n = 0, nnz = 0;
+    const int64_t *off = nullptr;
+    const int32_t *col = nullptr;
+    const void *w = nullptr;
+    int wk = W_UNIT;
+};
+
+template <int WK> struct WLoad;
+template <> struct WLoad<W_UNIT> {
+    static __device__ __forceinline__ int64_t at(const void *, int64_t) { return 1; }
+};
+template <> struct WLoad<W_I32> {
+    static __device__ __forceinline__ int64_t at(const void *w, int64_t e) { return ((const int32_t *)w)[e]; }
+};
+template <> struct WLoad<W_I64> {
+    static __device__ __forceinline__ int64_t at(const void *w, int64_t e) { return ((const int64_t *)w)[e]; }
+};
+
+constexpr int BLOCK = 256;
+
+inline unsigned grid_for(int64_t items, int64_t per_block)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+// ---- device helpers -------------------------------------------------------
+
+// smallest power of two >= x (x >= 1)
+__host__ __device__ inline int64_t pow2_ceil(int64_t x)
+{
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// largest r with off[r] <= e, searching rows [lo, hi) (off ascending)
+__device__ __forceinline__ int64_t row_of(const int64_t *off, int64_t lo, int64_t hi, int64_t e)
+{
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (off[mid] <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// entry-parallel tiles: a block covers ETILE consecutive CSR entries and
+// caches the offsets of the rows they span in LDS when they fit
+constexpr int EITEMS = 8;
+constexpr int ETILE = BLOCK * EITEMS;
+constexpr int ROWCAP = 2048;
+
+struct TileRows {
+    int64_t rlo, rhi; // rows of the tile's first and last entry
+    bool cached;
+};
+
+__device__ __forceinline__ TileRows tile_rows(const int64_t *off, int64_t n, int64_t e0, int64_t e1, int64_t *s_off,
+                                              int64_t *s_meta)
+{
+    if (threadIdx.x == 0) {
+        int64_t lo = row_of(off, 0, n, e0);
+        int64_t hi = row_of(off, lo, n, e1);
+        s_meta[0] = lo;
+        s_meta[1] = hi;
+    }
+    __syncthreads();
+    TileRows t;
+    t.rlo = s_meta[0];
+    t.rhi = s_meta[1];
+    const int64_t cnt = t.rhi - t.rlo + 2; // offsets rlo .. rhi+1
+    t.cached = cnt <= ROWCAP + 1;
+    if (t.cached)
+        for (int64_t j = threadIdx.x; j < cnt; j += BLOCK) s_off[j] = off[t.rlo + j];
+    __syncthreads();
+    return t;
+}
+
+// row of entry e inside the tile
+__device__ __forceinline__ int64_t tile_row(const TileRows &t, const int64_t *off, const int64_t *s_off, int64_t e)
+{
+    if (t.cached) {
+        int64_t lo = 0, hi = t.rhi - t.rlo + 1;
+        while (hi - lo > 1) {
+            int64_t mid = (lo + hi) >> 1;
+            if (s_off[mid] <= e) lo = mid; else hi = mid;
+        }
+        return t.rlo + lo;
+    }
+    return row_of(off, t.rlo, t.rhi + 1, e);
+}
+
+__device__ __forceinline__ int64_t tile_off(const TileRows &t, const int64_t *off, const int64_t *s_off, int64_t r)
+{
+    return t.cached ? s_off[r - t.rlo] : off[r];
+}
+
+// ---- primitives (prims.hip) ----------------------------------------------
+
+// Work buffers for scans and sorts; sized by the handle for its largest graph.
+struct Scratch {
+    int64_t *part = nullptr;   // scan partials
+    int64_t part_cap = 0;
+    int64_t *scalar = nullptr; // a few device scalars (scan totals etc.)
+};
+
+// exclusive scans of n values; *total (device pointer, may be null) gets the sum
+void scan_i32_to_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *total, Scratch &s, hipStream_t st);
+void scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, Scratch &s, hipStream_t st);
+// head flags of sorted keys (key[e] != key[e-1]) scanned into run ids: out[e] = #heads before e
+void scan_heads(const uint64_t *keys, int64_t *out, int64_t n, int64_t *total, Scratch &s, hipStream_t st);
+int64_t scan_partials_needed(int64_t n);
+
+// stable LSD radix sort of (key, value) by the low `bits` bits of key; the
+// result ends in keys/vals (the alt buffers are clobbered); vals may be null
+void radix_sort(uint64_t *keys, uint64_t *keys_alt, int64_t *vals, int64_t *vals_alt, int64_t n, int bits,
+                Scratch &s, hipStream_t st);
+int64_t radix_partials_needed(int64_t n);
+
+template <typename T> void fill(T *p, T v, int64_t n, hipStream_t st);
+void iota_i32(int32_t *p, int64_t n, hipStream_t st);
+
+// ---- graph kernels (graph.hip) -------------------------------------------
+
+// 0 = valid, else a detail code written to *flag: 1 offsets, 2 column range,
+// 3 columns not strictly ascending, 4 weight < 1, 5 asymmetric.  The entry
+// checks assume offsets already passed; without `full` only column range.
+void validate_csr(const Csr &g, int32_t *flag, hipStream_t st);
+void validate_entries(const Csr &g, bool full, int32_t *flag, hipStream_t st);
+// k_i = row sums; stats[0] += sum k, stats[1] = max k (atomic), stats[2] += self-loop weights
+void degrees(const Csr &g, int64_t *k, int64_t *stats, hipStream_t st);
+// sum of a_c^2 over c in [0, n) into a 128-bit accumulator (out[0] = lo, out[1] = hi)
+void sum_squares(const int64_t *a, int64_t n, int64_t *out, Scratch &s, hipStream_t st);
+// internal weight of a partition: sum over entries with comm[u] == comm[v]
+void internal_weight(const Csr &g, const int32_t *comm, int64_t *out, hipStream_t st);
+// vertex following: map[i] = representative (Sec. 5.3)
+void vf_map(const Csr &g, int32_t *map, hipStream_t st);
+
+struct CoarsenBufs {
+    int32_t *flag;       // n+1
+    int32_t *new_id;     // n+1
+    uint64_t *keys, *keys_alt;
+    int64_t *vals, *vals_alt;
+    int64_t *run;        // nnz (run id of each sorted entry)
+};
+// builds the community graph of g under comm into (off_out, col_out, w_out);
+// returns n' and nnz' (synchronizes); composes orig_map (n_orig entries)
+void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_orig, CoarsenBufs &b,
+             int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *n_new, int64_t *nnz_new, Scratch &s,
+             hipStream_t st);
+// expands weights of g to int64
+void weights_i64(const Csr &g, int64_t *w_out, hipStream_t st);
+
+// ---- sweep (sweep.hip) -----------------------------------------------------
+
+constexpr int NBINS = 10; // 0: isolated, 1..8 LDS bins, 9: hubs (global tables)
+__host__ __device__ inline int degree_bin(int64_t d)
+{
+    if (d == 0) return 0;
+    if (d <= 4) return 1;
+    if (d <= 8) return 2;
+    if (d <= 16) return 3;
+    if (d <= 32) return 4;
+    if (d <= 64) return 5;
+    if (d <= 256) return 6;
+    if (d <= 1024) return 7;
+    if (d <= 2048) return 8;
+    return 9;
+}
+
+// device accumulators of one sweep launch group
+struct SweepStats {
+    int64_t moves;
+    int64_t sigma_prev;  // sum over swept vertices of e_{i->C(i)} + w_ii (state read)
+    int64_t dsigma;      // sum over movers of 2 (e_{i->c*} - e_{i->C(i)\i})
+    int64_t pairs;       // distinct (vertex, community) pairs
+    int64_t entries;     // CSR entries gathered
+    int64_t pad[3];
+};
+
+struct SweepArgs {
+    Csr g;
+    const int32_t *verts;    // vertex list of the launch
+    int64_t count;           // vertices in the list
+    const int32_t *comm_prev;
+    int32_t *comm_next;
+    const int64_t *a;
+    const int32_t *size;
+    const int64_t *k;
+    int64_t two_m;
+    int singlet;
+    SweepStats *stats;
+    // hub tables (bin 9)
+    int32_t *hkey;
+    uint64_t *hval;
+    const int64_t *hoff;     // per hub vertex: table offset (slots), table size = hoff[h+1]-hoff[h]
+};
+
+// launches the sweep kernel of one degree bin; wide = 128-bit gains
+void sweep_bin(int bin, const SweepArgs &a, bool wide, hipStream_t st);
+// per-vertex degree bin keys for sorting: key = (group << 4) | bin, val = vertex;
+// hist[key] counts (hist zeroed by the caller, 16 * groups entries)
+void bin_keys(const Csr &g, const int32_t *group, uint64_t *keys, int64_t *vals, int32_t *hist, hipStream_t st);
+// vertex ids from sorted bin values (int64 -> int32)
+void narrow_ids(const int64_t *vals, int32_t *out, int64_t n, hipStream_t st);
+// hub table offsets over verts[0..count): hoff[h] = prefix of the table sizes
+// (pow2_ceil(2 d) for hub rows, 0 otherwise), hoff[count] = total slots;
+// returns the total (synchronizes)
+int64_t hub_tables(const Csr &g, const int32_t *verts, int64_t count, int64_t *hoff, int64_t *tmp, Scratch &s,
+                   hipStream_t st);
+// community degree/size updates for movers in the list (or all vertices if verts == null)
+void commit(const int32_t *verts, int64_t count, int32_t *comm_prev, const int32_t *comm_next,
+            const int64_t *k, int64_t *a, int32_t *size, hipStream_t st);
+void clear_stats(SweepStats *s, int count, hipStream_t st);
+
+// ---- coloring (color.hip) ---------------------------------------------------
+
+// Jones-Plassmann coloring; returns the number of colors (synchronizes)
+int32_t color_jp(const Csr &g, uint64_t seed, int32_t *color, int32_t *cnt, int32_t *front_a, int32_t *front_b,
+                 int32_t *counters, hipStream_t st);
+
+} // namespace lv

@@ -1,0 +1,390 @@
+"""Thin ctypes binding of liblouvain.so (C ABI in include/louvain.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+Functions carry the C names (``louvain_init_csr``, ``louvain_vf``,
+``louvain_color``, ``louvain_sweep``, ``louvain_coarsen``, ``louvain_run``,
+...); ``Graph`` bundles them around one handle.  PyTorch is used only for
+device buffers and the current HIP stream.  There is no fallback: if the
+library is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblouvain.so")
+
+OK, E_INVALID_ARG, E_BAD_CSR, E_OOM, E_HIP, E_OVERFLOW, E_STATE = range(7)
+DEVICE_PTRS = 1
+VALIDATE = 2
+DEFAULT_SEED = 0x4C4F5556
+
+
+class LouvainError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"louvain status {status}: {msg}")
+        self.status = status
+
+
+class Ratio(ctypes.Structure):
+    _fields_ = [("num", ctypes.c_int64), ("den", ctypes.c_int64)]
+
+
+class I128(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_int64)]
+
+    def value(self) -> int:
+        return (int(self.hi) << 64) | int(self.lo)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("vf", ctypes.c_int32), ("color", ctypes.c_int32), ("singlet_rule", ctypes.c_int32),
+                ("threshold_mode", ctypes.c_int32), ("color_first_phase_only", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("max_phases", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("theta_color", Ratio), ("theta_final", Ratio), ("color_cutoff", ctypes.c_int64),
+                ("color_seed", ctypes.c_uint64)]
+
+
+class IterStats(ctypes.Structure):
+    _fields_ = [("moves", ctypes.c_int64), ("q_num", I128), ("pairs", ctypes.c_int64),
+                ("entries", ctypes.c_int64), ("ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+class PhaseStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("colored", ctypes.c_int32),
+                ("num_colors", ctypes.c_int32), ("iterations", ctypes.c_int32), ("hit_max_iter", ctypes.c_int32),
+                ("first_iter", ctypes.c_int64), ("q_num", I128), ("ms_color", ctypes.c_double),
+                ("ms_sweep", ctypes.c_double), ("ms_coarsen", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("n_orig", ctypes.c_int64), ("n_vf", ctypes.c_int64), ("num_communities", ctypes.c_int64),
+                ("phases", ctypes.c_int64), ("iterations", ctypes.c_int64), ("q_num", I128), ("q_den", I128),
+                ("q0_num", I128), ("q", ctypes.c_double), ("sweep_entries", ctypes.c_int64),
+                ("ms_total", ctypes.c_double), ("ms_vf", ctypes.c_double), ("ms_color", ctypes.c_double),
+                ("ms_sweep", ctypes.c_double), ("ms_coarsen", ctypes.c_double),
+                ("phase", ctypes.POINTER(PhaseStats)), ("iter", ctypes.POINTER(IterStats))]
+
+
+_lib = None
+
+EXPORTS = ["louvain_params_default", "louvain_init_csr", "louvain_vf", "louvain_color", "louvain_sweep",
+           "louvain_coarsen", "louvain_run", "louvain_destroy", "louvain_last_error", "louvain_get_info",
+           "louvain_get_state", "louvain_get_graph", "louvain_get_colors", "louvain_get_map", "louvain_profile",
+           "louvain_profile_get"]
+
+
+def lib():
+    """The loaded library; raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1410_1237_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, u32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
+    st = ctypes.c_int
+    L.louvain_params_default.argtypes = [ctypes.POINTER(Params)]
+    L.louvain_params_default.restype = None
+    L.louvain_init_csr.argtypes = [i64, i64, vp, vp, vp, u32, vp, ctypes.POINTER(vp)]
+    L.louvain_init_csr.restype = st
+    L.louvain_vf.argtypes = [vp, ctypes.POINTER(i64)]
+    L.louvain_vf.restype = st
+    L.louvain_color.argtypes = [vp, u64, ctypes.POINTER(i32)]
+    L.louvain_color.restype = st
+    L.louvain_sweep.argtypes = [vp, ctypes.POINTER(Params), ctypes.POINTER(IterStats)]
+    L.louvain_sweep.restype = st
+    L.louvain_coarsen.argtypes = [vp, ctypes.POINTER(i64)]
+    L.louvain_coarsen.restype = st
+    L.louvain_run.argtypes = [vp, ctypes.POINTER(Params), vp, u32, ctypes.POINTER(Result)]
+    L.louvain_run.restype = st
+    L.louvain_destroy.argtypes = [vp]
+    L.louvain_destroy.restype = None
+    L.louvain_last_error.argtypes = [vp]
+    L.louvain_last_error.restype = ctypes.c_char_p
+    L.louvain_get_info.argtypes = [vp, vp]
+    L.louvain_get_info.restype = st
+    L.louvain_get_state.argtypes = [vp, vp, vp, vp, vp, u32]
+    L.louvain_get_state.restype = st
+    L.louvain_get_graph.argtypes = [vp, vp, vp, vp, u32]
+    L.louvain_get_graph.restype = st
+    L.louvain_get_colors.argtypes = [vp, vp, u32]
+    L.louvain_get_colors.restype = st
+    L.louvain_get_map.argtypes = [vp, vp, u32]
+    L.louvain_get_map.restype = st
+    L.louvain_profile.argtypes = [vp, i32]
+    L.louvain_profile.restype = st
+    L.louvain_profile_get.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(i64),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]
+    L.louvain_profile_get.restype = st
+    _lib = L
+    return L
+
+
+def _check(status: int, handle=None):
+    if status != OK:
+        msg = lib().louvain_last_error(handle)
+        raise LouvainError(status, msg.decode() if msg else "")
+
+
+def params(**kw) -> Params:
+    """louvain_params with the paper's defaults, overridden by keyword:
+    vf, color, singlet_rule, threshold_mode, color_first_phase_only, max_iter,
+    max_phases, theta_color=(num, den), theta_final=(num, den), color_cutoff,
+    color_seed."""
+    p = Params()
+    lib().louvain_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if k in ("theta_color", "theta_final"):
+            setattr(p, k, Ratio(int(v[0]), int(v[1])))
+        else:
+            setattr(p, k, int(v))
+    return p
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+        return None
+    return getattr(stream, "cuda_stream", stream)
+
+
+# ---- C-named functions --------------------------------------------------------
+def louvain_init_csr(n, nnz, offsets, cols, weights=None, flags=VALIDATE, hip_stream=None) -> int:
+    """Pointers are ints (device pointers with DEVICE_PTRS) or numpy arrays (host)."""
+    def ptr(x):
+        if x is None:
+            return None
+        if isinstance(x, np.ndarray):
+            return x.ctypes.data
+        return int(x)
+    h = ctypes.c_void_p()
+    _check(lib().louvain_init_csr(int(n), int(nnz), ptr(offsets), ptr(cols), ptr(weights), int(flags),
+                                  _stream_ptr(hip_stream), ctypes.byref(h)))
+    return h.value
+
+
+def louvain_vf(h) -> int:
+    out = ctypes.c_int64()
+    _check(lib().louvain_vf(h, ctypes.byref(out)), h)
+    return out.value
+
+
+def louvain_color(h, seed=DEFAULT_SEED) -> int:
+    out = ctypes.c_int32()
+    _check(lib().louvain_color(h, seed, ctypes.byref(out)), h)
+    return out.value
+
+
+def louvain_sweep(h, p: Params) -> IterStats:
+    out = IterStats()
+    _check(lib().louvain_sweep(h, ctypes.byref(p), ctypes.byref(out)), h)
+    return out
+
+
+def louvain_coarsen(h) -> int:
+    out = ctypes.c_int64()
+    _check(lib().louvain_coarsen(h, ctypes.byref(out)), h)
+    return out.value
+
+
+def louvain_run(h, p: Params, labels_ptr=None, labels_on_device=0) -> Result:
+    out = Result()
+    _check(lib().louvain_run(h, ctypes.byref(p), labels_ptr, int(labels_on_device), ctypes.byref(out)), h)
+    return out
+
+
+def louvain_destroy(h):
+    lib().louvain_destroy(h)
+
+
+def louvain_last_error(h=None) -> str:
+    m = lib().louvain_last_error(h)
+    return m.decode() if m else ""
+
+
+# ---- convenience wrapper ----------------------------------------------------------
+@dataclass
+class PhaseInfo:
+    n: int
+    nnz: int
+    colored: bool
+    num_colors: int
+    iterations: int
+    hit_max_iter: bool
+    moves: List[int]
+    N_iter: List[int]
+    N_end: int
+    pairs: List[int]
+    entries: List[int]
+    ms_color: float
+    ms_sweep: float
+    ms_coarsen: float
+
+
+@dataclass
+class RunResult:
+    labels: Optional[np.ndarray]
+    K: int
+    N: int
+    D: int
+    q: float
+    n_vf: int
+    N0: int
+    sweep_entries: int
+    ms_total: float
+    ms_vf: float
+    ms_color: float
+    ms_sweep: float
+    ms_coarsen: float
+    phases: List[PhaseInfo] = field(default_factory=list)
+
+
+def _convert(res: Result, labels) -> RunResult:
+    iters = [res.iter[t] for t in range(res.iterations)]
+    phases = []
+    for p in range(res.phases):
+        ph = res.phase[p]
+        its = iters[ph.first_iter:ph.first_iter + ph.iterations]
+        phases.append(PhaseInfo(n=ph.n, nnz=ph.nnz, colored=bool(ph.colored), num_colors=ph.num_colors,
+                                iterations=ph.iterations, hit_max_iter=bool(ph.hit_max_iter),
+                                moves=[it.moves for it in its], N_iter=[it.q_num.value() for it in its],
+                                N_end=ph.q_num.value(), pairs=[it.pairs for it in its],
+                                entries=[it.entries for it in its], ms_color=ph.ms_color,
+                                ms_sweep=ph.ms_sweep, ms_coarsen=ph.ms_coarsen))
+    return RunResult(labels=labels, K=res.num_communities, N=res.q_num.value(), D=res.q_den.value(), q=res.q,
+                     n_vf=res.n_vf, N0=res.q0_num.value(), sweep_entries=res.sweep_entries,
+                     ms_total=res.ms_total, ms_vf=res.ms_vf, ms_color=res.ms_color, ms_sweep=res.ms_sweep,
+                     ms_coarsen=res.ms_coarsen, phases=phases)
+
+
+class Graph:
+    """One library handle.  Build from a host CSR (numpy) or from device
+    tensors (torch)."""
+
+    def __init__(self, handle: int):
+        self.h = handle
+
+    @classmethod
+    def from_csr(cls, g, validate: bool = True, stream=None) -> "Graph":
+        off = np.ascontiguousarray(g.offsets, dtype=np.int64)
+        col = np.ascontiguousarray(g.cols, dtype=np.int32)
+        w = None if g.weights is None else np.ascontiguousarray(g.weights, dtype=np.int32)
+        return cls(louvain_init_csr(g.n, int(off[-1]), off, col, w, VALIDATE if validate else 0, stream))
+
+    @classmethod
+    def from_tensors(cls, offsets, cols, weights=None, validate: bool = False, stream=None) -> "Graph":
+        n = offsets.numel() - 1
+        nnz = cols.numel()
+        flags = DEVICE_PTRS | (VALIDATE if validate else 0)
+        return cls(louvain_init_csr(n, nnz, offsets.data_ptr(), cols.data_ptr(),
+                                    None if weights is None else weights.data_ptr(), flags, stream))
+
+    def close(self):
+        if self.h:
+            louvain_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # steps
+    def vf(self) -> int:
+        return louvain_vf(self.h)
+
+    def color(self, seed: int = DEFAULT_SEED) -> int:
+        return louvain_color(self.h, seed)
+
+    def sweep(self, p: Optional[Params] = None, **kw) -> dict:
+        s = louvain_sweep(self.h, p or params(**kw))
+        return {"moves": s.moves, "N": s.q_num.value(), "pairs": s.pairs, "entries": s.entries}
+
+    def coarsen(self) -> int:
+        return louvain_coarsen(self.h)
+
+    def run(self, p: Optional[Params] = None, labels=None, **kw) -> RunResult:
+        """labels: None (host copy returned), or a torch int32 device tensor of n_orig."""
+        p = p or params(**kw)
+        info = self.info()
+        if labels is None:
+            out = np.zeros(max(info["n_orig"], 1), dtype=np.int32)
+            res = louvain_run(self.h, p, out.ctypes.data, 0)
+            return _convert(res, out[:info["n_orig"]])
+        res = louvain_run(self.h, p, labels.data_ptr(), 1)
+        return _convert(res, None)
+
+    # inspection
+    def info(self) -> dict:
+        out = np.zeros(8, dtype=np.int64)
+        _check(lib().louvain_get_info(self.h, out.ctypes.data), self.h)
+        return {"n": int(out[0]), "nnz": int(out[1]), "two_m": int(out[2]), "n_orig": int(out[3]),
+                "num_colors": int(out[4]), "weight_kind": int(out[5]), "k_max": int(out[6]), "level": int(out[7])}
+
+    def state(self) -> dict:
+        n = self.info()["n"]
+        comm = np.zeros(max(n, 1), np.int32)
+        a = np.zeros(max(n, 1), np.int64)
+        size = np.zeros(max(n, 1), np.int32)
+        k = np.zeros(max(n, 1), np.int64)
+        _check(lib().louvain_get_state(self.h, comm.ctypes.data, a.ctypes.data, size.ctypes.data, k.ctypes.data, 0),
+               self.h)
+        return {"comm": comm[:n], "a": a[:n], "size": size[:n], "k": k[:n]}
+
+    def graph(self):
+        info = self.info()
+        n, nnz = info["n"], info["nnz"]
+        off = np.zeros(n + 1, np.int64)
+        col = np.zeros(max(nnz, 1), np.int32)
+        w = np.zeros(max(nnz, 1), np.int64)
+        _check(lib().louvain_get_graph(self.h, off.ctypes.data, col.ctypes.data, w.ctypes.data, 0), self.h)
+        return off, col[:nnz], w[:nnz]
+
+    def colors(self) -> np.ndarray:
+        n = self.info()["n"]
+        out = np.zeros(max(n, 1), np.int32)
+        _check(lib().louvain_get_colors(self.h, out.ctypes.data, 0), self.h)
+        return out[:n]
+
+    def orig_map(self) -> np.ndarray:
+        n0 = self.info()["n_orig"]
+        out = np.zeros(max(n0, 1), np.int32)
+        _check(lib().louvain_get_map(self.h, out.ctypes.data, 0), self.h)
+        return out[:n0]
+
+    def profile(self, enable: bool = True):
+        _check(lib().louvain_profile(self.h, 1 if enable else 0), self.h)
+
+    def profile_records(self) -> list:
+        recs = []
+        idx = 0
+        while True:
+            name = ctypes.c_char_p()
+            launches = ctypes.c_int64()
+            ms = ctypes.c_double()
+            byts = ctypes.c_double()
+            ent = ctypes.c_double()
+            st = lib().louvain_profile_get(self.h, idx, ctypes.byref(name), ctypes.byref(launches), ctypes.byref(ms),
+                                           ctypes.byref(byts), ctypes.byref(ent))
+            if st != OK:
+                break
+            recs.append({"name": name.value.decode(), "launches": launches.value, "ms": ms.value,
+                         "bytes": byts.value, "entries": ent.value})
+            idx += 1
+        return recs

@@ -1,0 +1,263 @@
+"""GPU path vs the oracle, bit for bit, through the C ABI.
+
+Step level: degrees, vertex following, coloring, every synchronous sweep
+(communities, community degrees and sizes, moves, modularity numerator)
+and every rebuild (CSR byte-equal, composed map).  Run level: labels, K,
+exact (N, D), the double, per-phase sizes, iteration counts, per-iteration
+moves and N.  Inputs: seeded small random graphs with self-loops and
+weights, a star large enough for the hub bin, SBM, R-MAT, Chung-Lu, and the
+degenerate cases.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import small_graphs as SG
+from paper_1410_1237_amd import graphs as GG
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1410_1237_amd import louvain
+    louvain.lib()
+    return louvain
+
+
+@pytest.fixture(scope="module")
+def O():
+    return oracle.default()
+
+
+def hub_graph(seed=3, hub_deg=5000, extra=20000, n=8000):
+    """A random graph with one vertex of degree > 2048 (hub bin) and a few mid-degree ones."""
+    rng = np.random.default_rng(seed)
+    edges = set()
+    for v in rng.choice(np.arange(1, n), size=hub_deg, replace=False):
+        edges.add((0, int(v)))
+    for h in (1, 2, 3):
+        for v in rng.choice(np.arange(4, n), size=300 * h, replace=False):
+            edges.add((min(h, int(v)), max(h, int(v))))
+    while len(edges) < hub_deg + extra:
+        u, v = (int(x) for x in rng.integers(0, n, 2))
+        if u != v:
+            edges.add((min(u, v), max(u, v)))
+    edges = sorted(edges)
+    w = rng.integers(1, 20, size=len(edges))
+    return SG.from_edges(n, edges, w, name="hub_graph")
+
+
+def small_cases():
+    rng = np.random.default_rng(101)
+    gs = []
+    for t in range(6):
+        n = int(rng.integers(5, 60))
+        gs.append(SG.random_graph(rng, n, p=float(rng.uniform(0.05, 0.5)), self_loops=0.3 if t % 2 else 0.0,
+                                  wmax=1 if t % 3 == 0 else 9))
+    gs.append(SG.ring_of_cliques(6, 5))
+    gs.append(SG.star(40))
+    return gs
+
+
+def medium_cases():
+    return [GG.sbm_1000(), GG.rmat(12, 8, seed=5), GG.rmat(13, 16, wmax=100, seed=6), hub_graph(),
+            GG.chung_lu(20000, 2.1, 2000.0, 3.0e5, 150000, wmax=100, seed=4), GG.batch_sbm(7)]
+
+
+def expand_w(g):
+    return np.ones(g.nnz, np.int64) if g.weights is None else g.weights.astype(np.int64)
+
+
+def compare_state(gs, st, tag):
+    s = gs.state()
+    assert np.array_equal(s["comm"], st.get("comm")), tag + ": communities"
+    assert np.array_equal(s["a"], st.get("a")), tag + ": community degrees"
+    assert np.array_equal(s["size"], st.get("size")), tag + ": community sizes"
+    assert np.array_equal(s["k"], st.get("k")), tag + ": degrees"
+
+
+def compare_graph(gs, st, tag):
+    off, col, w = gs.graph()
+    assert np.array_equal(off, st.get("offsets")), tag + ": offsets"
+    assert np.array_equal(col, st.get("cols")), tag + ": cols"
+    assert np.array_equal(w, st.get("weights")), tag + ": weights"
+    assert np.array_equal(gs.orig_map(), st.get("orig_map")), tag + ": map"
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_steps_small(L, O, case):
+    g = small_cases()[case]
+    _steps(L, O, g, colored=(case % 2 == 1), vf=(case % 3 == 0))
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_steps_medium(L, O, case):
+    g = medium_cases()[case]
+    _steps(L, O, g, colored=(case % 2 == 0), vf=(case % 3 != 1), phases=2, iters=4)
+
+
+def _steps(L, O, g, colored, vf, phases=3, iters=6):
+    print(f"[steps] {g.name} n={g.n} nnz={g.nnz} colored={colored} vf={vf}", flush=True)
+    gs = L.Graph.from_csr(g)
+    st = O.state(g)
+    info = gs.info()
+    assert info["two_m"] == st.info()["two_m"]
+    compare_state(gs, st, "init")
+    if vf:
+        n1 = gs.vf()
+        st.vf()
+        assert n1 == st.info()["n"]
+        compare_graph(gs, st, "vf")
+        compare_state(gs, st, "vf")
+    p = L.params(color=1 if colored else 0)
+    for ph in range(phases):
+        if colored:
+            c1 = gs.color()
+            c2 = st.color()
+            assert c1 == c2
+            assert np.array_equal(gs.colors(), st.get("color")), "colors"
+        else:
+            st.uncolor()
+        for t in range(iters):
+            r = gs.sweep(p)
+            moves, N = st.iterate(1)
+            tag = f"phase {ph} iteration {t}"
+            assert r["moves"] == moves, tag + ": moves"
+            assert r["N"] == N, tag + ": modularity numerator"
+            compare_state(gs, st, tag)
+            if moves == 0:
+                break
+        n1 = gs.coarsen()
+        n2 = st.coarsen()
+        assert n1 == n2
+        compare_graph(gs, st, f"coarsen {ph}")
+        compare_state(gs, st, f"coarsen {ph}")
+    gs.close()
+
+
+def compare_run(res, ref, tag=""):
+    assert res.K == ref.K, tag + ": K"
+    assert (res.N, res.D) == (ref.N, ref.D), tag + ": exact modularity"
+    assert res.q == ref.q, tag + ": double"
+    assert res.N0 == ref.N0 and res.n_vf == ref.n_vf, tag + ": first phase"
+    assert len(res.phases) == len(ref.phases), tag + ": phases"
+    for a, b in zip(res.phases, ref.phases):
+        assert (a.n, a.nnz, a.colored, a.num_colors, a.iterations, a.hit_max_iter) == \
+               (b.n, b.nnz, b.colored, b.ncolors, b.iterations, b.hit_max_iter), tag + ": phase shape"
+        assert a.moves == b.moves, tag + ": moves"
+        assert a.N_iter == b.N_iter, tag + ": per-iteration modularity"
+        assert a.N_end == b.N_end, tag + ": phase modularity"
+    assert np.array_equal(res.labels, ref.labels), tag + ": labels"
+
+
+PARAM_SETS = [
+    dict(),
+    dict(singlet_rule=0),
+    dict(vf=1, color=1, color_cutoff=1),
+    dict(vf=1, color=1, color_cutoff=1, color_first_phase_only=1),
+    dict(vf=1, color=1, color_cutoff=50, theta_color=(1, 10000)),
+    dict(threshold_mode=1, theta_final=(1, 1000)),
+    dict(max_iter=2, max_phases=2),
+]
+
+
+def oracle_params(d):
+    return oracle.Params(**d)
+
+
+@pytest.mark.parametrize("pi", range(len(PARAM_SETS)))
+def test_run_small(L, O, pi):
+    for g in small_cases():
+        res = L.Graph.from_csr(g).run(L.params(**PARAM_SETS[pi]))
+        ref = O.run(g, oracle_params(PARAM_SETS[pi]))
+        compare_run(res, ref, f"{g.name} {PARAM_SETS[pi]}")
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_run_medium(L, O, case):
+    g = medium_cases()[case]
+    for d in (dict(), dict(vf=1, color=1, color_cutoff=1000)):
+        print(f"[run] {g.name} {d}", flush=True)
+        with L.Graph.from_csr(g) as gs:
+            res = gs.run(L.params(**d))
+        compare_run(res, O.run(g, oracle_params(d)), f"{g.name} {d}")
+
+
+def test_run_sbm_1000(L, O):
+    g = GG.sbm_1000()
+    res = L.Graph.from_csr(g).run(L.params())
+    ref = O.run(g)
+    compare_run(res, ref, "sbm_1000")
+    assert res.K == 10
+
+
+def test_repeat_and_device_labels(L, O):
+    import torch
+    g = GG.rmat(12, 16, seed=9)
+    gs = L.Graph.from_csr(g)
+    a = gs.run(L.params(vf=1, color=1, color_cutoff=100))
+    b = gs.run(L.params(vf=1, color=1, color_cutoff=100))
+    lab = torch.zeros(g.n, dtype=torch.int32, device="cuda")
+    c = gs.run(L.params(vf=1, color=1, color_cutoff=100), labels=lab)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.labels, b.labels) and np.array_equal(a.labels, lab.cpu().numpy())
+    assert (a.N, b.N, c.N) == (a.N, a.N, a.N)
+    gs.close()
+
+
+def test_device_pointer_ingest(L, O):
+    import torch
+    g = GG.rmat(11, 8, wmax=50, seed=2)
+    off = torch.from_numpy(g.offsets).cuda()
+    col = torch.from_numpy(g.cols).cuda()
+    w = torch.from_numpy(g.weights).cuda()
+    gs = L.Graph.from_tensors(off, col, w, validate=True)
+    compare_run(gs.run(L.params()), O.run(g), "device ingest")
+    gs.close()
+
+
+def test_degenerate(L, O):
+    cases = [SG.from_edges(0, []), SG.from_edges(1, []), SG.from_edges(5, []),
+             SG.from_edges(3, [(0, 0), (2, 2)], weights=[3, 4]), SG.from_edges(2, [(0, 1)]),
+             SG.from_edges(4, [(0, 1), (2, 3)]), SG.from_edges(6, [(0, 1), (1, 2), (4, 4)])]
+    for g in cases:
+        for d in (dict(), dict(vf=1, color=1, color_cutoff=1), dict(singlet_rule=0)):
+            res = L.Graph.from_csr(g).run(L.params(**d))
+            compare_run(res, O.run(g, oracle_params(d)), f"degenerate n={g.n} {d}")
+
+
+def test_bad_csr_rejected(L):
+    g = SG.from_edges(4, [(0, 1), (1, 2), (2, 3)], weights=[1, 2, 3])
+    bad = [("asym", lambda c: c.weights.__setitem__(0, 5)), ("range", lambda c: c.cols.__setitem__(0, 9)),
+           ("order", lambda c: c.cols.__setitem__(slice(1, 3), c.cols[1:3][::-1].copy())),
+           ("weight", lambda c: (c.weights.__setitem__(0, 0), c.weights.__setitem__(1, 0)))]
+    for name, mutate in bad:
+        c = SG.from_edges(4, [(0, 1), (1, 2), (2, 3)], weights=[1, 2, 3])
+        c.cols = c.cols.copy()
+        c.weights = c.weights.copy()
+        mutate(c)
+        with pytest.raises(L.LouvainError) as e:
+            L.Graph.from_csr(c)
+        assert e.value.status == L.E_BAD_CSR, name
+    # without full validation the column range is still checked
+    c = SG.from_edges(4, [(0, 1), (1, 2), (2, 3)])
+    c.cols = c.cols.copy()
+    c.cols[0] = 7
+    with pytest.raises(L.LouvainError):
+        L.Graph.from_csr(c, validate=False)
+    L.Graph.from_csr(g).close()
+
+
+def test_profiling_records(L):
+    g = GG.rmat(12, 16, seed=4)
+    gs = L.Graph.from_csr(g)
+    gs.profile(True)
+    res = gs.run(L.params())
+    recs = {r["name"]: r for r in gs.profile_records()}
+    swept = sum(r["entries"] for n, r in recs.items() if n.startswith("sweep"))
+    assert swept == res.sweep_entries
+    assert all(r["ms"] >= 0 for r in recs.values())
+    gs.close()
