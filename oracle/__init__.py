@@ -121,6 +121,8 @@ class Oracle:
         L.oracle_state_gain.argtypes = [vp, i64, i32, vp, vp]
         L.oracle_state_decide.argtypes = [vp, i64, i32]
         L.oracle_state_decide.restype = i32
+        L.oracle_state_decide_range.argtypes = [vp, i64, i64, i32, vp]
+        L.oracle_state_decide_range.restype = i64
         L.oracle_run.argtypes = [i64, vp, vp, vp, vp]
         L.oracle_run.restype = vp
         L.oracle_result_free.argtypes = [vp]
@@ -281,6 +283,13 @@ class State:
 
     def decide(self, i: int, singlet_rule: int = 1) -> int:
         return int(self.O.L.oracle_state_decide(self.h, i, singlet_rule))
+
+    def decide_range(self, lo: int, hi: int, singlet_rule: int = 1):
+        """Decisions of vertices [lo, hi) against the current state; returns
+        (decisions, CSR entries of those rows)."""
+        out = np.zeros(max(hi - lo, 1), dtype=np.int32)
+        ent = int(self.O.L.oracle_state_decide_range(self.h, lo, hi, singlet_rule, _ptr(out)))
+        return out[:hi - lo], ent
 
 
 _default = None

@@ -676,6 +676,15 @@ int32_t oracle_state_decide(void *h, int64_t i, int32_t singlet_rule)
     return ((State *)h)->decide(i, singlet_rule);
 }
 
+/* decisions of vertices [lo, hi) against the current state (nothing applied);
+ * returns the number of CSR entries those rows hold */
+int64_t oracle_state_decide_range(void *h, int64_t lo, int64_t hi, int32_t singlet_rule, int32_t *out)
+{
+    State *st = (State *)h;
+    for (int64_t i = lo; i < hi; ++i) out[i - lo] = st->decide(i, singlet_rule);
+    return st->g.off[hi] - st->g.off[lo];
+}
+
 /* ---- full run ---- */
 void *oracle_run(int64_t n, const int64_t *off, const int32_t *col, const int32_t *w32,
                  const int64_t *params)

@@ -221,10 +221,13 @@ struct louvain_graph_s {
     int bin_groups = 0;
     bool bins_valid = false;
     bool bins_colored = false;
-    int64_t *hoff = nullptr, *htmp = nullptr;
+    int64_t *bin_offd = nullptr;  // device copy of bin_off (capacity bin_hist_cap + 1)
+    int64_t *hoff = nullptr, *cpre = nullptr, *htmp = nullptr;
     int32_t *hkey = nullptr;
     uint64_t *hval = nullptr;
-    int64_t hcap = 0;
+    int64_t *hpart = nullptr, *haux = nullptr;
+    int64_t hcap = 0;                       // table slots allocated
+    std::vector<lv::HubArgs> hub_groups;    // per group (e <= s when the group has no hub)
 
     // coarsening
     int32_t *flag = nullptr, *new_id = nullptr;
@@ -419,39 +422,90 @@ louvain_status reset_level0(G *g)
 
 bool wide_gains(const G *g) { return (i128)g->two_m * (i128)g->kmax >= ((i128)1 << 62); }
 
+void release_buffer(G *g, void *p)
+{
+    for (auto it = g->owned.begin(); it != g->owned.end(); ++it)
+        if (it->first == p) {
+            pool().put(it->first, it->second, g->dev);
+            g->owned.erase(it);
+            return;
+        }
+}
+
 // sorts the current graph's vertices by (group, degree bin); group = colour or none
 louvain_status build_bins(G *g, bool by_color)
 {
     const int64_t n = g->cur.n;
     const int groups = by_color ? g->num_colors : 1;
-    const int64_t hist_n = 16 * (int64_t)groups;
-    if (hist_n > g->bin_hist_cap) return fail(g, LOUVAIN_E_STATE, "bin histogram capacity exceeded");
-    lv::fill<int32_t>(g->bin_hist, 0, hist_n, g->st);
-    lv::bin_keys(g->cur, by_color ? g->color : nullptr, g->keys, g->vals, g->bin_hist, g->st);
+    const int64_t nkeys = 16 * (int64_t)groups;
+    if (nkeys > g->bin_hist_cap) return fail(g, LOUVAIN_E_STATE, "bin key capacity exceeded");
+    lv::bin_keys(g->cur, by_color ? g->color : nullptr, g->keys, g->vals, g->st);
     lv::radix_sort(g->keys, g->keys_alt, g->vals, g->vals_alt, n, 4 + (by_color ? bits_for(groups) : 0), g->scratch,
                    g->st);
     lv::narrow_ids(g->vals, g->bin_verts, n, g->st);
-    std::vector<int32_t> h(hist_n);
-    if (hist_n) HIPCHK(g, hipMemcpyAsync(h.data(), g->bin_hist, hist_n * sizeof(int32_t), hipMemcpyDeviceToHost, g->st));
-    // hub tables for every hub position of bin_verts
-    int64_t total = lv::hub_tables(g->cur, g->bin_verts, n, g->hoff, g->htmp, g->scratch, g->st);
+    lv::key_offsets(g->keys, n, nkeys, g->bin_offd, g->st);
+    lv::hub_prefix(g->cur, g->bin_verts, n, g->hoff, g->cpre, g->htmp, g->scratch, g->st);
+    g->bin_off.assign(nkeys + 1, 0);
+    HIPCHK(g, hipMemcpyAsync(g->bin_off.data(), g->bin_offd, (nkeys + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
+                             g->st));
+    int64_t total_slots = 0;
+    HIPCHK(g, hipMemcpyAsync(&total_slots, g->hoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
     louvain_status s = sync(g);
     if (s) return s;
-    g->bin_off.assign(hist_n + 1, 0);
-    for (int64_t t = 0; t < hist_n; ++t) g->bin_off[t + 1] = g->bin_off[t] + h[t];
-    if (total > g->hcap) {
-        for (auto it = g->owned.begin(); it != g->owned.end();) {
-            if (it->first == g->hkey || it->first == g->hval) {
-                pool().put(it->first, it->second, g->dev);
-                it = g->owned.erase(it);
-            } else ++it;
+    // hub position ranges per group, and their table/chunk prefixes
+    std::vector<int64_t> idx;
+    std::vector<int> with_hubs;
+    for (int grp = 0; grp < groups; ++grp) {
+        const int64_t hs = g->bin_off[grp * 16 + 9], he = g->bin_off[grp * 16 + 10];
+        if (he > hs) {
+            with_hubs.push_back(grp);
+            idx.push_back(hs);
+            idx.push_back(he);
         }
-        int64_t cap = total + total / 4;
-        if ((s = alloc(g, &g->hkey, cap))) return s;
-        if ((s = alloc(g, &g->hval, cap))) return s;
-        g->hcap = cap;
-        lv::fill<int32_t>(g->hkey, -1, cap, g->st);
-        lv::fill<uint64_t>(g->hval, 0, cap, g->st);
+    }
+    g->hub_groups.assign(groups, lv::HubArgs{});
+    for (auto &h : g->hub_groups) h.s = h.e = 0;
+    if (!with_hubs.empty()) {
+        if (total_slots > g->hcap) {
+            release_buffer(g, g->hkey);
+            release_buffer(g, g->hval);
+            release_buffer(g, g->hpart);
+            release_buffer(g, g->haux);
+            const int64_t cap = ((total_slots + total_slots / 4) / lv::HUB_SLICE + 1) * lv::HUB_SLICE;
+            const int64_t slices = cap / lv::HUB_SLICE;
+            if ((s = alloc(g, &g->hkey, cap)) || (s = alloc(g, &g->hval, cap)) || (s = alloc(g, &g->hpart, 4 * slices)) ||
+                (s = alloc(g, &g->haux, 4 * slices)))
+                return s;
+            g->hcap = cap;
+            lv::fill<int32_t>(g->hkey, -1, cap, g->st);
+            lv::fill<uint64_t>(g->hval, 0, cap, g->st);
+            lv::fill<int64_t>(g->haux, 0, 4 * slices, g->st);
+        }
+        const int64_t m = (int64_t)idx.size();
+        // gather hoff and cpre at the range ends: device scratch in vals_alt (free here)
+        int64_t *didx = g->vals_alt, *dout = g->vals_alt + m;
+        HIPCHK(g, hipMemcpyAsync(didx, idx.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, g->st));
+        lv::gather_i64(g->hoff, didx, m, dout, g->st);
+        lv::gather_i64(g->cpre, didx, m, dout + m, g->st);
+        std::vector<int64_t> vals(2 * m);
+        HIPCHK(g, hipMemcpyAsync(vals.data(), dout, 2 * m * sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
+        if ((s = sync(g))) return s;
+        for (size_t t = 0; t < with_hubs.size(); ++t) {
+            lv::HubArgs &h = g->hub_groups[with_hubs[t]];
+            h.verts = g->bin_verts;
+            h.s = idx[2 * t];
+            h.e = idx[2 * t + 1];
+            h.hoff = g->hoff;
+            h.cpre = g->cpre;
+            h.chunk0 = vals[m + 2 * t];
+            h.n_insert = vals[m + 2 * t + 1] - h.chunk0;
+            h.slice0 = vals[2 * t] / lv::HUB_SLICE;
+            h.n_scan = vals[2 * t + 1] / lv::HUB_SLICE - h.slice0;
+            h.hkey = g->hkey;
+            h.hval = g->hval;
+            h.part = g->hpart;
+            h.aux = g->haux;
+        }
     }
     g->bin_groups = groups;
     g->bins_colored = by_color;
@@ -471,18 +525,23 @@ void sweep_group(G *g, int group, int singlet)
     a.k = g->k;
     a.two_m = g->two_m;
     a.singlet = singlet;
-    a.hkey = g->hkey;
-    a.hval = g->hval;
     const bool wide = wide_gains(g);
-    for (int b = 1; b < lv::NBINS; ++b) {
+    for (int b = 1; b < 9; ++b) {
         const int64_t s = g->bin_off[group * 16 + b], e = g->bin_off[group * 16 + b + 1];
         if (e <= s) continue;
         a.verts = g->bin_verts + s;
         a.count = e - s;
-        a.hoff = g->hoff + s;
         a.stats = g->stats + b;
         ProfScope ps(g, b - 1, (double)(e - s), 0, b);
         lv::sweep_bin(b, a, wide, g->st);
+    }
+    const lv::HubArgs &h = g->hub_groups[group];
+    if (h.e > h.s) {
+        a.verts = g->bin_verts;
+        a.count = h.e - h.s;
+        a.stats = g->stats + 9;
+        ProfScope ps(g, 8, (double)(h.e - h.s), 0, 9);
+        lv::sweep_hubs(a, h, wide, g->st);
     }
 }
 
@@ -587,14 +646,11 @@ louvain_status do_color(G *g, uint64_t seed)
     if (s) return s;
     prof_collect(g, nullptr, 0);
     if ((int64_t)16 * g->num_colors > g->bin_hist_cap) {
-        for (auto it = g->owned.begin(); it != g->owned.end();) {
-            if (it->first == g->bin_hist) {
-                pool().put(it->first, it->second, g->dev);
-                it = g->owned.erase(it);
-            } else ++it;
-        }
+        release_buffer(g, g->bin_hist);
+        release_buffer(g, g->bin_offd);
         g->bin_hist_cap = (int64_t)16 * g->num_colors + 16;
         if ((s = alloc(g, &g->bin_hist, g->bin_hist_cap))) return s;
+        if ((s = alloc(g, &g->bin_offd, g->bin_hist_cap + 1))) return s;
     }
     g->colored = true;
     g->bins_valid = false;
@@ -800,15 +856,16 @@ louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, 
             return bail(s);
     if ((s = alloc(g, &g->k, n)) || (s = alloc(g, &g->a, n)) || (s = alloc(g, &g->comm_prev, n)) ||
         (s = alloc(g, &g->comm_next, n)) || (s = alloc(g, &g->size, n)) || (s = alloc(g, &g->orig_map, n)) ||
-        (s = alloc(g, &g->color, n)) || (s = alloc(g, &g->jp_cnt, 2 * n)) || (s = alloc(g, &g->front_a, n)) ||
+        (s = alloc(g, &g->color, n)) || (s = alloc(g, &g->jp_cnt, 3 * n)) || (s = alloc(g, &g->front_a, n)) ||
         (s = alloc(g, &g->front_b, n)) || (s = alloc(g, &g->counters, 16)) || (s = alloc(g, &g->keys, big)) ||
         (s = alloc(g, &g->keys_alt, big)) || (s = alloc(g, &g->vals, big)) || (s = alloc(g, &g->vals_alt, big)) ||
         (s = alloc(g, &g->run, big)) || (s = alloc(g, &g->bin_verts, n)) || (s = alloc(g, &g->hoff, n + 1)) ||
-        (s = alloc(g, &g->htmp, n)) || (s = alloc(g, &g->flag, n + 1)) || (s = alloc(g, &g->new_id, n + 1)) ||
+        (s = alloc(g, &g->cpre, n + 1)) || (s = alloc(g, &g->htmp, n + 1)) || (s = alloc(g, &g->flag, n + 1)) || (s = alloc(g, &g->new_id, n + 1)) ||
         (s = alloc(g, &g->stats, lv::NBINS)) || (s = alloc(g, &g->dscal, 16)) || (s = alloc(g, &g->vflag, 4)))
         return bail(s);
     g->bin_hist_cap = 16 * 64;
-    if ((s = alloc(g, &g->bin_hist, g->bin_hist_cap))) return bail(s);
+    if ((s = alloc(g, &g->bin_hist, g->bin_hist_cap)) || (s = alloc(g, &g->bin_offd, g->bin_hist_cap + 1)))
+        return bail(s);
     const int64_t part = lv::radix_partials_needed(big) + lv::scan_partials_needed(256 * (big / 4096 + 1)) +
                          lv::scan_partials_needed(big) + 4096;
     if ((s = alloc(g, &g->scratch.part, part))) return bail(s);

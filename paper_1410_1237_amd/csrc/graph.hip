@@ -89,16 +89,23 @@ void validate_entries(const Csr &g, bool full, int32_t *flag, hipStream_t st)
 }
 
 // ---- degrees -----------------------------------------------------------------
-// each thread sums EITEMS consecutive entries, flushing per row with an atomic
+// Each thread sums EITEMS consecutive entries per row; partial row sums are
+// combined in LDS when the tile's rows are cached (one global atomic per row
+// and block), else added to k directly.
 template <int WK>
 __global__ __launch_bounds__(BLOCK) void k_degrees(Csr g, int64_t *k, int64_t *stats)
 {
     __shared__ int64_t s_off[ROWCAP + 1];
     __shared__ int64_t s_meta[2];
     __shared__ int64_t s_red[BLOCK / 64];
+    __shared__ unsigned long long s_acc[ROWCAP + 1];
     const int64_t e0 = (int64_t)blockIdx.x * ETILE;
     const int64_t e1 = min(e0 + ETILE, g.nnz) - 1;
     TileRows t = tile_rows(g.off, g.n, e0, e1, s_off, s_meta);
+    const int64_t nrows = t.rhi - t.rlo + 1;
+    if (t.cached)
+        for (int64_t j = threadIdx.x; j < nrows; j += BLOCK) s_acc[j] = 0;
+    __syncthreads();
     const int64_t b = e0 + (int64_t)threadIdx.x * EITEMS;
     const int64_t e_end = min(b + EITEMS, e1 + 1);
     int64_t tot = 0, self = 0;
@@ -108,7 +115,10 @@ __global__ __launch_bounds__(BLOCK) void k_degrees(Csr g, int64_t *k, int64_t *s
         int64_t acc = 0;
         for (int64_t e = b; e < e_end; ++e) {
             while (e >= next) {
-                if (acc) atomicAdd((unsigned long long *)&k[row], (unsigned long long)acc);
+                if (acc) {
+                    if (t.cached) atomicAdd(&s_acc[row - t.rlo], (unsigned long long)acc);
+                    else atomicAdd((unsigned long long *)&k[row], (unsigned long long)acc);
+                }
                 acc = 0;
                 ++row;
                 next = tile_off(t, g.off, s_off, row + 1);
@@ -118,8 +128,15 @@ __global__ __launch_bounds__(BLOCK) void k_degrees(Csr g, int64_t *k, int64_t *s
             tot += w;
             if (g.col[e] == row) self += w;
         }
-        if (acc) atomicAdd((unsigned long long *)&k[row], (unsigned long long)acc);
+        if (acc) {
+            if (t.cached) atomicAdd(&s_acc[row - t.rlo], (unsigned long long)acc);
+            else atomicAdd((unsigned long long *)&k[row], (unsigned long long)acc);
+        }
     }
+    __syncthreads();
+    if (t.cached)
+        for (int64_t j = threadIdx.x; j < nrows; j += BLOCK)
+            if (s_acc[j]) atomicAdd((unsigned long long *)&k[t.rlo + j], s_acc[j]);
     tot = block_total(tot, s_red);
     self = block_total(self, s_red);
     if (threadIdx.x == 0) {

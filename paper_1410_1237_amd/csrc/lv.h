@@ -207,24 +207,40 @@ struct SweepArgs {
     int64_t two_m;
     int singlet;
     SweepStats *stats;
-    // hub tables (bin 9)
-    int32_t *hkey;
-    uint64_t *hval;
-    const int64_t *hoff;     // per hub vertex: table offset (slots), table size = hoff[h+1]-hoff[h]
 };
 
-// launches the sweep kernel of one degree bin; wide = 128-bit gains
+// hubs (bin 9): rows are split in HUB_CHUNK-entry chunks for insertion and
+// their HBM tables (pow2_ceil(2 d) slots) in HUB_SLICE-slot slices for the scan
+constexpr int HUB_CHUNK = 2048;
+constexpr int HUB_SLICE = 4096;
+struct HubArgs {
+    const int32_t *verts;    // sorted vertex list (positions are absolute)
+    int64_t s, e;            // hub positions [s, e) of this launch group
+    const int64_t *hoff;     // prefix of table slots per position (n+1)
+    const int64_t *cpre;     // prefix of row chunks per position (n+1)
+    int64_t chunk0, n_insert; // cpre[s], cpre[e] - cpre[s]
+    int64_t slice0, n_scan;   // hoff[s] / HUB_SLICE, (hoff[e] - hoff[s]) / HUB_SLICE
+    int32_t *hkey;           // tables: key -1 = empty
+    uint64_t *hval;
+    int64_t *part;           // per slice: best gain (lo, hi), community, e
+    int64_t *aux;            // per slice (used at a hub's first slice): w_self, entries, e_A, distinct
+};
+
+// launches the sweep kernel of one LDS degree bin (1..8); wide = 128-bit gains
 void sweep_bin(int bin, const SweepArgs &a, bool wide, hipStream_t st);
-// per-vertex degree bin keys for sorting: key = (group << 4) | bin, val = vertex;
-// hist[key] counts (hist zeroed by the caller, 16 * groups entries)
-void bin_keys(const Csr &g, const int32_t *group, uint64_t *keys, int64_t *vals, int32_t *hist, hipStream_t st);
+// the three hub kernels for positions [h.s, h.e)
+void sweep_hubs(const SweepArgs &a, const HubArgs &h, bool wide, hipStream_t st);
+// per-vertex degree bin keys for sorting: key = (group << 4) | bin, val = vertex
+void bin_keys(const Csr &g, const int32_t *group, uint64_t *keys, int64_t *vals, hipStream_t st);
+// off[key] = first index of the sorted keys with key >= key, key in [0, nkeys]
+void key_offsets(const uint64_t *keys, int64_t n, int64_t nkeys, int64_t *off, hipStream_t st);
 // vertex ids from sorted bin values (int64 -> int32)
 void narrow_ids(const int64_t *vals, int32_t *out, int64_t n, hipStream_t st);
-// hub table offsets over verts[0..count): hoff[h] = prefix of the table sizes
-// (pow2_ceil(2 d) for hub rows, 0 otherwise), hoff[count] = total slots;
-// returns the total (synchronizes)
-int64_t hub_tables(const Csr &g, const int32_t *verts, int64_t count, int64_t *hoff, int64_t *tmp, Scratch &s,
-                   hipStream_t st);
+// per position of verts: hoff = prefix of hub table slots, cpre = prefix of hub
+// row chunks (both n+1; tmp needs n+1 entries)
+void hub_prefix(const Csr &g, const int32_t *verts, int64_t count, int64_t *hoff, int64_t *cpre, int64_t *tmp,
+                Scratch &s, hipStream_t st);
+void gather_i64(const int64_t *src, const int64_t *idx, int64_t n, int64_t *out, hipStream_t st);
 // community degree/size updates for movers in the list (or all vertices if verts == null)
 void commit(const int32_t *verts, int64_t count, int32_t *comm_prev, const int32_t *comm_next,
             const int64_t *k, int64_t *a, int32_t *size, hipStream_t st);

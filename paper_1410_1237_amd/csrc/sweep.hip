@@ -50,10 +50,10 @@ __device__ __forceinline__ uint32_t slot_hash(int32_t c, int shift)
     return ((uint32_t)c * 0x9E3779B1u) >> (32 - shift);
 }
 
-template <int LPV, int WK, typename GT, bool GLOBAL>
-__global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a, int shift_lds)
+template <int LPV, int WK, typename GT>
+__global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a, int shift)
 {
-    typedef typename std::conditional<(WK == W_UNIT && !GLOBAL), uint32_t, unsigned long long>::type VT;
+    typedef typename std::conditional<WK == W_UNIT, uint32_t, unsigned long long>::type VT;
     constexpr int VPB = BLOCK / LPV;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long bstat[5];
@@ -63,25 +63,12 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a, int shift_lds)
     const bool valid = vidx < a.count;
     const int32_t i = valid ? a.verts[vidx] : 0;
 
-    int32_t *tkey;
-    VT *tval;
-    int64_t S;
-    int shift;
-    if (GLOBAL) {
-        const int64_t t0 = valid ? a.hoff[vidx] : 0;
-        S = valid ? a.hoff[vidx + 1] - t0 : 0;
-        tkey = a.hkey + t0;
-        tval = (VT *)(a.hval + t0);
-        shift = S > 0 ? (__ffsll((unsigned long long)S) - 1) : 0;
-    } else {
-        S = (int64_t)1 << shift_lds;
-        shift = shift_lds;
-        tkey = (int32_t *)smem + grp * S;
-        tval = (VT *)(smem + (size_t)VPB * S * sizeof(int32_t)) + grp * S;
-        for (int64_t s = lane; s < S; s += LPV) {
-            tkey[s] = -1;
-            tval[s] = 0;
-        }
+    const int64_t S = (int64_t)1 << shift;
+    int32_t *tkey = (int32_t *)smem + grp * S;
+    VT *tval = (VT *)(smem + (size_t)VPB * S * sizeof(int32_t)) + grp * S;
+    for (int64_t s = lane; s < S; s += LPV) {
+        tkey[s] = -1;
+        tval[s] = 0;
     }
     if (threadIdx.x < 5) bstat[threadIdx.x] = 0;
     __syncthreads();
@@ -104,31 +91,21 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a, int shift_lds)
         const int32_t c = a.comm_prev[j];
         uint32_t h = slot_hash(c, shift);
         for (;;) {
-            int32_t cur;
-            if (GLOBAL) {
+            int32_t cur = tkey[h];
+            if (cur == c) {
+                atomicAdd(&tval[h], (VT)w);
+                break;
+            }
+            if (cur == -1) {
                 cur = atomicCAS(&tkey[h], -1, c);
                 if (cur == -1 || cur == c) {
                     atomicAdd(&tval[h], (VT)w);
                     break;
                 }
-            } else {
-                cur = tkey[h];
-                if (cur == c) {
-                    atomicAdd(&tval[h], (VT)w);
-                    break;
-                }
-                if (cur == -1) {
-                    cur = atomicCAS(&tkey[h], -1, c);
-                    if (cur == -1 || cur == c) {
-                        atomicAdd(&tval[h], (VT)w);
-                        break;
-                    }
-                }
             }
             h = (h + 1) & (uint32_t)(S - 1);
         }
     }
-    if (GLOBAL) __threadfence();
     __syncthreads();
 
     // gains over the distinct communities (Eq. 4 scaled by 2m^2), best by (G, -c)
@@ -136,19 +113,9 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a, int shift_lds)
     Best<GT> best{0, -1, 0};
     int64_t eA = 0, distinct = 0;
     for (int64_t s = lane; s < S; s += LPV) {
-        int32_t c;
-        int64_t e;
-        if (GLOBAL) {
-            c = __hip_atomic_load(&tkey[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (c < 0) continue;
-            e = (int64_t)__hip_atomic_load(&tval[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            tkey[s] = -1; // leave the table clean for the next sweep
-            tval[s] = 0;
-        } else {
-            c = tkey[s];
-            if (c < 0) continue;
-            e = (int64_t)tval[s];
-        }
+        const int32_t c = tkey[s];
+        if (c < 0) continue;
+        const int64_t e = (int64_t)tval[s];
         ++distinct;
         if (c == A) {
             eA = e;
@@ -213,24 +180,20 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a, int shift_lds)
     }
 }
 
-template <int LPV, bool GLOBAL, typename GT>
-static void launch_wk(const SweepArgs &a, int shift, hipStream_t st)
+template <int LPV, typename GT> static void launch_wk(const SweepArgs &a, int shift, hipStream_t st)
 {
     constexpr int VPB = BLOCK / LPV;
     const unsigned grid = grid_for(a.count, VPB);
-    size_t lds = 0;
+    const size_t slots = (size_t)VPB * ((size_t)1 << shift);
     switch (a.g.wk) {
     case W_UNIT:
-        if (!GLOBAL) lds = (size_t)VPB * ((size_t)1 << shift) * (sizeof(int32_t) + sizeof(uint32_t));
-        k_sweep<LPV, W_UNIT, GT, GLOBAL><<<grid, BLOCK, lds, st>>>(a, shift);
+        k_sweep<LPV, W_UNIT, GT><<<grid, BLOCK, slots * (sizeof(int32_t) + sizeof(uint32_t)), st>>>(a, shift);
         break;
     case W_I32:
-        if (!GLOBAL) lds = (size_t)VPB * ((size_t)1 << shift) * (sizeof(int32_t) + sizeof(uint64_t));
-        k_sweep<LPV, W_I32, GT, GLOBAL><<<grid, BLOCK, lds, st>>>(a, shift);
+        k_sweep<LPV, W_I32, GT><<<grid, BLOCK, slots * (sizeof(int32_t) + sizeof(uint64_t)), st>>>(a, shift);
         break;
     default:
-        if (!GLOBAL) lds = (size_t)VPB * ((size_t)1 << shift) * (sizeof(int32_t) + sizeof(uint64_t));
-        k_sweep<LPV, W_I64, GT, GLOBAL><<<grid, BLOCK, lds, st>>>(a, shift);
+        k_sweep<LPV, W_I64, GT><<<grid, BLOCK, slots * (sizeof(int32_t) + sizeof(uint64_t)), st>>>(a, shift);
         break;
     }
 }
@@ -238,45 +201,276 @@ static void launch_wk(const SweepArgs &a, int shift, hipStream_t st)
 template <typename GT> static void sweep_bin_t(int bin, const SweepArgs &a, hipStream_t st)
 {
     switch (bin) {
-    case 1: launch_wk<4, false, GT>(a, 3, st); break;     // d <= 4: 8 slots
-    case 2: launch_wk<8, false, GT>(a, 4, st); break;     // d <= 8: 16 slots
-    case 3: launch_wk<16, false, GT>(a, 5, st); break;    // d <= 16: 32 slots
-    case 4: launch_wk<32, false, GT>(a, 6, st); break;    // d <= 32: 64 slots
-    case 5: launch_wk<64, false, GT>(a, 7, st); break;    // d <= 64: 128 slots
-    case 6: launch_wk<64, false, GT>(a, 9, st); break;    // d <= 256: 512 slots
-    case 7: launch_wk<256, false, GT>(a, 11, st); break;  // d <= 1024: 2048 slots
-    case 8: launch_wk<256, false, GT>(a, 12, st); break;  // d <= 2048: 4096 slots
-    case 9: launch_wk<256, true, GT>(a, 0, st); break;    // hubs: HBM tables
+    case 1: launch_wk<4, GT>(a, 3, st); break;     // d <= 4: 8 slots
+    case 2: launch_wk<8, GT>(a, 4, st); break;     // d <= 8: 16 slots
+    case 3: launch_wk<16, GT>(a, 5, st); break;    // d <= 16: 32 slots
+    case 4: launch_wk<32, GT>(a, 6, st); break;    // d <= 32: 64 slots
+    case 5: launch_wk<64, GT>(a, 7, st); break;    // d <= 64: 128 slots
+    case 6: launch_wk<64, GT>(a, 9, st); break;    // d <= 256: 512 slots
+    case 7: launch_wk<256, GT>(a, 11, st); break;  // d <= 1024: 2048 slots
+    case 8: launch_wk<256, GT>(a, 12, st); break;  // d <= 2048: 4096 slots
     default: break;
     }
 }
 
 void sweep_bin(int bin, const SweepArgs &a, bool wide, hipStream_t st)
 {
-    if (a.count <= 0) return;
+    if (a.count <= 0 || bin < 1 || bin > 8) return;
     if (wide) sweep_bin_t<i128>(bin, a, st);
     else sweep_bin_t<int64_t>(bin, a, st);
 }
 
-// ---- binning ----------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_bin_keys(const int64_t *off, int64_t n, const int32_t *group,
-                                                    uint64_t *keys, int64_t *vals, int32_t *hist)
+// ---- hubs: rows longer than 2048 entries --------------------------------------
+// (1) insert: each block pre-aggregates a 2048-entry chunk of one hub row in an
+// LDS table, then adds its distinct communities to the hub's HBM table;
+// (2) scan: each block reads a 4096-slot slice of one hub table, leaves it
+// clean and keeps the slice's best (G, -c); (3) decide: one thread per hub
+// reduces its slices and applies the same rule as the other bins.
+constexpr int HUB_LDS = 2 * HUB_CHUNK;
+
+__device__ __forceinline__ int64_t last_leq(const int64_t *arr, int64_t lo, int64_t hi, int64_t x)
 {
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
-        const int b = degree_bin(off[i + 1] - off[i]);
-        const uint64_t key = ((uint64_t)(group ? group[i] : 0) << 4) | (uint64_t)b;
-        keys[i] = key;
-        vals[i] = i;
-        atomicAdd(&hist[key], 1);
+    // largest p in [lo, hi) with arr[p] <= x (arr non-decreasing, arr[lo] <= x)
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (arr[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <int WK>
+__global__ __launch_bounds__(BLOCK) void k_hub_insert(SweepArgs a, HubArgs h)
+{
+    __shared__ int32_t tkey[HUB_LDS];
+    __shared__ unsigned long long tval[HUB_LDS];
+    __shared__ int64_t red[BLOCK / 64][2];
+    const int64_t target = h.chunk0 + blockIdx.x;
+    const int64_t p = last_leq(h.cpre, h.s, h.e, target);
+    const int32_t v = h.verts[p];
+    const int64_t rb = a.g.off[v], re = a.g.off[v + 1];
+    const int64_t beg = rb + (target - h.cpre[p]) * HUB_CHUNK;
+    const int64_t end = min(re, beg + HUB_CHUNK);
+    for (int s = threadIdx.x; s < HUB_LDS; s += BLOCK) {
+        tkey[s] = -1;
+        tval[s] = 0;
+    }
+    __syncthreads();
+    constexpr int shift = 12; // log2(HUB_LDS)
+    int64_t wself = 0;
+    for (int64_t e = beg + threadIdx.x; e < end; e += BLOCK) {
+        const int32_t j = a.g.col[e];
+        const int64_t w = WLoad<WK>::at(a.g.w, e);
+        if (j == v) {
+            wself += w;
+            continue;
+        }
+        const int32_t c = a.comm_prev[j];
+        uint32_t q = slot_hash(c, shift);
+        for (;;) {
+            int32_t cur = tkey[q];
+            if (cur == c) {
+                atomicAdd(&tval[q], (unsigned long long)w);
+                break;
+            }
+            if (cur == -1) {
+                cur = atomicCAS(&tkey[q], -1, c);
+                if (cur == -1 || cur == c) {
+                    atomicAdd(&tval[q], (unsigned long long)w);
+                    break;
+                }
+            }
+            q = (q + 1) & (HUB_LDS - 1);
+        }
+    }
+    __syncthreads();
+    const int64_t t0 = h.hoff[p], S = h.hoff[p + 1] - t0;
+    const int gshift = __ffsll((unsigned long long)S) - 1;
+    int32_t *gkey = h.hkey + t0;
+    unsigned long long *gval = (unsigned long long *)h.hval + t0;
+    for (int s = threadIdx.x; s < HUB_LDS; s += BLOCK) {
+        const int32_t c = tkey[s];
+        if (c < 0) continue;
+        const unsigned long long w = tval[s];
+        uint32_t q = slot_hash(c, gshift);
+        for (;;) {
+            const int32_t cur = atomicCAS(&gkey[q], -1, c);
+            if (cur == -1 || cur == c) {
+                atomicAdd(&gval[q], w);
+                break;
+            }
+            q = (q + 1) & (uint32_t)(S - 1);
+        }
+    }
+    // self-loop weight and entry count of the chunk
+    int64_t x = wself;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) x += shfl_xor_t(x, m, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][0] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int w = 0; w < BLOCK / 64; ++w) t += red[w][0];
+        int64_t *aux = h.aux + 4 * (t0 / HUB_SLICE);
+        if (t) atomicAdd((unsigned long long *)&aux[0], (unsigned long long)t);
+        atomicAdd((unsigned long long *)&aux[1], (unsigned long long)(end - beg));
     }
 }
 
-void bin_keys(const Csr &g, const int32_t *group, uint64_t *keys, int64_t *vals, int32_t *hist, hipStream_t st)
+template <typename GT>
+__global__ __launch_bounds__(BLOCK) void k_hub_scan(SweepArgs a, HubArgs h)
+{
+    __shared__ Best<GT> sb[BLOCK / 64];
+    __shared__ int64_t se[BLOCK / 64][2];
+    const int64_t slice = h.slice0 + blockIdx.x;
+    const int64_t p = last_leq(h.hoff, h.s, h.e, slice * HUB_SLICE);
+    const int32_t v = h.verts[p];
+    const int32_t A = a.comm_prev[v];
+    const int64_t kv = a.k[v];
+    Best<GT> best{0, -1, 0};
+    int64_t eA = 0, distinct = 0;
+    const int64_t base = slice * HUB_SLICE;
+    for (int s = threadIdx.x; s < HUB_SLICE; s += BLOCK) {
+        const int32_t c = __hip_atomic_load(&h.hkey[base + s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (c < 0) continue;
+        const int64_t e = (int64_t)__hip_atomic_load(&h.hval[base + s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        h.hkey[base + s] = -1; // leave the table clean for the next sweep
+        h.hval[base + s] = 0;
+        ++distinct;
+        if (c == A) {
+            eA += e;
+            continue;
+        }
+        Best<GT> cand{(GT)a.two_m * (GT)e - (GT)kv * (GT)a.a[c], c, e};
+        if (better(cand, best)) best = cand;
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        Best<GT> o;
+        o.g = shfl_xor_t(best.g, m, 64);
+        o.c = shfl_xor_t(best.c, m, 64);
+        o.e = shfl_xor_t(best.e, m, 64);
+        if (better(o, best)) best = o;
+        eA += shfl_xor_t(eA, m, 64);
+        distinct += shfl_xor_t(distinct, m, 64);
+    }
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sb[wid] = best;
+        se[wid][0] = eA;
+        se[wid][1] = distinct;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < BLOCK / 64; ++w) {
+            if (better(sb[w], best)) best = sb[w];
+            eA += se[w][0];
+            distinct += se[w][1];
+        }
+        int64_t *rec = h.part + 4 * slice;
+        const i128 g = (i128)best.g;
+        rec[0] = (int64_t)(uint64_t)(u128)g;
+        rec[1] = (int64_t)(g >> 64);
+        rec[2] = best.c;
+        rec[3] = best.e;
+        int64_t *aux = h.aux + 4 * (h.hoff[p] / HUB_SLICE);
+        if (eA) atomicAdd((unsigned long long *)&aux[2], (unsigned long long)eA);
+        if (distinct) atomicAdd((unsigned long long *)&aux[3], (unsigned long long)distinct);
+    }
+}
+
+template <typename GT>
+__global__ __launch_bounds__(BLOCK) void k_hub_decide(SweepArgs a, HubArgs h)
+{
+    __shared__ unsigned long long bstat[5];
+    if (threadIdx.x < 5) bstat[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t p = h.s + (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p < h.e) {
+        const int32_t v = h.verts[p];
+        const int64_t first = h.hoff[p] / HUB_SLICE, last = h.hoff[p + 1] / HUB_SLICE;
+        Best<GT> best{0, -1, 0};
+        for (int64_t q = first; q < last; ++q) {
+            const int64_t *rec = h.part + 4 * q;
+            const i128 g = (i128)(((u128)(uint64_t)rec[1] << 64) | (u128)(uint64_t)rec[0]);
+            Best<GT> cand{(GT)g, (int32_t)rec[2], rec[3]};
+            if (better(cand, best)) best = cand;
+        }
+        int64_t *aux = h.aux + 4 * first;
+        const int64_t wself = aux[0], entries = aux[1], eA = aux[2], distinct = aux[3];
+        aux[0] = aux[1] = aux[2] = aux[3] = 0;
+        const int32_t A = a.comm_prev[v];
+        const int64_t kv = a.k[v];
+        const GT stay = (GT)a.two_m * (GT)eA - (GT)kv * (GT)(a.a[A] - kv);
+        bool move = best.c >= 0 && best.g > stay;
+        if (move && a.singlet && a.size[A] == 1 && a.size[best.c] == 1 && best.c > A) move = false;
+        a.comm_next[v] = move ? best.c : A;
+        if (move) {
+            atomicAdd(&bstat[0], 1ull);
+            atomicAdd(&bstat[2], (unsigned long long)(2 * (best.e - eA)));
+        }
+        atomicAdd(&bstat[1], (unsigned long long)(eA + wself));
+        atomicAdd(&bstat[3], (unsigned long long)distinct);
+        atomicAdd(&bstat[4], (unsigned long long)entries);
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const unsigned long long x = bstat[threadIdx.x];
+        if (x) atomicAdd((unsigned long long *)&a.stats->moves + threadIdx.x, x);
+    }
+}
+
+template <typename GT> static void hubs_t(const SweepArgs &a, const HubArgs &h, hipStream_t st)
+{
+    switch (a.g.wk) {
+    case W_UNIT: k_hub_insert<W_UNIT><<<(unsigned)h.n_insert, BLOCK, 0, st>>>(a, h); break;
+    case W_I32: k_hub_insert<W_I32><<<(unsigned)h.n_insert, BLOCK, 0, st>>>(a, h); break;
+    default: k_hub_insert<W_I64><<<(unsigned)h.n_insert, BLOCK, 0, st>>>(a, h); break;
+    }
+    k_hub_scan<GT><<<(unsigned)h.n_scan, BLOCK, 0, st>>>(a, h);
+    k_hub_decide<GT><<<grid_for(h.e - h.s, BLOCK), BLOCK, 0, st>>>(a, h);
+}
+
+void sweep_hubs(const SweepArgs &a, const HubArgs &h, bool wide, hipStream_t st)
+{
+    if (h.e <= h.s) return;
+    if (wide) hubs_t<i128>(a, h, st);
+    else hubs_t<int64_t>(a, h, st);
+}
+
+// ---- binning ----------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_bin_keys(const int64_t *off, int64_t n, const int32_t *group,
+                                                    uint64_t *keys, int64_t *vals)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        const int b = degree_bin(off[i + 1] - off[i]);
+        keys[i] = ((uint64_t)(group ? group[i] : 0) << 4) | (uint64_t)b;
+        vals[i] = i;
+    }
+}
+
+void bin_keys(const Csr &g, const int32_t *group, uint64_t *keys, int64_t *vals, hipStream_t st)
 {
     if (g.n == 0) return;
     unsigned gb = grid_for(g.n, BLOCK * 4);
     if (gb > 65536) gb = 65536;
-    k_bin_keys<<<gb, BLOCK, 0, st>>>(g.off, g.n, group, keys, vals, hist);
+    k_bin_keys<<<gb, BLOCK, 0, st>>>(g.off, g.n, group, keys, vals);
+}
+
+// off[key] = first index of sorted keys whose key is >= key, for key in [0, nkeys]
+__global__ __launch_bounds__(BLOCK) void k_key_offsets(const uint64_t *keys, int64_t n, int64_t nkeys, int64_t *off)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i <= n; i += (int64_t)gridDim.x * BLOCK) {
+        const int64_t prev = i == 0 ? -1 : (int64_t)keys[i - 1];
+        const int64_t cur = i == n ? nkeys : (int64_t)keys[i];
+        for (int64_t k = prev + 1; k <= cur; ++k) off[k] = i;
+    }
+}
+
+void key_offsets(const uint64_t *keys, int64_t n, int64_t nkeys, int64_t *off, hipStream_t st)
+{
+    unsigned gb = grid_for(n + 1, BLOCK * 4);
+    if (gb > 65536) gb = 65536;
+    k_key_offsets<<<gb, BLOCK, 0, st>>>(keys, n, nkeys, off);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_narrow(const int64_t *vals, int32_t *out, int64_t n)
@@ -294,25 +488,43 @@ void narrow_ids(const int64_t *vals, int32_t *out, int64_t n, hipStream_t st)
 }
 
 __global__ __launch_bounds__(BLOCK) void k_hub_sizes(const int64_t *off, const int32_t *verts, int64_t count,
-                                                     int64_t *sz)
+                                                     int64_t *slots, int64_t *chunks)
 {
-    for (int64_t h = (int64_t)blockIdx.x * BLOCK + threadIdx.x; h < count; h += (int64_t)gridDim.x * BLOCK) {
-        const int32_t v = verts[h];
+    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < count; p += (int64_t)gridDim.x * BLOCK) {
+        const int32_t v = verts[p];
         const int64_t d = off[v + 1] - off[v];
-        sz[h] = degree_bin(d) == 9 ? pow2_ceil(2 * d) : 0;
+        const bool hub = degree_bin(d) == 9;
+        slots[p] = hub ? pow2_ceil(2 * d) : 0; // >= 8192, a multiple of HUB_SLICE
+        chunks[p] = hub ? (d + HUB_CHUNK - 1) / HUB_CHUNK : 0;
     }
 }
 
-int64_t hub_tables(const Csr &g, const int32_t *verts, int64_t count, int64_t *hoff, int64_t *tmp, Scratch &s,
-                   hipStream_t st)
+void hub_prefix(const Csr &g, const int32_t *verts, int64_t count, int64_t *hoff, int64_t *cpre, int64_t *tmp,
+                Scratch &s, hipStream_t st)
 {
-    if (count == 0) return 0;
-    k_hub_sizes<<<grid_for(count, BLOCK), BLOCK, 0, st>>>(g.off, verts, count, tmp);
+    if (count == 0) {
+        fill<int64_t>(hoff, 0, 1, st);
+        fill<int64_t>(cpre, 0, 1, st);
+        return;
+    }
+    unsigned gb = grid_for(count, BLOCK * 4);
+    if (gb > 65536) gb = 65536;
+    k_hub_sizes<<<gb, BLOCK, 0, st>>>(g.off, verts, count, tmp, cpre);
     scan_i64(tmp, hoff, count, hoff + count, s, st);
-    int64_t total = 0;
-    hipMemcpyAsync(&total, hoff + count, sizeof(int64_t), hipMemcpyDeviceToHost, st);
-    hipStreamSynchronize(st);
-    return total;
+    scan_i64(cpre, tmp, count, tmp + count, s, st);  // chunk prefix lands in tmp ...
+    hipMemcpyAsync(cpre, tmp, (count + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, st); // ... then cpre
+}
+
+__global__ __launch_bounds__(BLOCK) void k_gather_i64(const int64_t *src, const int64_t *idx, int64_t n, int64_t *out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK)
+        out[i] = src[idx[i]];
+}
+
+void gather_i64(const int64_t *src, const int64_t *idx, int64_t n, int64_t *out, hipStream_t st)
+{
+    if (n <= 0) return;
+    k_gather_i64<<<grid_for(n, BLOCK), BLOCK, 0, st>>>(src, idx, n, out);
 }
 
 // ---- community totals (Eq. 2) for movers ------------------------------------

@@ -93,10 +93,11 @@ def test_steps_small(L, O, case):
     _steps(L, O, g, colored=(case % 2 == 1), vf=(case % 3 == 0))
 
 
+@pytest.mark.parametrize("colored", [False, True])
 @pytest.mark.parametrize("case", range(6))
-def test_steps_medium(L, O, case):
+def test_steps_medium(L, O, case, colored):
     g = medium_cases()[case]
-    _steps(L, O, g, colored=(case % 2 == 0), vf=(case % 3 != 1), phases=2, iters=4)
+    _steps(L, O, g, colored=colored, vf=(case % 3 != 1), phases=2, iters=4)
 
 
 def _steps(L, O, g, colored, vf, phases=3, iters=6):
