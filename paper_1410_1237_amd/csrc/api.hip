@@ -312,10 +312,11 @@ louvain_status sync(G *g)
 }
 
 // ---- profiling ----------------------------------------------------------------
-const char *kNames[] = {"sweep_bin1_d4",    "sweep_bin2_d8",   "sweep_bin3_d16",  "sweep_bin4_d32",
-                        "sweep_bin5_d64",   "sweep_bin6_d256", "sweep_bin7_d1024", "sweep_bin8_d2048",
-                        "sweep_bin9_hub",   "commit",          "coarsen",          "color"};
-enum { PR_COMMIT = 9, PR_COARSEN = 10, PR_COLOR = 11, PR_COUNT = 12 };
+const char *kNames[] = {"sweep_small_bins1to5", "sweep_large_bins6to9_hub_insert", "sweep_all_bins_small_group",
+                        "sweep_hub_scan_decide", "commit", "coarsen", "color"};
+enum { PR_SMALL = 0, PR_LARGE = 1, PR_ALL = 2, PR_HUB_SCAN = 3, PR_COMMIT = 4, PR_COARSEN = 5, PR_COLOR = 6,
+       PR_COUNT = 7 };
+constexpr double SMALL_GROUP = 65536; // vertices: one fused launch below this
 
 hipEvent_t take_event(G *g)
 {
@@ -334,7 +335,7 @@ struct ProfScope {
     int rec;
     hipEvent_t a{}, b{};
     double bytes, entries;
-    int slot;
+    int slot;  // bit mask of the stats slots (bins) the launch covers, -1: none
     bool from_stats;
     ProfScope(G *g_, int rec_, double bytes_ = 0, double entries_ = 0, int slot_ = -1)
         : g(g_), rec(rec_), bytes(bytes_), entries(entries_), slot(slot_), from_stats(slot_ >= 0)
@@ -370,11 +371,12 @@ void prof_collect(G *g, const lv::SweepStats *host_stats, int wb)
             // per entry: column 4 + weight wb + comm of the neighbour 4; per distinct community: a 8
             // (a slot sums all launches of its bin since the last read: counted once)
             r.bytes += 52.0 * p.bytes;
-            if (!slot_done[p.stat_slot]) {
-                const lv::SweepStats &s = host_stats[p.stat_slot];
+            for (int b = 0; b < lv::NBINS; ++b) {
+                if (!((p.stat_slot >> b) & 1) || slot_done[b]) continue;
+                const lv::SweepStats &s = host_stats[b];
                 r.bytes += (8.0 + wb) * (double)s.entries + 8.0 * (double)s.pairs;
                 r.entries += (double)s.entries;
-                slot_done[p.stat_slot] = true;
+                slot_done[b] = true;
             }
         } else {
             r.bytes += p.bytes;
@@ -456,7 +458,7 @@ louvain_status build_bins(G *g, bool by_color)
     std::vector<int64_t> idx;
     std::vector<int> with_hubs;
     for (int grp = 0; grp < groups; ++grp) {
-        const int64_t hs = g->bin_off[grp * 16 + 9], he = g->bin_off[grp * 16 + 10];
+        const int64_t hs = g->bin_off[grp * 16 + 10], he = g->bin_off[grp * 16 + 11];
         if (he > hs) {
             with_hubs.push_back(grp);
             idx.push_back(hs);
@@ -465,8 +467,8 @@ louvain_status build_bins(G *g, bool by_color)
     }
     g->hub_groups.assign(groups, lv::HubArgs{});
     for (auto &h : g->hub_groups) h.s = h.e = 0;
-    if (!with_hubs.empty()) {
-        if (total_slots > g->hcap) {
+    if (total_slots > g->hcap) {
+        {
             release_buffer(g, g->hkey);
             release_buffer(g, g->hval);
             release_buffer(g, g->hpart);
@@ -474,13 +476,15 @@ louvain_status build_bins(G *g, bool by_color)
             const int64_t cap = ((total_slots + total_slots / 4) / lv::HUB_SLICE + 1) * lv::HUB_SLICE;
             const int64_t slices = cap / lv::HUB_SLICE;
             if ((s = alloc(g, &g->hkey, cap)) || (s = alloc(g, &g->hval, cap)) || (s = alloc(g, &g->hpart, 4 * slices)) ||
-                (s = alloc(g, &g->haux, 4 * slices)))
+                (s = alloc(g, &g->haux, 8 * slices)))
                 return s;
             g->hcap = cap;
             lv::fill<int32_t>(g->hkey, -1, cap, g->st);
             lv::fill<uint64_t>(g->hval, 0, cap, g->st);
-            lv::fill<int64_t>(g->haux, 0, 4 * slices, g->st);
+            lv::fill<int64_t>(g->haux, 0, 8 * slices, g->st);
         }
+    }
+    if (!with_hubs.empty()) {
         const int64_t m = (int64_t)idx.size();
         // gather hoff and cpre at the range ends: device scratch in vals_alt (free here)
         int64_t *didx = g->vals_alt, *dout = g->vals_alt + m;
@@ -525,23 +529,39 @@ void sweep_group(G *g, int group, int singlet)
     a.k = g->k;
     a.two_m = g->two_m;
     a.singlet = singlet;
+    a.verts = nullptr;
+    a.count = 0;
+    a.stats = g->stats + 10;
     const bool wide = wide_gains(g);
-    for (int b = 1; b < 9; ++b) {
+    lv::FusedBins f;
+    double cnt_small = 0, cnt_large = 0;
+    for (int b = 1; b <= 9; ++b) {
         const int64_t s = g->bin_off[group * 16 + b], e = g->bin_off[group * 16 + b + 1];
-        if (e <= s) continue;
-        a.verts = g->bin_verts + s;
-        a.count = e - s;
-        a.stats = g->stats + b;
-        ProfScope ps(g, b - 1, (double)(e - s), 0, b);
-        lv::sweep_bin(b, a, wide, g->st);
+        f.bins[b].verts = g->bin_verts + s;
+        f.bins[b].count = e - s;
+        f.bins[b].stats = g->stats + b;
+        (b <= 5 ? cnt_small : cnt_large) += (double)(e - s);
+        if (b == 9) f.hoff9 = g->hoff + s;
     }
+    f.hkey = g->hkey;
+    f.hval = g->hval;
     const lv::HubArgs &h = g->hub_groups[group];
+    const double nhub = (double)(h.e > h.s ? h.e - h.s : 0);
+    if (cnt_small + cnt_large + nhub <= SMALL_GROUP) {
+        // small group (typical late colour class): one launch for every bin
+        ProfScope ps(g, PR_ALL, cnt_small + cnt_large + nhub, 0, 0x7fe);
+        lv::sweep_all(a, f, h, wide, g->st);
+    } else {
+        {
+            ProfScope ps(g, PR_SMALL, cnt_small, 0, 0x3e);
+            lv::sweep_small(a, f, wide, g->st);
+        }
+        ProfScope ps(g, PR_LARGE, cnt_large + nhub, 0, 0x7c0);
+        lv::sweep_large(a, f, h, wide, g->st);
+    }
     if (h.e > h.s) {
-        a.verts = g->bin_verts;
-        a.count = h.e - h.s;
-        a.stats = g->stats + 9;
-        ProfScope ps(g, 8, (double)(h.e - h.s), 0, 9);
-        lv::sweep_hubs(a, h, wide, g->st);
+        ProfScope ps(g, PR_HUB_SCAN, 0, 0);
+        lv::sweep_hub_scan(a, h, wide, g->st);
     }
 }
 
@@ -856,7 +876,7 @@ louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, 
             return bail(s);
     if ((s = alloc(g, &g->k, n)) || (s = alloc(g, &g->a, n)) || (s = alloc(g, &g->comm_prev, n)) ||
         (s = alloc(g, &g->comm_next, n)) || (s = alloc(g, &g->size, n)) || (s = alloc(g, &g->orig_map, n)) ||
-        (s = alloc(g, &g->color, n)) || (s = alloc(g, &g->jp_cnt, 3 * n)) || (s = alloc(g, &g->front_a, n)) ||
+        (s = alloc(g, &g->color, n)) || (s = alloc(g, &g->jp_cnt, 5 * n)) || (s = alloc(g, &g->front_a, n)) ||
         (s = alloc(g, &g->front_b, n)) || (s = alloc(g, &g->counters, 16)) || (s = alloc(g, &g->keys, big)) ||
         (s = alloc(g, &g->keys_alt, big)) || (s = alloc(g, &g->vals, big)) || (s = alloc(g, &g->vals_alt, big)) ||
         (s = alloc(g, &g->run, big)) || (s = alloc(g, &g->bin_verts, n)) || (s = alloc(g, &g->hoff, n + 1)) ||

@@ -8,9 +8,10 @@
 // Each vertex keeps the count of its uncoloured higher-priority neighbours;
 // colouring a vertex decrements its lower-priority neighbours and those
 // reaching zero form the next round's frontier.  One wavefront colours one
-// frontier vertex (LDS bitmap of the colours its higher-priority neighbours
-// use, 4096 colours per window), so every row is read a bounded number of
-// times.  Rounds are launched in batches without host synchronisation: the
+// frontier vertex with a row of up to 256 entries (64-colour register windows),
+// a 256-thread workgroup one with up to 4096 entries and a 1024-thread
+// workgroup a longer one (LDS bitmap of 4096 colours per window), so every
+// row is read a bounded number of times.  Rounds are launched in batches without host synchronisation: the
 // frontier sizes live in a small device ring indexed by round; round r reads
 // slot r, counts the next frontier into slot r+1 and clears slot r+2 for the
 // round after.
@@ -19,9 +20,10 @@
 namespace lv {
 
 constexpr int JP_WINDOW_WORDS = 64; // 64 x 64 = 4096 colours per window
-constexpr unsigned JP_GRID = 8192;  // light blocks (one wave each) per round, grid-stride over the frontier
-constexpr unsigned JP_HEAVY_GRID = 512;
-constexpr int64_t JP_RING = 6; // frontier sizes by round: slots 2(r % JP_RING) (light) and +1 (heavy)
+constexpr unsigned JP_GRID = 512;        // light: 2048 waves per round, grid-stride over the frontier
+constexpr unsigned JP_MEDIUM_GRID = 512; // medium: one vertex per 256-thread block, grid-stride
+constexpr unsigned JP_HEAVY_GRID = 128;  // heavy: one vertex per 1024-thread block, grid-stride
+constexpr int64_t JP_RING = 4; // frontier sizes by round: slots 3 (r % JP_RING) + (light, medium, heavy)
 
 __device__ __forceinline__ uint64_t jp_priority(uint64_t seed, int64_t v)
 {
@@ -51,25 +53,29 @@ __global__ __launch_bounds__(BLOCK) void k_jp_count(Csr g, uint64_t seed, int32_
 
 // vertices without higher-priority neighbours start the frontier; a vertex
 // with no neighbour other than itself takes colour 0 at once.  Frontier
-// lists are split by row length: light rows go to one wavefront each, heavy
-// rows (> JP_HEAVY entries) to a 1024-thread workgroup each.
-constexpr int64_t JP_HEAVY = 4096;
-constexpr int JP_HEAVY_BLOCK = 1024;
+// lists are split by row length into light, medium and heavy.
+constexpr int64_t JP_MEDIUM = 256;  // rows above: a 256-thread workgroup
+constexpr int64_t JP_HEAVY = 4096;  // rows above: a 1024-thread workgroup
 
-__device__ __forceinline__ void jp_push(const Csr &g, int32_t u, int32_t *light, int32_t *heavy, int32_t *counts)
+struct JpLists {
+    int32_t *list[3]; // light, medium, heavy
+};
+
+__device__ __forceinline__ void jp_push(const Csr &g, int32_t u, const JpLists &out, int32_t *counts)
 {
-    if (g.off[u + 1] - g.off[u] > JP_HEAVY) heavy[atomicAdd(&counts[1], 1)] = u;
-    else light[atomicAdd(&counts[0], 1)] = u;
+    const int64_t d = g.off[u + 1] - g.off[u];
+    const int k = d > JP_HEAVY ? 2 : (d > JP_MEDIUM ? 1 : 0);
+    out.list[k][atomicAdd(&counts[k], 1)] = u;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_jp_start(Csr g, const int32_t *cnt, int32_t *color, int32_t *light,
-                                                    int32_t *heavy, int32_t *ring)
+__global__ __launch_bounds__(BLOCK) void k_jp_start(Csr g, const int32_t *cnt, int32_t *color, JpLists out,
+                                                    int32_t *ring)
 {
     for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < g.n; v += (int64_t)gridDim.x * BLOCK) {
         const int64_t b = g.off[v], e = g.off[v + 1];
         const bool alone = (e == b) || (e - b == 1 && g.col[b] == v);
         color[v] = alone ? 0 : -1;
-        if (!alone && cnt[v] == 0) jp_push(g, (int32_t)v, light, heavy, ring);
+        if (!alone && cnt[v] == 0) jp_push(g, (int32_t)v, out, ring);
     }
 }
 
@@ -109,21 +115,66 @@ __device__ __forceinline__ int32_t jp_mex(const Csr &g, uint64_t seed, int32_t v
     return c;
 }
 
-// one round over the light and heavy frontier lists of slot r
-template <int NT, bool HEAVY>
-__global__ __launch_bounds__(NT) void k_jp_round(Csr g, uint64_t seed, const int32_t *in_light, const int32_t *in_heavy,
-                                                 int32_t *ring, int64_t r, int32_t *out_light, int32_t *out_heavy,
-                                                 int32_t *color, int32_t *cnt)
+__device__ __forceinline__ unsigned long long wave_or(unsigned long long x)
+{
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const unsigned lo = __shfl_xor((unsigned)x, m, 64);
+        const unsigned hi = __shfl_xor((unsigned)(x >> 32), m, 64);
+        x |= ((unsigned long long)hi << 32) | lo;
+    }
+    return x;
+}
+
+// light rows: one wavefront per frontier vertex, colours in 64-colour register
+// windows OR-reduced across the wave; waves of a block are independent
+__global__ __launch_bounds__(BLOCK) void k_jp_light(Csr g, uint64_t seed, const int32_t *in, int32_t *ring, int64_t r,
+                                                    JpLists out, int32_t *color, int32_t *cnt)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * (BLOCK / 64);
+    int32_t *cur = ring + 3 * (r % JP_RING);
+    int32_t *next = ring + 3 * ((r + 1) % JP_RING);
+    const int64_t nf = cur[0];
+    if (blockIdx.x == 0 && threadIdx.x < 3) ring[3 * ((r + 2) % JP_RING) + threadIdx.x] = 0;
+    for (int64_t f = wave; f < nf; f += nwaves) {
+        const int32_t v = in[f];
+        const int64_t b = g.off[v], e = g.off[v + 1];
+        const uint64_t pv = jp_priority(seed, v);
+        int32_t c = -1;
+        for (int32_t base = 0; c < 0; base += 64) {
+            unsigned long long used = 0;
+            for (int64_t x = b + lane; x < e; x += 64) {
+                const int32_t u = g.col[x];
+                if (u == v || jp_priority(seed, u) < pv) continue;
+                const int32_t cu = color[u] - base;
+                if (cu >= 0 && cu < 64) used |= 1ull << cu;
+            }
+            used = wave_or(used);
+            if (used != ~0ull) c = base + __ffsll(~used) - 1;
+        }
+        if (lane == 0) color[v] = c;
+        for (int64_t x = b + lane; x < e; x += 64) {
+            const int32_t u = g.col[x];
+            if (u != v && jp_priority(seed, u) < pv)
+                if (atomicSub(&cnt[u], 1) == 1) jp_push(g, u, out, next);
+        }
+    }
+}
+
+// medium and heavy rows: one NT-thread workgroup per frontier vertex
+template <int NT, int K>
+__global__ __launch_bounds__(NT) void k_jp_block(Csr g, uint64_t seed, const int32_t *in, int32_t *ring, int64_t r,
+                                                 JpLists out, int32_t *color, int32_t *cnt)
 {
     __shared__ unsigned long long bm[JP_WINDOW_WORDS];
     __shared__ int32_t s_c;
-    int32_t *cur = ring + 2 * (r % JP_RING);
-    int32_t *next = ring + 2 * ((r + 1) % JP_RING);
-    const int64_t nf = HEAVY ? cur[1] : cur[0];
-    const int32_t *front = HEAVY ? in_heavy : in_light;
-    if (!HEAVY && blockIdx.x == 0 && threadIdx.x < 2) ring[2 * ((r + 2) % JP_RING) + threadIdx.x] = 0;
+    int32_t *cur = ring + 3 * (r % JP_RING);
+    int32_t *next = ring + 3 * ((r + 1) % JP_RING);
+    const int64_t nf = cur[K];
     for (int64_t f = blockIdx.x; f < nf; f += gridDim.x) {
-        const int32_t v = front[f];
+        const int32_t v = in[f];
         const int64_t b = g.off[v], e = g.off[v + 1];
         const uint64_t pv = jp_priority(seed, v);
         const int32_t c = jp_mex<NT>(g, seed, v, pv, b, e, color, bm, &s_c);
@@ -131,7 +182,7 @@ __global__ __launch_bounds__(NT) void k_jp_round(Csr g, uint64_t seed, const int
         for (int64_t x = b + threadIdx.x; x < e; x += NT) {
             const int32_t u = g.col[x];
             if (u != v && jp_priority(seed, u) < pv)
-                if (atomicSub(&cnt[u], 1) == 1) jp_push(g, u, out_light, out_heavy, next);
+                if (atomicSub(&cnt[u], 1) == 1) jp_push(g, u, out, next);
         }
     }
 }
@@ -144,37 +195,36 @@ __global__ __launch_bounds__(BLOCK) void k_color_max(const int32_t *color, int64
     atomicMax(out, m);
 }
 
-// ring needs 2 JP_RING + 1 entries (<= 16); cnt needs 3n entries (counts, then
-// the two heavy frontier lists); front_a / front_b are the light lists (n each)
+// ring needs 3 JP_RING + 1 entries (<= 16); cnt needs 5n entries (counts, then
+// the medium and heavy frontier lists, two each); front_a / front_b are the
+// light lists (n each)
 int32_t color_jp(const Csr &g, uint64_t seed, int32_t *color, int32_t *cnt, int32_t *front_a, int32_t *front_b,
                  int32_t *ring, hipStream_t st)
 {
     if (g.n == 0) return 0;
     fill<int32_t>(cnt, 0, g.n, st);
-    fill<int32_t>(ring, 0, 2 * JP_RING + 1, st);
+    fill<int32_t>(ring, 0, 3 * JP_RING + 1, st);
     if (g.nnz > 0) k_jp_count<<<grid_for(g.nnz, ETILE), BLOCK, 0, st>>>(g, seed, cnt);
     unsigned gv = grid_for(g.n, BLOCK * 4);
     if (gv > 65536) gv = 65536;
-    int32_t *heavy[2] = {cnt + g.n, cnt + 2 * g.n};
-    int32_t *light[2] = {front_a, front_b};
-    k_jp_start<<<gv, BLOCK, 0, st>>>(g, cnt, color, light[0], heavy[0], ring);
+    JpLists lists[2] = {{{front_a, cnt + g.n, cnt + 3 * g.n}}, {{front_b, cnt + 2 * g.n, cnt + 4 * g.n}}};
+    k_jp_start<<<gv, BLOCK, 0, st>>>(g, cnt, color, lists[0], ring);
     int64_t r = 0;     // next round to launch
     int64_t batch = 4; // rounds launched per host check, doubled up to 256
     for (;;) {
         for (int64_t i = 0; i < batch; ++i, ++r) {
-            const int a = r & 1, b = (r + 1) & 1;
-            k_jp_round<64, false><<<JP_GRID, 64, 0, st>>>(g, seed, light[a], heavy[a], ring, r, light[b], heavy[b],
-                                                          color, cnt);
-            k_jp_round<JP_HEAVY_BLOCK, true><<<JP_HEAVY_GRID, JP_HEAVY_BLOCK, 0, st>>>(
-                g, seed, light[a], heavy[a], ring, r, light[b], heavy[b], color, cnt);
+            const JpLists &in = lists[r & 1], &out = lists[(r + 1) & 1];
+            k_jp_light<<<JP_GRID, BLOCK, 0, st>>>(g, seed, in.list[0], ring, r, out, color, cnt);
+            k_jp_block<BLOCK, 1><<<JP_MEDIUM_GRID, BLOCK, 0, st>>>(g, seed, in.list[1], ring, r, out, color, cnt);
+            k_jp_block<1024, 2><<<JP_HEAVY_GRID, 1024, 0, st>>>(g, seed, in.list[2], ring, r, out, color, cnt);
         }
-        int32_t nf[2] = {0, 0};
-        hipMemcpyAsync(nf, ring + 2 * (r % JP_RING), 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        int32_t nf[3] = {0, 0, 0};
+        hipMemcpyAsync(nf, ring + 3 * (r % JP_RING), 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st);
         hipStreamSynchronize(st);
-        if (nf[0] == 0 && nf[1] == 0) break;
+        if (nf[0] == 0 && nf[1] == 0 && nf[2] == 0) break;
         if (batch < 256) batch *= 2;
     }
-    int32_t *mx_slot = ring + 2 * JP_RING;
+    int32_t *mx_slot = ring + 3 * JP_RING;
     fill<int32_t>(mx_slot, -1, 1, st);
     k_color_max<<<gv, BLOCK, 0, st>>>(color, g.n, mx_slot);
     int32_t mx = -1;

@@ -170,7 +170,11 @@ void weights_i64(const Csr &g, int64_t *w_out, hipStream_t st);
 
 // ---- sweep (sweep.hip) -----------------------------------------------------
 
-constexpr int NBINS = 10; // 0: isolated, 1..8 LDS bins, 9: hubs (global tables)
+// degree bins: 0 isolated, 1..8 LDS tables (rows up to 2048 entries), 9 mid
+// hubs (one workgroup, HBM table, rows up to MID_HUB_MAX), 10 giant hubs
+// (split across workgroups)
+constexpr int NBINS = 11;
+constexpr int64_t MID_HUB_MAX = 4096;
 __host__ __device__ inline int degree_bin(int64_t d)
 {
     if (d == 0) return 0;
@@ -182,7 +186,8 @@ __host__ __device__ inline int degree_bin(int64_t d)
     if (d <= 256) return 6;
     if (d <= 1024) return 7;
     if (d <= 2048) return 8;
-    return 9;
+    if (d <= MID_HUB_MAX) return 9;
+    return 10;
 }
 
 // device accumulators of one sweep launch group
@@ -209,8 +214,9 @@ struct SweepArgs {
     SweepStats *stats;
 };
 
-// hubs (bin 9): rows are split in HUB_CHUNK-entry chunks for insertion and
-// their HBM tables (pow2_ceil(2 d) slots) in HUB_SLICE-slot slices for the scan
+// hub rows (bins 9, 10) use HBM tables of pow2_ceil(2 d) slots; giant hubs
+// (bin 10) are split in HUB_CHUNK-entry chunks for insertion and their tables
+// in HUB_SLICE-slot slices for the scan
 constexpr int HUB_CHUNK = 2048;
 constexpr int HUB_SLICE = 4096;
 struct HubArgs {
@@ -223,13 +229,33 @@ struct HubArgs {
     int32_t *hkey;           // tables: key -1 = empty
     uint64_t *hval;
     int64_t *part;           // per slice: best gain (lo, hi), community, e
-    int64_t *aux;            // per slice (used at a hub's first slice): w_self, entries, e_A, distinct
+    int64_t *aux;            // 8 per slice (used at a hub's first slice): w_self, entries, e_A,
+                             // distinct, slices done
 };
 
-// launches the sweep kernel of one LDS degree bin (1..8); wide = 128-bit gains
-void sweep_bin(int bin, const SweepArgs &a, bool wide, hipStream_t st);
-// the three hub kernels for positions [h.s, h.e)
-void sweep_hubs(const SweepArgs &a, const HubArgs &h, bool wide, hipStream_t st);
+// vertices of one degree bin for a fused launch
+struct BinRange {
+    const int32_t *verts = nullptr;
+    int64_t count = 0;
+    int64_t block0 = 0;       // first block of the bin (set by the launcher)
+    SweepStats *stats = nullptr;
+};
+struct FusedBins {
+    BinRange bins[10];        // index = bin (1..9 used)
+    const int64_t *hoff9 = nullptr; // table offsets of the bin-9 vertices (count + 1, absolute slots)
+    int32_t *hkey = nullptr;        // HBM tables (shared with the giant hubs)
+    uint64_t *hval = nullptr;
+    int64_t hub_block0 = 0;   // first giant-hub insert block of the large launch
+};
+
+// Fused sweep launches (wide = 128-bit gains); each returns false when it had
+// nothing to launch.  small: bins 1..5; large: bins 6..9 plus the giant-hub
+// chunk inserts; then the giant-hub table scan and decisions (stats in a.stats).
+bool sweep_small(const SweepArgs &a, FusedBins f, bool wide, hipStream_t st);
+bool sweep_large(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, hipStream_t st);
+bool sweep_hub_scan(const SweepArgs &a, const HubArgs &h, bool wide, hipStream_t st);
+// small and large bins (and giant-hub inserts) in one launch with the large LDS size
+bool sweep_all(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, hipStream_t st);
 // per-vertex degree bin keys for sorting: key = (group << 4) | bin, val = vertex
 void bin_keys(const Csr &g, const int32_t *group, uint64_t *keys, int64_t *vals, hipStream_t st);
 // off[key] = first index of the sorted keys with key >= key, key in [0, nkeys]

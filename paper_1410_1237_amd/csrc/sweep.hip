@@ -50,18 +50,18 @@ __device__ __forceinline__ uint32_t slot_hash(int32_t c, int shift)
     return ((uint32_t)c * 0x9E3779B1u) >> (32 - shift);
 }
 
+// One block-tile of a degree bin: VPB = BLOCK / LPV vertices, LPV lanes each,
+// hash tables of 2^shift slots per vertex in LDS.
 template <int LPV, int WK, typename GT>
-__global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a, int shift)
+__device__ __forceinline__ void sweep_tile(const SweepArgs &a, const BinRange &br, int64_t tile, int shift,
+                                           unsigned char *smem, unsigned long long *bstat)
 {
     typedef typename std::conditional<WK == W_UNIT, uint32_t, unsigned long long>::type VT;
     constexpr int VPB = BLOCK / LPV;
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ unsigned long long bstat[5];
-
     const int grp = threadIdx.x / LPV, lane = threadIdx.x % LPV;
-    const int64_t vidx = (int64_t)blockIdx.x * VPB + grp;
-    const bool valid = vidx < a.count;
-    const int32_t i = valid ? a.verts[vidx] : 0;
+    const int64_t vidx = tile * VPB + grp;
+    const bool valid = vidx < br.count;
+    const int32_t i = valid ? br.verts[vidx] : 0;
 
     const int64_t S = (int64_t)1 << shift;
     int32_t *tkey = (int32_t *)smem + grp * S;
@@ -176,51 +176,11 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(SweepArgs a, int shift)
     __syncthreads();
     if (threadIdx.x < 5) {
         const unsigned long long v = bstat[threadIdx.x];
-        if (v) atomicAdd((unsigned long long *)&a.stats->moves + threadIdx.x, v);
+        if (v) atomicAdd((unsigned long long *)&br.stats->moves + threadIdx.x, v);
     }
 }
 
-template <int LPV, typename GT> static void launch_wk(const SweepArgs &a, int shift, hipStream_t st)
-{
-    constexpr int VPB = BLOCK / LPV;
-    const unsigned grid = grid_for(a.count, VPB);
-    const size_t slots = (size_t)VPB * ((size_t)1 << shift);
-    switch (a.g.wk) {
-    case W_UNIT:
-        k_sweep<LPV, W_UNIT, GT><<<grid, BLOCK, slots * (sizeof(int32_t) + sizeof(uint32_t)), st>>>(a, shift);
-        break;
-    case W_I32:
-        k_sweep<LPV, W_I32, GT><<<grid, BLOCK, slots * (sizeof(int32_t) + sizeof(uint64_t)), st>>>(a, shift);
-        break;
-    default:
-        k_sweep<LPV, W_I64, GT><<<grid, BLOCK, slots * (sizeof(int32_t) + sizeof(uint64_t)), st>>>(a, shift);
-        break;
-    }
-}
-
-template <typename GT> static void sweep_bin_t(int bin, const SweepArgs &a, hipStream_t st)
-{
-    switch (bin) {
-    case 1: launch_wk<4, GT>(a, 3, st); break;     // d <= 4: 8 slots
-    case 2: launch_wk<8, GT>(a, 4, st); break;     // d <= 8: 16 slots
-    case 3: launch_wk<16, GT>(a, 5, st); break;    // d <= 16: 32 slots
-    case 4: launch_wk<32, GT>(a, 6, st); break;    // d <= 32: 64 slots
-    case 5: launch_wk<64, GT>(a, 7, st); break;    // d <= 64: 128 slots
-    case 6: launch_wk<64, GT>(a, 9, st); break;    // d <= 256: 512 slots
-    case 7: launch_wk<256, GT>(a, 11, st); break;  // d <= 1024: 2048 slots
-    case 8: launch_wk<256, GT>(a, 12, st); break;  // d <= 2048: 4096 slots
-    default: break;
-    }
-}
-
-void sweep_bin(int bin, const SweepArgs &a, bool wide, hipStream_t st)
-{
-    if (a.count <= 0 || bin < 1 || bin > 8) return;
-    if (wide) sweep_bin_t<i128>(bin, a, st);
-    else sweep_bin_t<int64_t>(bin, a, st);
-}
-
-// ---- hubs: rows longer than 2048 entries --------------------------------------
+// hubs: rows longer than 2048 entries -----------------------------------------
 // (1) insert: each block pre-aggregates a 2048-entry chunk of one hub row in an
 // LDS table, then adds its distinct communities to the hub's HBM table;
 // (2) scan: each block reads a 4096-slot slice of one hub table, leaves it
@@ -238,13 +198,84 @@ __device__ __forceinline__ int64_t last_leq(const int64_t *arr, int64_t lo, int6
     return lo;
 }
 
-template <int WK>
-__global__ __launch_bounds__(BLOCK) void k_hub_insert(SweepArgs a, HubArgs h)
+// Merges the occupied slots of a block's LDS table (HUB_LDS slots) into an
+// HBM table of S slots.  Each thread holds its PER slots in registers and
+// issues their compare-and-swaps together, so up to PER device-coherent
+// atomics per thread are in flight instead of one.
+constexpr int FLUSH_PER = HUB_LDS / BLOCK;
+
+__device__ __forceinline__ void flush_to_hbm(const int32_t *tkey, const unsigned long long *tval, int32_t *gkey,
+                                             unsigned long long *gval, int64_t S, int gshift)
 {
-    __shared__ int32_t tkey[HUB_LDS];
-    __shared__ unsigned long long tval[HUB_LDS];
-    __shared__ int64_t red[BLOCK / 64][2];
-    const int64_t target = h.chunk0 + blockIdx.x;
+    int32_t kc[FLUSH_PER];
+    unsigned long long kv[FLUSH_PER];
+    uint32_t kq[FLUSH_PER];
+    uint32_t pend = 0;
+#pragma unroll
+    for (int j = 0; j < FLUSH_PER; ++j) {
+        const int s = threadIdx.x + j * BLOCK;
+        kc[j] = tkey[s];
+        kv[j] = tval[s];
+        kq[j] = kc[j] >= 0 ? slot_hash(kc[j], gshift) : 0;
+        if (kc[j] >= 0) pend |= 1u << j;
+    }
+    while (pend) {
+        int32_t old[FLUSH_PER];
+#pragma unroll
+        for (int j = 0; j < FLUSH_PER; ++j)
+            if ((pend >> j) & 1) old[j] = atomicCAS(&gkey[kq[j]], -1, kc[j]);
+#pragma unroll
+        for (int j = 0; j < FLUSH_PER; ++j) {
+            if (!((pend >> j) & 1)) continue;
+            if (old[j] == -1 || old[j] == kc[j]) {
+                atomicAdd(&gval[kq[j]], kv[j]);
+                pend &= ~(1u << j);
+            } else {
+                kq[j] = (kq[j] + 1) & (uint32_t)(S - 1);
+            }
+        }
+    }
+}
+
+// Reads (and clears) HBM table slots [base, base + count) with SCAN_PER
+// independent loads in flight per thread; calls f(community, weight) for
+// each occupied slot.
+constexpr int SCAN_PER = 16;
+
+template <class F>
+__device__ __forceinline__ void scan_hbm(int32_t *gkey, unsigned long long *gval, int64_t count, F f)
+{
+    for (int64_t base = 0; base < count; base += (int64_t)BLOCK * SCAN_PER) {
+        int32_t c[SCAN_PER];
+#pragma unroll
+        for (int j = 0; j < SCAN_PER; ++j) {
+            const int64_t s = base + threadIdx.x + (int64_t)j * BLOCK;
+            c[j] = s < count ? __hip_atomic_load(&gkey[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
+        }
+        unsigned long long w[SCAN_PER];
+#pragma unroll
+        for (int j = 0; j < SCAN_PER; ++j) {
+            const int64_t s = base + threadIdx.x + (int64_t)j * BLOCK;
+            w[j] = c[j] >= 0 ? __hip_atomic_load(&gval[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < SCAN_PER; ++j) {
+            if (c[j] < 0) continue;
+            const int64_t s = base + threadIdx.x + (int64_t)j * BLOCK;
+            gkey[s] = -1; // leave the table clean for the next sweep
+            gval[s] = 0;
+            f(c[j], (int64_t)w[j]);
+        }
+    }
+}
+
+template <int WK>
+__device__ __forceinline__ void hub_insert_tile(const SweepArgs &a, const HubArgs &h, int64_t tile, unsigned char *smem,
+                                                int64_t *red)
+{
+    int32_t *tkey = (int32_t *)smem;
+    unsigned long long *tval = (unsigned long long *)(smem + HUB_LDS * sizeof(int32_t));
+    const int64_t target = h.chunk0 + tile;
     const int64_t p = last_leq(h.cpre, h.s, h.e, target);
     const int32_t v = h.verts[p];
     const int64_t rb = a.g.off[v], re = a.g.off[v + 1];
@@ -287,35 +318,214 @@ __global__ __launch_bounds__(BLOCK) void k_hub_insert(SweepArgs a, HubArgs h)
     const int gshift = __ffsll((unsigned long long)S) - 1;
     int32_t *gkey = h.hkey + t0;
     unsigned long long *gval = (unsigned long long *)h.hval + t0;
-    for (int s = threadIdx.x; s < HUB_LDS; s += BLOCK) {
-        const int32_t c = tkey[s];
-        if (c < 0) continue;
-        const unsigned long long w = tval[s];
-        uint32_t q = slot_hash(c, gshift);
-        for (;;) {
-            const int32_t cur = atomicCAS(&gkey[q], -1, c);
-            if (cur == -1 || cur == c) {
-                atomicAdd(&gval[q], w);
-                break;
-            }
-            q = (q + 1) & (uint32_t)(S - 1);
-        }
-    }
+    flush_to_hbm(tkey, tval, gkey, gval, S, gshift);
     // self-loop weight and entry count of the chunk
     int64_t x = wself;
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) x += shfl_xor_t(x, m, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][0] = x;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
     __syncthreads();
     if (threadIdx.x == 0) {
         int64_t t = 0;
-        for (int w = 0; w < BLOCK / 64; ++w) t += red[w][0];
-        int64_t *aux = h.aux + 4 * (t0 / HUB_SLICE);
+        for (int w = 0; w < BLOCK / 64; ++w) t += red[w];
+        int64_t *aux = h.aux + 8 * (t0 / HUB_SLICE);
         if (t) atomicAdd((unsigned long long *)&aux[0], (unsigned long long)t);
         atomicAdd((unsigned long long *)&aux[1], (unsigned long long)(end - beg));
     }
 }
 
+// mid hubs (bin 9): one workgroup per vertex; the row is pre-aggregated per
+// 2048-entry chunk in LDS, merged into the vertex's HBM table, and the same
+// workgroup scans (and clears) the table and decides.
+template <int WK, typename GT>
+__device__ __forceinline__ void mid_hub_tile(const SweepArgs &a, const BinRange &br, const FusedBins &f,
+                                             int64_t tile, unsigned char *smem, unsigned long long *bstat)
+{
+    __shared__ Best<GT> sb[BLOCK / 64];
+    __shared__ int64_t se[BLOCK / 64][3];
+    int32_t *tkey = (int32_t *)smem;
+    unsigned long long *tval = (unsigned long long *)(smem + HUB_LDS * sizeof(int32_t));
+    const int32_t i = br.verts[tile];
+    const int64_t rb = a.g.off[i], re = a.g.off[i + 1];
+    const int64_t t0 = f.hoff9[tile], S = f.hoff9[tile + 1] - t0;
+    const int gshift = __ffsll((unsigned long long)S) - 1;
+    int32_t *gkey = f.hkey + t0;
+    unsigned long long *gval = (unsigned long long *)f.hval + t0;
+    (void)bstat;
+    int64_t wself = 0;
+    for (int64_t cb = rb; cb < re; cb += HUB_CHUNK) {
+        const int64_t ce = min(re, cb + HUB_CHUNK);
+        for (int s = threadIdx.x; s < HUB_LDS; s += BLOCK) {
+            tkey[s] = -1;
+            tval[s] = 0;
+        }
+        __syncthreads();
+        for (int64_t e = cb + threadIdx.x; e < ce; e += BLOCK) {
+            const int32_t j = a.g.col[e];
+            const int64_t w = WLoad<WK>::at(a.g.w, e);
+            if (j == i) {
+                wself += w;
+                continue;
+            }
+            const int32_t c = a.comm_prev[j];
+            uint32_t q = slot_hash(c, 12);
+            for (;;) {
+                int32_t cur = tkey[q];
+                if (cur == c) {
+                    atomicAdd(&tval[q], (unsigned long long)w);
+                    break;
+                }
+                if (cur == -1) {
+                    cur = atomicCAS(&tkey[q], -1, c);
+                    if (cur == -1 || cur == c) {
+                        atomicAdd(&tval[q], (unsigned long long)w);
+                        break;
+                    }
+                }
+                q = (q + 1) & (HUB_LDS - 1);
+            }
+        }
+        __syncthreads();
+        flush_to_hbm(tkey, tval, gkey, gval, S, gshift);
+        __threadfence();
+        __syncthreads();
+    }
+    const int32_t A = a.comm_prev[i];
+    const int64_t ki = a.k[i];
+    Best<GT> best{0, -1, 0};
+    int64_t eA = 0, distinct = 0;
+    scan_hbm(gkey, gval, S, [&](int32_t c, int64_t e) {
+        ++distinct;
+        if (c == A) {
+            eA = e;
+            return;
+        }
+        Best<GT> cand{(GT)a.two_m * (GT)e - (GT)ki * (GT)a.a[c], c, e};
+        if (better(cand, best)) best = cand;
+    });
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        Best<GT> o;
+        o.g = shfl_xor_t(best.g, m, 64);
+        o.c = shfl_xor_t(best.c, m, 64);
+        o.e = shfl_xor_t(best.e, m, 64);
+        if (better(o, best)) best = o;
+        eA += shfl_xor_t(eA, m, 64);
+        wself += shfl_xor_t(wself, m, 64);
+        distinct += shfl_xor_t(distinct, m, 64);
+    }
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sb[wid] = best;
+        se[wid][0] = eA;
+        se[wid][1] = wself;
+        se[wid][2] = distinct;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < BLOCK / 64; ++w) {
+            if (better(sb[w], best)) best = sb[w];
+            eA += se[w][0];
+            wself += se[w][1];
+            distinct += se[w][2];
+        }
+        const GT stay = (GT)a.two_m * (GT)eA - (GT)ki * (GT)(a.a[A] - ki);
+        bool move = best.c >= 0 && best.g > stay;
+        if (move && a.singlet && a.size[A] == 1 && a.size[best.c] == 1 && best.c > A) move = false;
+        a.comm_next[i] = move ? best.c : A;
+        unsigned long long *st = (unsigned long long *)&br.stats->moves;
+        if (move) {
+            atomicAdd(&st[0], 1ull);
+            atomicAdd(&st[2], (unsigned long long)(2 * (best.e - eA)));
+        }
+        atomicAdd(&st[1], (unsigned long long)(eA + wself));
+        atomicAdd(&st[3], (unsigned long long)distinct);
+        atomicAdd(&st[4], (unsigned long long)(re - rb));
+    }
+}
+
+// Fused launches: blocks are assigned to bins by block ranges.
+//  small: bins 1..5 (4..64 lanes per vertex, 512 LDS slots per block)
+//  large: bins 6..8 (64 or 256 lanes per vertex, up to 4096 slots) and the hub chunk inserts
+template <int WK, typename GT>
+__global__ __launch_bounds__(BLOCK) void k_sweep_small(SweepArgs a, FusedBins f)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ unsigned long long bstat[5];
+    const int64_t blk = blockIdx.x;
+    int b = 1;
+    while (b < 5 && blk >= f.bins[b + 1].block0) ++b;
+    const int64_t tile = blk - f.bins[b].block0;
+    switch (b) {
+    case 1: sweep_tile<4, WK, GT>(a, f.bins[1], tile, 3, smem, bstat); break;
+    case 2: sweep_tile<8, WK, GT>(a, f.bins[2], tile, 4, smem, bstat); break;
+    case 3: sweep_tile<16, WK, GT>(a, f.bins[3], tile, 5, smem, bstat); break;
+    case 4: sweep_tile<32, WK, GT>(a, f.bins[4], tile, 6, smem, bstat); break;
+    default: sweep_tile<64, WK, GT>(a, f.bins[5], tile, 7, smem, bstat); break;
+    }
+}
+
+template <int WK, typename GT>
+__global__ __launch_bounds__(BLOCK) void k_sweep_large(SweepArgs a, FusedBins f, HubArgs h)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ unsigned long long bstat[5];
+    __shared__ int64_t red[BLOCK / 64];
+    const int64_t blk = blockIdx.x;
+    if (blk >= f.hub_block0) {
+        hub_insert_tile<WK>(a, h, blk - f.hub_block0, smem, red);
+        return;
+    }
+    int b = 6;
+    while (b < 9 && blk >= f.bins[b + 1].block0) ++b;
+    const int64_t tile = blk - f.bins[b].block0;
+    switch (b) {
+    case 6: sweep_tile<64, WK, GT>(a, f.bins[6], tile, 9, smem, bstat); break;
+    case 7: sweep_tile<256, WK, GT>(a, f.bins[7], tile, 11, smem, bstat); break;
+    case 8: sweep_tile<256, WK, GT>(a, f.bins[8], tile, 12, smem, bstat); break;
+    default: mid_hub_tile<WK, GT>(a, f.bins[9], f, tile, smem, bstat); break;
+    }
+}
+
+// decision of giant hub p from its slice records (called by the last slice block)
+template <typename GT> __device__ void hub_decide_one(const SweepArgs &a, const HubArgs &h, int64_t p)
+{
+    const int32_t v = h.verts[p];
+    const int64_t first = h.hoff[p] / HUB_SLICE, last = h.hoff[p + 1] / HUB_SLICE;
+    Best<GT> best{0, -1, 0};
+    for (int64_t q = first; q < last; ++q) {
+        int64_t *rec = h.part + 4 * q;
+        const uint64_t lo = (uint64_t)__hip_atomic_load(&rec[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t hi = __hip_atomic_load(&rec[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const i128 g = (i128)(((u128)(uint64_t)hi << 64) | (u128)lo);
+        Best<GT> cand{(GT)g, (int32_t)__hip_atomic_load(&rec[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                      __hip_atomic_load(&rec[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+        if (better(cand, best)) best = cand;
+    }
+    int64_t *aux = h.aux + 8 * first;
+    const int64_t wself = __hip_atomic_load(&aux[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t entries = __hip_atomic_load(&aux[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t eA = __hip_atomic_load(&aux[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t distinct = __hip_atomic_load(&aux[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int t = 0; t < 5; ++t) __hip_atomic_store(&aux[t], (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t A = a.comm_prev[v];
+    const int64_t kv = a.k[v];
+    const GT stay = (GT)a.two_m * (GT)eA - (GT)kv * (GT)(a.a[A] - kv);
+    bool move = best.c >= 0 && best.g > stay;
+    if (move && a.singlet && a.size[A] == 1 && a.size[best.c] == 1 && best.c > A) move = false;
+    a.comm_next[v] = move ? best.c : A;
+    unsigned long long *st = (unsigned long long *)&a.stats->moves;
+    if (move) {
+        atomicAdd(&st[0], 1ull);
+        atomicAdd(&st[2], (unsigned long long)(2 * (best.e - eA)));
+    }
+    atomicAdd(&st[1], (unsigned long long)(eA + wself));
+    atomicAdd(&st[3], (unsigned long long)distinct);
+    atomicAdd(&st[4], (unsigned long long)entries);
+}
+
+// scan of one 4096-slot slice of a giant-hub table; the last slice block of a
+// hub (counted in aux[4]) makes the hub's decision
 template <typename GT>
 __global__ __launch_bounds__(BLOCK) void k_hub_scan(SweepArgs a, HubArgs h)
 {
@@ -329,20 +539,15 @@ __global__ __launch_bounds__(BLOCK) void k_hub_scan(SweepArgs a, HubArgs h)
     Best<GT> best{0, -1, 0};
     int64_t eA = 0, distinct = 0;
     const int64_t base = slice * HUB_SLICE;
-    for (int s = threadIdx.x; s < HUB_SLICE; s += BLOCK) {
-        const int32_t c = __hip_atomic_load(&h.hkey[base + s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (c < 0) continue;
-        const int64_t e = (int64_t)__hip_atomic_load(&h.hval[base + s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        h.hkey[base + s] = -1; // leave the table clean for the next sweep
-        h.hval[base + s] = 0;
+    scan_hbm(h.hkey + base, (unsigned long long *)h.hval + base, HUB_SLICE, [&](int32_t c, int64_t e) {
         ++distinct;
         if (c == A) {
             eA += e;
-            continue;
+            return;
         }
         Best<GT> cand{(GT)a.two_m * (GT)e - (GT)kv * (GT)a.a[c], c, e};
         if (better(cand, best)) best = cand;
-    }
+    });
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) {
         Best<GT> o;
@@ -368,73 +573,133 @@ __global__ __launch_bounds__(BLOCK) void k_hub_scan(SweepArgs a, HubArgs h)
         }
         int64_t *rec = h.part + 4 * slice;
         const i128 g = (i128)best.g;
-        rec[0] = (int64_t)(uint64_t)(u128)g;
-        rec[1] = (int64_t)(g >> 64);
-        rec[2] = best.c;
-        rec[3] = best.e;
-        int64_t *aux = h.aux + 4 * (h.hoff[p] / HUB_SLICE);
+        __hip_atomic_store(&rec[0], (int64_t)(uint64_t)(u128)g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&rec[1], (int64_t)(g >> 64), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&rec[2], (int64_t)best.c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&rec[3], best.e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t first = h.hoff[p] / HUB_SLICE, nsl = h.hoff[p + 1] / HUB_SLICE - first;
+        int64_t *aux = h.aux + 8 * first;
         if (eA) atomicAdd((unsigned long long *)&aux[2], (unsigned long long)eA);
         if (distinct) atomicAdd((unsigned long long *)&aux[3], (unsigned long long)distinct);
+        __threadfence();
+        const int64_t done = __hip_atomic_fetch_add(&aux[4], (int64_t)1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (done == nsl - 1) {
+            __threadfence();
+            hub_decide_one<GT>(a, h, p);
+        }
+    }
+}
+
+template <int WK, typename GT>
+__global__ __launch_bounds__(BLOCK) void k_sweep_all(SweepArgs a, FusedBins f, HubArgs h)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ unsigned long long bstat[5];
+    __shared__ int64_t red[BLOCK / 64];
+    const int64_t blk = blockIdx.x;
+    if (blk >= f.hub_block0) {
+        hub_insert_tile<WK>(a, h, blk - f.hub_block0, smem, red);
+        return;
+    }
+    int b = 1;
+    while (b < 9 && blk >= f.bins[b + 1].block0) ++b;
+    const int64_t tile = blk - f.bins[b].block0;
+    switch (b) {
+    case 1: sweep_tile<4, WK, GT>(a, f.bins[1], tile, 3, smem, bstat); break;
+    case 2: sweep_tile<8, WK, GT>(a, f.bins[2], tile, 4, smem, bstat); break;
+    case 3: sweep_tile<16, WK, GT>(a, f.bins[3], tile, 5, smem, bstat); break;
+    case 4: sweep_tile<32, WK, GT>(a, f.bins[4], tile, 6, smem, bstat); break;
+    case 5: sweep_tile<64, WK, GT>(a, f.bins[5], tile, 7, smem, bstat); break;
+    case 6: sweep_tile<64, WK, GT>(a, f.bins[6], tile, 9, smem, bstat); break;
+    case 7: sweep_tile<256, WK, GT>(a, f.bins[7], tile, 11, smem, bstat); break;
+    case 8: sweep_tile<256, WK, GT>(a, f.bins[8], tile, 12, smem, bstat); break;
+    default: mid_hub_tile<WK, GT>(a, f.bins[9], f, tile, smem, bstat); break;
+    }
+}
+
+// ---- host launchers --------------------------------------------------------
+template <typename GT> static void small_t(const SweepArgs &a, const FusedBins &f, int64_t blocks, hipStream_t st)
+{
+    switch (a.g.wk) {
+    case W_UNIT: k_sweep_small<W_UNIT, GT><<<(unsigned)blocks, BLOCK, 512 * 8, st>>>(a, f); break;
+    case W_I32: k_sweep_small<W_I32, GT><<<(unsigned)blocks, BLOCK, 512 * 12, st>>>(a, f); break;
+    default: k_sweep_small<W_I64, GT><<<(unsigned)blocks, BLOCK, 512 * 12, st>>>(a, f); break;
     }
 }
 
 template <typename GT>
-__global__ __launch_bounds__(BLOCK) void k_hub_decide(SweepArgs a, HubArgs h)
+static void large_t(const SweepArgs &a, const FusedBins &f, const HubArgs &h, int64_t blocks, hipStream_t st)
 {
-    __shared__ unsigned long long bstat[5];
-    if (threadIdx.x < 5) bstat[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t p = h.s + (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (p < h.e) {
-        const int32_t v = h.verts[p];
-        const int64_t first = h.hoff[p] / HUB_SLICE, last = h.hoff[p + 1] / HUB_SLICE;
-        Best<GT> best{0, -1, 0};
-        for (int64_t q = first; q < last; ++q) {
-            const int64_t *rec = h.part + 4 * q;
-            const i128 g = (i128)(((u128)(uint64_t)rec[1] << 64) | (u128)(uint64_t)rec[0]);
-            Best<GT> cand{(GT)g, (int32_t)rec[2], rec[3]};
-            if (better(cand, best)) best = cand;
-        }
-        int64_t *aux = h.aux + 4 * first;
-        const int64_t wself = aux[0], entries = aux[1], eA = aux[2], distinct = aux[3];
-        aux[0] = aux[1] = aux[2] = aux[3] = 0;
-        const int32_t A = a.comm_prev[v];
-        const int64_t kv = a.k[v];
-        const GT stay = (GT)a.two_m * (GT)eA - (GT)kv * (GT)(a.a[A] - kv);
-        bool move = best.c >= 0 && best.g > stay;
-        if (move && a.singlet && a.size[A] == 1 && a.size[best.c] == 1 && best.c > A) move = false;
-        a.comm_next[v] = move ? best.c : A;
-        if (move) {
-            atomicAdd(&bstat[0], 1ull);
-            atomicAdd(&bstat[2], (unsigned long long)(2 * (best.e - eA)));
-        }
-        atomicAdd(&bstat[1], (unsigned long long)(eA + wself));
-        atomicAdd(&bstat[3], (unsigned long long)distinct);
-        atomicAdd(&bstat[4], (unsigned long long)entries);
-    }
-    __syncthreads();
-    if (threadIdx.x < 5) {
-        const unsigned long long x = bstat[threadIdx.x];
-        if (x) atomicAdd((unsigned long long *)&a.stats->moves + threadIdx.x, x);
-    }
-}
-
-template <typename GT> static void hubs_t(const SweepArgs &a, const HubArgs &h, hipStream_t st)
-{
+    const size_t lds = (size_t)HUB_LDS * 12; // 4096 slots: int32 key + 64-bit value
     switch (a.g.wk) {
-    case W_UNIT: k_hub_insert<W_UNIT><<<(unsigned)h.n_insert, BLOCK, 0, st>>>(a, h); break;
-    case W_I32: k_hub_insert<W_I32><<<(unsigned)h.n_insert, BLOCK, 0, st>>>(a, h); break;
-    default: k_hub_insert<W_I64><<<(unsigned)h.n_insert, BLOCK, 0, st>>>(a, h); break;
+    case W_UNIT: k_sweep_large<W_UNIT, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h); break;
+    case W_I32: k_sweep_large<W_I32, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h); break;
+    default: k_sweep_large<W_I64, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h); break;
     }
-    k_hub_scan<GT><<<(unsigned)h.n_scan, BLOCK, 0, st>>>(a, h);
-    k_hub_decide<GT><<<grid_for(h.e - h.s, BLOCK), BLOCK, 0, st>>>(a, h);
 }
 
-void sweep_hubs(const SweepArgs &a, const HubArgs &h, bool wide, hipStream_t st)
+static const int kLanes[10] = {0, 4, 8, 16, 32, 64, 64, 256, 256, 256};
+
+bool sweep_small(const SweepArgs &a, FusedBins f, bool wide, hipStream_t st)
 {
-    if (h.e <= h.s) return;
-    if (wide) hubs_t<i128>(a, h, st);
-    else hubs_t<int64_t>(a, h, st);
+    int64_t blocks = 0;
+    for (int b = 1; b <= 5; ++b) {
+        f.bins[b].block0 = blocks;
+        blocks += (f.bins[b].count + BLOCK / kLanes[b] - 1) / (BLOCK / kLanes[b]);
+    }
+    if (blocks == 0) return false;
+    if (wide) small_t<i128>(a, f, blocks, st);
+    else small_t<int64_t>(a, f, blocks, st);
+    return true;
+}
+
+bool sweep_large(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, hipStream_t st)
+{
+    int64_t blocks = 0;
+    for (int b = 6; b <= 9; ++b) {
+        f.bins[b].block0 = blocks;
+        blocks += (f.bins[b].count + BLOCK / kLanes[b] - 1) / (BLOCK / kLanes[b]);
+    }
+    f.hub_block0 = blocks;
+    if (h.e > h.s) blocks += h.n_insert;
+    if (blocks == 0) return false;
+    if (wide) large_t<i128>(a, f, h, blocks, st);
+    else large_t<int64_t>(a, f, h, blocks, st);
+    return true;
+}
+
+bool sweep_hub_scan(const SweepArgs &a, const HubArgs &h, bool wide, hipStream_t st)
+{
+    if (h.e <= h.s) return false;
+    if (wide) k_hub_scan<i128><<<(unsigned)h.n_scan, BLOCK, 0, st>>>(a, h);
+    else k_hub_scan<int64_t><<<(unsigned)h.n_scan, BLOCK, 0, st>>>(a, h);
+    return true;
+}
+
+template <typename GT>
+static void all_t(const SweepArgs &a, const FusedBins &f, const HubArgs &h, int64_t blocks, hipStream_t st)
+{
+    const size_t lds = (size_t)HUB_LDS * 12;
+    switch (a.g.wk) {
+    case W_UNIT: k_sweep_all<W_UNIT, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h); break;
+    case W_I32: k_sweep_all<W_I32, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h); break;
+    default: k_sweep_all<W_I64, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h); break;
+    }
+}
+
+bool sweep_all(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, hipStream_t st)
+{
+    int64_t blocks = 0;
+    for (int b = 1; b <= 9; ++b) {
+        f.bins[b].block0 = blocks;
+        blocks += (f.bins[b].count + BLOCK / kLanes[b] - 1) / (BLOCK / kLanes[b]);
+    }
+    f.hub_block0 = blocks;
+    if (h.e > h.s) blocks += h.n_insert;
+    if (blocks == 0) return false;
+    if (wide) all_t<i128>(a, f, h, blocks, st);
+    else all_t<int64_t>(a, f, h, blocks, st);
+    return true;
 }
 
 // ---- binning ----------------------------------------------------------------
@@ -493,9 +758,9 @@ __global__ __launch_bounds__(BLOCK) void k_hub_sizes(const int64_t *off, const i
     for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < count; p += (int64_t)gridDim.x * BLOCK) {
         const int32_t v = verts[p];
         const int64_t d = off[v + 1] - off[v];
-        const bool hub = degree_bin(d) == 9;
-        slots[p] = hub ? pow2_ceil(2 * d) : 0; // >= 8192, a multiple of HUB_SLICE
-        chunks[p] = hub ? (d + HUB_CHUNK - 1) / HUB_CHUNK : 0;
+        const int bin = degree_bin(d);
+        slots[p] = bin >= 9 ? pow2_ceil(2 * d) : 0; // >= 8192, a multiple of HUB_SLICE
+        chunks[p] = bin == 10 ? (d + HUB_CHUNK - 1) / HUB_CHUNK : 0;
     }
 }
 

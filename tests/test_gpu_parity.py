@@ -33,7 +33,7 @@ def O():
 
 
 def hub_graph(seed=3, hub_deg=5000, extra=20000, n=8000):
-    """A random graph with one vertex of degree > 2048 (hub bin) and a few mid-degree ones."""
+    """A random graph with one vertex of degree hub_deg (hub bins) and a few of degree 300-900."""
     rng = np.random.default_rng(seed)
     edges = set()
     for v in rng.choice(np.arange(1, n), size=hub_deg, replace=False):
@@ -64,7 +64,8 @@ def small_cases():
 
 def medium_cases():
     return [GG.sbm_1000(), GG.rmat(12, 8, seed=5), GG.rmat(13, 16, wmax=100, seed=6), hub_graph(),
-            GG.chung_lu(20000, 2.1, 2000.0, 3.0e5, 150000, wmax=100, seed=4), GG.batch_sbm(7)]
+            GG.chung_lu(20000, 2.1, 2000.0, 3.0e5, 150000, wmax=100, seed=4), GG.batch_sbm(7),
+            hub_graph(seed=11, hub_deg=40000, extra=60000, n=50000)]
 
 
 def expand_w(g):
@@ -94,7 +95,7 @@ def test_steps_small(L, O, case):
 
 
 @pytest.mark.parametrize("colored", [False, True])
-@pytest.mark.parametrize("case", range(6))
+@pytest.mark.parametrize("case", range(7))
 def test_steps_medium(L, O, case, colored):
     g = medium_cases()[case]
     _steps(L, O, g, colored=colored, vf=(case % 3 != 1), phases=2, iters=4)
@@ -177,7 +178,7 @@ def test_run_small(L, O, pi):
         compare_run(res, ref, f"{g.name} {PARAM_SETS[pi]}")
 
 
-@pytest.mark.parametrize("case", range(6))
+@pytest.mark.parametrize("case", range(7))
 def test_run_medium(L, O, case):
     g = medium_cases()[case]
     for d in (dict(), dict(vf=1, color=1, color_cutoff=1000)):
