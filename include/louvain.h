@@ -228,6 +228,47 @@ louvain_status louvain_profile(louvain_graph_t g, int32_t enable);
 louvain_status louvain_profile_get(louvain_graph_t g, int32_t idx, const char **name, int64_t *launches,
                                    double *total_ms, double *bytes, double *entries);
 
+/* ---- batched form -------------------------------------------------------- */
+
+/*
+ * Many independent graphs in one handle, run together: the disjoint union is
+ * given as one CSR whose vertex ids are global (graph g owns vertices
+ * [graph_off[g], graph_off[g+1]) and no entry may leave its graph).  Every
+ * sweep, update and rebuild kernel covers all graphs at once; each graph
+ * keeps its own 2m and its own iteration and phase decisions, so each
+ * graph's labels and statistics equal those of louvain_run on that graph
+ * alone.  graph_off is a host array of num_graphs + 1 entries; the CSR
+ * arrays follow louvain_init_csr (flags LOUVAIN_DEVICE_PTRS, LOUVAIN_VALIDATE).
+ * The batched form runs uncolored phases (params->color must be 0).
+ */
+typedef struct louvain_batch_s *louvain_batch_t;
+
+typedef struct {
+    int64_t n, nnz;          /* the graph as given */
+    int64_t num_communities; /* K: its labels are 0..K-1 */
+    int64_t phases, iterations;
+    louvain_i128 q_num, q_den, q0_num;
+    double q;
+    int64_t n_vf;
+} louvain_graph_result;
+
+louvain_status louvain_batch_init(int32_t num_graphs, const int64_t *graph_off, int64_t nnz, const int64_t *offsets,
+                                  const int32_t *cols, const int32_t *weights, uint32_t flags, void *hip_stream,
+                                  louvain_batch_t *out);
+
+/* labels_out: graph_off[num_graphs] labels, local to each graph (may be NULL);
+ * results: num_graphs records (may be NULL). */
+louvain_status louvain_batch_run(louvain_batch_t b, const louvain_params *params, int32_t *labels_out,
+                                 uint32_t labels_on_device, louvain_graph_result *results);
+
+/* Per-phase and per-iteration records of one graph from the last batch run
+ * (owned by the batch; valid until the next run or destroy). */
+louvain_status louvain_batch_graph_stats(louvain_batch_t b, int32_t graph, const louvain_phase_stats **phases,
+                                         int64_t *num_phases, const louvain_iter_stats **iters, int64_t *num_iters);
+
+void louvain_batch_destroy(louvain_batch_t b);
+const char *louvain_batch_last_error(louvain_batch_t b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -236,6 +236,12 @@ struct louvain_graph_s {
     int64_t *dscal = nullptr;        // 16 device scalars
     int32_t *vflag = nullptr;
 
+    // batched graphs: set while a batch runs on this union graph
+    const int32_t *b_gid = nullptr;
+    const int64_t *b_two_m = nullptr;
+    const int32_t *b_active = nullptr;
+    int64_t *b_gstats = nullptr;
+
     // results
     std::vector<louvain_phase_stats> phases;
     std::vector<louvain_iter_stats> iters;
@@ -529,6 +535,10 @@ void sweep_group(G *g, int group, int singlet)
     a.k = g->k;
     a.two_m = g->two_m;
     a.singlet = singlet;
+    a.gid = g->b_gid;
+    a.two_m_g = g->b_two_m;
+    a.active_g = g->b_active;
+    a.gstats = g->b_gstats;
     a.verts = nullptr;
     a.count = 0;
     a.stats = g->stats + 10;
@@ -1219,6 +1229,381 @@ louvain_status louvain_profile_get(louvain_graph_t g, int32_t idx, const char **
     if (total_ms) *total_ms = r.ms;
     if (bytes) *bytes = r.bytes;
     if (entries) *entries = r.entries;
+    return LOUVAIN_OK;
+}
+
+} // extern "C"
+
+// ===========================================================================
+// Batched form: many independent graphs in one disjoint-union CSR.  Every
+// launch covers all graphs; each graph keeps its own iteration and phase
+// decisions (the rules of louvain_run, applied per graph on the host from
+// per-graph sweep statistics), so every graph's result is the one it gets
+// alone.  Coloring is not available in this form.
+// ===========================================================================
+struct louvain_batch_s {
+    G *g = nullptr;
+    int32_t ng = 0;
+    std::string err;
+    std::vector<int64_t> goff0, goff; // input / current graph offsets (host)
+    int64_t *goff_d = nullptr, *goff_tmp = nullptr, *gsum = nullptr, *gstats = nullptr, *two_m_d = nullptr,
+            *idx_d = nullptr, *gath = nullptr;
+    int32_t *gid0 = nullptr, *gid = nullptr, *active_d = nullptr, *keep_d = nullptr, *labels_tmp = nullptr;
+    std::vector<int64_t> two_m;
+    struct Run {
+        std::vector<louvain_phase_stats> phases;
+        std::vector<louvain_iter_stats> iters;
+        int64_t n = 0, nnz = 0, K = 0, n_vf = 0;
+        i128 N = 0, N0 = 0, Q_prev = 0;
+        bool finished = false;
+        // current phase
+        bool sweeping = false;
+        std::vector<i128> S2, Nt;
+        int t_end = 0, hit = 0;
+    };
+    std::vector<Run> runs;
+};
+
+namespace {
+
+typedef louvain_batch_s B;
+
+louvain_status bfail(B *b, louvain_status s, const std::string &m)
+{
+    b->err = m;
+    return s;
+}
+
+// current graph offsets (device goff_d) -> host goff; graph ids of the current level
+louvain_status batch_refresh_ids(B *b)
+{
+    G *g = b->g;
+    HIPCHK(g, hipMemcpyAsync(b->goff.data(), b->goff_d, (b->ng + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
+    lv::graph_ids(b->goff_d, b->ng, g->cur.n, b->gid, g->st);
+    return sync(g);
+}
+
+// after coarsen_current: new graph offsets from the renumbering
+louvain_status batch_after_coarsen(B *b, int64_t n_before, int64_t n_after)
+{
+    G *g = b->g;
+    lv::new_graph_offsets(b->goff_d, b->ng, n_before, g->new_id, n_after, b->goff_tmp, g->st);
+    std::swap(b->goff_d, b->goff_tmp);
+    return batch_refresh_ids(b);
+}
+
+// per-graph sums of x (and self-loops if with_self) into host vectors
+louvain_status batch_sums(B *b, const int64_t *x, bool with_self, std::vector<i128> &sq, std::vector<int64_t> *sum,
+                          std::vector<int64_t> *self)
+{
+    G *g = b->g;
+    lv::graph_sums(g->cur, with_self, x, b->goff_d, b->ng, b->gsum, g->st);
+    std::vector<int64_t> h(4 * (size_t)b->ng);
+    if (b->ng) HIPCHK(g, hipMemcpyAsync(h.data(), b->gsum, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
+    louvain_status s = sync(g);
+    if (s) return s;
+    sq.resize(b->ng);
+    if (sum) sum->resize(b->ng);
+    if (self) self->resize(b->ng);
+    for (int32_t i = 0; i < b->ng; ++i) {
+        sq[i] = (i128)(((u128)(uint64_t)h[4 * i + 2] << 64) | (u128)(uint64_t)h[4 * i + 1]);
+        if (sum) (*sum)[i] = h[4 * i];
+        if (self) (*self)[i] = h[4 * i + 3];
+    }
+    return LOUVAIN_OK;
+}
+
+// CSR entries of every graph of the current level
+louvain_status batch_nnz(B *b, std::vector<int64_t> &nnz)
+{
+    G *g = b->g;
+    lv::gather_i64(g->cur.off, b->goff_d, b->ng + 1, b->gath, g->st);
+    std::vector<int64_t> h(b->ng + 1);
+    HIPCHK(g, hipMemcpyAsync(h.data(), b->gath, (b->ng + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
+    louvain_status s = sync(g);
+    if (s) return s;
+    nnz.resize(b->ng);
+    for (int32_t i = 0; i < b->ng; ++i) nnz[i] = h[i + 1] - h[i];
+    return LOUVAIN_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+louvain_status louvain_batch_init(int32_t num_graphs, const int64_t *graph_off, int64_t nnz, const int64_t *offsets,
+                                  const int32_t *cols, const int32_t *weights, uint32_t flags, void *hip_stream,
+                                  louvain_batch_t *out)
+{
+    g_init_error.clear();
+    if (!out) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (num_graphs < 0 || !graph_off) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "bad graph offsets");
+    if (graph_off[0] != 0) return fail(nullptr, LOUVAIN_E_BAD_CSR, "graph_off[0] must be 0");
+    for (int32_t i = 0; i < num_graphs; ++i)
+        if (graph_off[i + 1] < graph_off[i]) return fail(nullptr, LOUVAIN_E_BAD_CSR, "graph offsets not monotone");
+    const int64_t n = graph_off[num_graphs];
+    louvain_graph_t g = nullptr;
+    louvain_status s = louvain_init_csr(n, nnz, offsets, cols, weights, flags, hip_stream, &g);
+    if (s) return s;
+    B *b = new B();
+    b->g = g;
+    b->ng = num_graphs;
+    b->goff0.assign(graph_off, graph_off + num_graphs + 1);
+    b->goff = b->goff0;
+    auto bail = [&](louvain_status st) {
+        g_init_error = g->err.empty() ? b->err : g->err;
+        louvain_destroy(g);
+        delete b;
+        return st;
+    };
+    const int64_t ng1 = num_graphs + 1;
+    if ((s = alloc(g, &b->goff_d, ng1)) || (s = alloc(g, &b->goff_tmp, ng1)) || (s = alloc(g, &b->gsum, 4 * ng1)) ||
+        (s = alloc(g, &b->gstats, 8 * ng1)) || (s = alloc(g, &b->two_m_d, ng1)) || (s = alloc(g, &b->gath, ng1)) ||
+        (s = alloc(g, &b->gid0, n)) || (s = alloc(g, &b->gid, n)) || (s = alloc(g, &b->active_d, ng1)) ||
+        (s = alloc(g, &b->keep_d, ng1)) || (s = alloc(g, &b->labels_tmp, n)))
+        return bail(s);
+    if (hipMemcpyAsync(b->goff_d, graph_off, ng1 * sizeof(int64_t), hipMemcpyHostToDevice, g->st) != hipSuccess)
+        return bail(LOUVAIN_E_HIP);
+    lv::graph_ids(b->goff_d, num_graphs, n, b->gid0, g->st);
+    // every edge must stay inside its graph
+    int32_t code = 0;
+    lv::fill<int32_t>(g->vflag, 0, 1, g->st);
+    lv::cross_edges(g->cur, b->gid0, g->vflag, g->st);
+    if (hipMemcpyAsync(&code, g->vflag, sizeof(code), hipMemcpyDeviceToHost, g->st) != hipSuccess ||
+        hipStreamSynchronize(g->st) != hipSuccess)
+        return bail(LOUVAIN_E_HIP);
+    if (code) {
+        g->err = "invalid batch: an edge joins two different graphs";
+        return bail(LOUVAIN_E_BAD_CSR);
+    }
+    *out = b;
+    return LOUVAIN_OK;
+}
+
+void louvain_batch_destroy(louvain_batch_t b)
+{
+    if (!b) return;
+    louvain_destroy(b->g);
+    delete b;
+}
+
+const char *louvain_batch_last_error(louvain_batch_t b)
+{
+    if (!b) return g_init_error.c_str();
+    return b->err.empty() ? b->g->err.c_str() : b->err.c_str();
+}
+
+louvain_status louvain_batch_run(louvain_batch_t b, const louvain_params *p, int32_t *labels_out,
+                                 uint32_t labels_on_device, louvain_graph_result *results)
+{
+    if (!b) return LOUVAIN_E_INVALID_ARG;
+    b->err.clear();
+    G *g = b->g;
+    louvain_status s = check_handle(g);
+    if (s) return s;
+    if ((s = check_params(g, p))) return s;
+    if (p->color) return bfail(b, LOUVAIN_E_INVALID_ARG, "the batched form runs uncolored phases (color must be 0)");
+    const int32_t ng = b->ng;
+    g->phases.clear();
+    g->iters.clear();
+    if ((s = reset_level0(g))) return s;
+    b->goff = b->goff0;
+    HIPCHK(g, hipMemcpyAsync(b->goff_d, b->goff0.data(), (ng + 1) * sizeof(int64_t), hipMemcpyHostToDevice, g->st));
+    if ((s = batch_refresh_ids(b))) return s;
+    b->runs.assign(ng, B::Run());
+    std::vector<i128> sq;
+    std::vector<int64_t> sum, self, nnz;
+    if ((s = batch_sums(b, g->k, true, sq, &sum, &self))) return s;
+    b->two_m = sum;
+    HIPCHK(g, hipMemcpyAsync(b->two_m_d, b->two_m.data(), ng * sizeof(int64_t), hipMemcpyHostToDevice, g->st));
+    if ((s = batch_nnz(b, nnz))) return s;
+    for (int32_t i = 0; i < ng; ++i) {
+        B::Run &r = b->runs[i];
+        r.n = b->goff[i + 1] - b->goff[i];
+        r.nnz = nnz[i];
+        r.finished = b->two_m[i] == 0;
+        r.K = r.n;
+        r.n_vf = r.n;
+    }
+    g->b_gid = b->gid;
+    g->b_two_m = b->two_m_d;
+    g->b_active = b->active_d;
+    g->b_gstats = b->gstats;
+    struct Unbind {
+        G *g;
+        ~Unbind() { g->b_gid = nullptr; g->b_two_m = nullptr; g->b_active = nullptr; g->b_gstats = nullptr; }
+    } unbind{g};
+
+    if (p->vf && g->two_m > 0) {
+        const int64_t n0 = g->cur.n;
+        int64_t nv = 0;
+        lv::vf_map(g->cur, g->comm_prev, g->st);
+        if ((s = coarsen_current(g, g->comm_prev, nv))) return s;
+        if ((s = batch_after_coarsen(b, n0, nv))) return s;
+    }
+    if ((s = batch_sums(b, g->k, true, sq, nullptr, &self))) return s;
+    for (int32_t i = 0; i < ng; ++i) {
+        B::Run &r = b->runs[i];
+        r.n_vf = b->goff[i + 1] - b->goff[i];
+        if (!r.finished) r.N0 = r.Q_prev = (i128)b->two_m[i] * self[i] - sq[i];
+    }
+    std::vector<int32_t> active(ng + 1, 0), keep(ng + 1, 0);
+    std::vector<int64_t> gst(8 * (size_t)(ng + 1));
+    for (int ph_idx = 1;; ++ph_idx) {
+        bool any = false;
+        for (auto &r : b->runs) any |= !r.finished;
+        if (!any) break;
+        if ((s = batch_nnz(b, nnz))) return s;
+        if ((s = build_bins(g, false))) return s;
+        // phase start: every graph from singletons; its Q_0 is its previous phase's Q
+        for (int32_t i = 0; i < ng; ++i) {
+            B::Run &r = b->runs[i];
+            active[i] = !r.finished;
+            r.sweeping = !r.finished;
+            if (r.finished) continue;
+            louvain_phase_stats ph;
+            std::memset(&ph, 0, sizeof(ph));
+            ph.n = b->goff[i + 1] - b->goff[i];
+            ph.nnz = nnz[i];
+            ph.first_iter = (int64_t)r.iters.size();
+            r.phases.push_back(ph);
+            r.S2.assign(1, sq[i]);
+            r.Nt.assign(1, r.Q_prev);
+            r.t_end = 0;
+            r.hit = 0;
+        }
+        HIPCHK(g, hipMemcpyAsync(b->active_d, active.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, g->st));
+        for (int sidx = 1;; ++sidx) {
+            lv::fill<int64_t>(b->gstats, 0, 8 * (int64_t)ng, g->st);
+            sweep_group(g, 0, p->singlet_rule);
+            if (ng) HIPCHK(g, hipMemcpyAsync(gst.data(), b->gstats, 8 * ng * sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
+            if ((s = sync(g))) return s;
+            prof_collect(g, nullptr, 0);
+            bool any_keep = false;
+            for (int32_t i = 0; i < ng; ++i) {
+                keep[i] = 0;
+                B::Run &r = b->runs[i];
+                if (!r.sweeping) continue;
+                const int64_t moves = gst[8 * i + 0], sigma = gst[8 * i + 1];
+                const i128 D = (i128)b->two_m[i] * b->two_m[i];
+                const louvain_ratio th = p->theta_final;
+                g->swept_entries += gst[8 * i + 4];
+                if (sidx >= 2) {
+                    r.Nt[sidx - 1] = (i128)b->two_m[i] * sigma - r.S2[sidx - 1];
+                    r.iters.back().q_num = to_abi(r.Nt[sidx - 1]);
+                    if (sidx - 1 >= 2 && below_threshold(r.Nt[sidx - 1], r.Nt[sidx - 2], D, th, p->threshold_mode)) {
+                        r.t_end = sidx - 1;
+                        r.sweeping = false;
+                        continue;
+                    }
+                    if (sidx - 1 >= p->max_iter) {
+                        r.hit = 1;
+                        r.t_end = sidx - 1;
+                        r.sweeping = false;
+                        continue;
+                    }
+                }
+                louvain_iter_stats rec{};
+                rec.moves = moves;
+                rec.pairs = gst[8 * i + 3];
+                rec.entries = gst[8 * i + 4];
+                r.iters.push_back(rec);
+                r.Nt.push_back(0);
+                r.S2.push_back(0);
+                if (moves == 0) {
+                    r.Nt[sidx] = r.Nt[sidx - 1];
+                    r.S2[sidx] = r.S2[sidx - 1];
+                    r.iters.back().q_num = to_abi(r.Nt[sidx]);
+                    r.t_end = sidx;
+                    r.sweeping = false;
+                    continue;
+                }
+                keep[i] = 1;
+                any_keep = true;
+            }
+            HIPCHK(g, hipMemcpyAsync(b->keep_d, keep.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, g->st));
+            {
+                ProfScope ps(g, PR_COMMIT, 8.0 * (double)g->cur.n, 0);
+                lv::commit_graphs(g->cur.n, g->comm_prev, g->comm_next, g->k, g->a, g->size, b->gid, b->keep_d,
+                                  g->st);
+            }
+            if (any_keep) {
+                std::vector<i128> s2;
+                if ((s = batch_sums(b, g->a, false, s2, nullptr, nullptr))) return s;
+                for (int32_t i = 0; i < ng; ++i)
+                    if (keep[i]) b->runs[i].S2[sidx] = s2[i];
+            }
+            bool still = false;
+            for (int32_t i = 0; i < ng; ++i) {
+                active[i] = b->runs[i].sweeping;
+                still |= b->runs[i].sweeping;
+            }
+            if (!still) break;
+            HIPCHK(g, hipMemcpyAsync(b->active_d, active.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, g->st));
+        }
+        if ((s = sync(g))) return s;
+        // rebuild every graph (a finished graph sits at singletons: an identity rebuild)
+        const int64_t n_before_all = g->cur.n;
+        std::vector<int64_t> n_before(ng);
+        for (int32_t i = 0; i < ng; ++i) n_before[i] = b->goff[i + 1] - b->goff[i];
+        int64_t n_after_all = 0;
+        if ((s = coarsen_current(g, g->comm_prev, n_after_all))) return s;
+        if ((s = batch_after_coarsen(b, n_before_all, n_after_all))) return s;
+        if ((s = batch_sums(b, g->k, true, sq, nullptr, nullptr))) return s;
+        for (int32_t i = 0; i < ng; ++i) {
+            B::Run &r = b->runs[i];
+            if (r.finished) continue;
+            louvain_phase_stats &ph = r.phases.back();
+            ph.iterations = r.t_end;
+            ph.hit_max_iter = r.hit;
+            const i128 Np = r.Nt[r.t_end];
+            ph.q_num = to_abi(Np);
+            const int64_t n_after = b->goff[i + 1] - b->goff[i];
+            const i128 D = (i128)b->two_m[i] * b->two_m[i];
+            const bool stop = n_after == n_before[i] || ph_idx >= p->max_phases ||
+                              below_threshold(Np, r.Q_prev, D, p->theta_final, 0);
+            r.Q_prev = Np;
+            if (stop) r.finished = true;
+        }
+    }
+    // labels local to each graph
+    if (labels_out && g->n0) {
+        lv::local_labels(g->orig_map, b->gid0, g->n0, b->goff_d, b->labels_tmp, g->st);
+        if ((s = copy_out(g, labels_out, b->labels_tmp, g->n0 * sizeof(int32_t), labels_on_device))) return s;
+    }
+    if ((s = sync(g))) return s;
+    if (results) {
+        for (int32_t i = 0; i < ng; ++i) {
+            B::Run &r = b->runs[i];
+            louvain_graph_result &o = results[i];
+            std::memset(&o, 0, sizeof(o));
+            o.n = b->goff0[i + 1] - b->goff0[i];
+            o.nnz = r.nnz;
+            o.num_communities = b->goff[i + 1] - b->goff[i];
+            o.phases = (int64_t)r.phases.size();
+            o.iterations = (int64_t)r.iters.size();
+            o.n_vf = r.n_vf;
+            const bool edges = b->two_m[i] > 0;
+            const i128 D = edges ? (i128)b->two_m[i] * b->two_m[i] : (i128)1;
+            o.q_num = to_abi(edges ? r.Q_prev : (i128)0);
+            o.q_den = to_abi(D);
+            o.q0_num = to_abi(edges ? r.N0 : (i128)0);
+            o.q = edges ? exact_ratio(r.Q_prev, D) : 0.0;
+        }
+    }
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_batch_graph_stats(louvain_batch_t b, int32_t graph, const louvain_phase_stats **phases,
+                                         int64_t *num_phases, const louvain_iter_stats **iters, int64_t *num_iters)
+{
+    if (!b || graph < 0 || graph >= b->ng || graph >= (int32_t)b->runs.size()) return LOUVAIN_E_INVALID_ARG;
+    const B::Run &r = b->runs[graph];
+    if (phases) *phases = r.phases.data();
+    if (num_phases) *num_phases = (int64_t)r.phases.size();
+    if (iters) *iters = r.iters.data();
+    if (num_iters) *num_iters = (int64_t)r.iters.size();
     return LOUVAIN_OK;
 }
 

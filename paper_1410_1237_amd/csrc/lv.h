@@ -202,16 +202,23 @@ struct SweepStats {
 
 struct SweepArgs {
     Csr g;
-    const int32_t *verts;    // vertex list of the launch
-    int64_t count;           // vertices in the list
-    const int32_t *comm_prev;
-    int32_t *comm_next;
-    const int64_t *a;
-    const int32_t *size;
-    const int64_t *k;
-    int64_t two_m;
-    int singlet;
-    SweepStats *stats;
+    const int32_t *verts = nullptr; // vertex list of the launch
+    int64_t count = 0;              // vertices in the list
+    const int32_t *comm_prev = nullptr;
+    int32_t *comm_next = nullptr;
+    const int64_t *a = nullptr;
+    const int32_t *size = nullptr;
+    const int64_t *k = nullptr;
+    int64_t two_m = 0;
+    int singlet = 1;
+    SweepStats *stats = nullptr;
+    // batched graphs (gid == null for a single graph): per-vertex graph id,
+    // per-graph 2m, per-graph "sweeping" flag and per-graph stats (8 int64
+    // each: moves, sigma_prev, dsigma, pairs, entries)
+    const int32_t *gid = nullptr;
+    const int64_t *two_m_g = nullptr;
+    const int32_t *active_g = nullptr;
+    int64_t *gstats = nullptr;
 };
 
 // hub rows (bins 9, 10) use HBM tables of pow2_ceil(2 d) slots; giant hubs
@@ -271,6 +278,21 @@ void gather_i64(const int64_t *src, const int64_t *idx, int64_t n, int64_t *out,
 void commit(const int32_t *verts, int64_t count, int32_t *comm_prev, const int32_t *comm_next,
             const int64_t *k, int64_t *a, int32_t *size, hipStream_t st);
 void clear_stats(SweepStats *s, int count, hipStream_t st);
+
+// ---- batched graphs (batch.hip) ------------------------------------------------
+void graph_ids(const int64_t *goff, int32_t ng, int64_t n, int32_t *gid, hipStream_t st);
+// flag := 6 when an entry joins two different graphs
+void cross_edges(const Csr &g, const int32_t *gid, int32_t *flag, hipStream_t st);
+// out[4g..4g+3]: sum x, sum x^2 (lo, hi), self-loop weight (if with_self)
+void graph_sums(const Csr &g, bool with_self, const int64_t *x, const int64_t *goff, int32_t ng, int64_t *out,
+                hipStream_t st);
+void commit_graphs(int64_t n, int32_t *comm_prev, int32_t *comm_next, const int64_t *k, int64_t *a, int32_t *size,
+                   const int32_t *gid, const int32_t *keep, hipStream_t st);
+void graph_internal(const Csr &g, const int32_t *comm, const int64_t *goff, int32_t ng, int64_t *out, hipStream_t st);
+void new_graph_offsets(const int64_t *goff, int32_t ng, int64_t n, const int32_t *new_id, int64_t total,
+                       int64_t *new_goff, hipStream_t st);
+void local_labels(const int32_t *orig_map, const int32_t *gid0, int64_t n0, const int64_t *goff, int32_t *labels,
+                  hipStream_t st);
 
 // ---- coloring (color.hip) ---------------------------------------------------
 

@@ -50,6 +50,48 @@ __device__ __forceinline__ uint32_t slot_hash(int32_t c, int shift)
     return ((uint32_t)c * 0x9E3779B1u) >> (32 - shift);
 }
 
+__device__ __forceinline__ int64_t two_m_of(const SweepArgs &a, int32_t v)
+{
+    return a.gid ? a.two_m_g[a.gid[v]] : a.two_m;
+}
+
+__device__ __forceinline__ bool sweeping(const SweepArgs &a, int32_t v)
+{
+    return !a.gid || a.active_g[a.gid[v]] != 0;
+}
+
+// per-graph stats of a batched sweep: one record per vertex group, runs of
+// equal graph ids folded by one thread (the vertices of a block are sorted by
+// id, so their graphs form few runs) before the global atomics
+template <int VPB>
+__device__ __forceinline__ void flush_graph_stats(const SweepArgs &a, int grp, bool leader, int32_t g,
+                                                  const int64_t v[5])
+{
+    __shared__ int64_t rec[VPB][5];
+    __shared__ int32_t rg[VPB];
+    if (leader) {
+        rg[grp] = g;
+        for (int k = 0; k < 5; ++k) rec[grp][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t cur = -1;
+        int64_t acc[5] = {0, 0, 0, 0, 0};
+        for (int q = 0; q <= VPB; ++q) {
+            const int32_t gq = q < VPB ? rg[q] : -2;
+            if (gq != cur) {
+                if (cur >= 0)
+                    for (int k = 0; k < 5; ++k)
+                        if (acc[k]) atomicAdd((unsigned long long *)&a.gstats[8 * (int64_t)cur + k], (unsigned long long)acc[k]);
+                cur = gq;
+                for (int k = 0; k < 5; ++k) acc[k] = 0;
+            }
+            if (q < VPB && gq >= 0)
+                for (int k = 0; k < 5; ++k) acc[k] += rec[q][k];
+        }
+    }
+}
+
 // One block-tile of a degree bin: VPB = BLOCK / LPV vertices, LPV lanes each,
 // hash tables of 2^shift slots per vertex in LDS.
 template <int LPV, int WK, typename GT>
@@ -60,8 +102,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const BinRange &b
     constexpr int VPB = BLOCK / LPV;
     const int grp = threadIdx.x / LPV, lane = threadIdx.x % LPV;
     const int64_t vidx = tile * VPB + grp;
-    const bool valid = vidx < br.count;
-    const int32_t i = valid ? br.verts[vidx] : 0;
+    const int32_t i = vidx < br.count ? br.verts[vidx] : 0;
+    const bool valid = vidx < br.count && sweeping(a, i);
+    const int64_t two_m = valid ? two_m_of(a, i) : 0;
 
     const int64_t S = (int64_t)1 << shift;
     int32_t *tkey = (int32_t *)smem + grp * S;
@@ -121,7 +164,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const BinRange &b
             eA = e;
             continue;
         }
-        Best<GT> cand{(GT)a.two_m * (GT)e - (GT)ki * (GT)a.a[c], c, e};
+        Best<GT> cand{(GT)two_m * (GT)e - (GT)ki * (GT)a.a[c], c, e};
         if (better(cand, best)) best = cand;
     }
 
@@ -160,18 +203,28 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const BinRange &b
     }
 
     // decision (Alg. 1: move iff the best gain beats staying; Sec. 5.1 singlet rule)
+    int64_t vs[5] = {0, 0, 0, 0, 0};
     if (lane == 0 && valid) {
-        const GT stay = (GT)a.two_m * (GT)eA - (GT)ki * (GT)(a.a[A] - ki);
+        const GT stay = (GT)two_m * (GT)eA - (GT)ki * (GT)(a.a[A] - ki);
         bool move = best.c >= 0 && best.g > stay;
         if (move && a.singlet && a.size[A] == 1 && a.size[best.c] == 1 && best.c > A) move = false;
         a.comm_next[i] = move ? best.c : A;
-        if (move) {
-            atomicAdd(&bstat[0], 1ull);
-            atomicAdd(&bstat[2], (unsigned long long)(2 * (best.e - eA)));
-        }
-        atomicAdd(&bstat[1], (unsigned long long)(eA + wself));
-        atomicAdd(&bstat[3], (unsigned long long)distinct);
-        atomicAdd(&bstat[4], (unsigned long long)(end - beg));
+        vs[0] = move ? 1 : 0;
+        vs[1] = eA + wself;
+        vs[2] = move ? 2 * (best.e - eA) : 0;
+        vs[3] = distinct;
+        vs[4] = end - beg;
+    }
+    if (a.gid) {
+        flush_graph_stats<VPB>(a, grp, lane == 0, valid ? a.gid[i] : -1, vs);
+        return;
+    }
+    if (lane == 0 && valid) {
+        if (vs[0]) atomicAdd(&bstat[0], 1ull);
+        if (vs[2]) atomicAdd(&bstat[2], (unsigned long long)vs[2]);
+        atomicAdd(&bstat[1], (unsigned long long)vs[1]);
+        atomicAdd(&bstat[3], (unsigned long long)vs[3]);
+        atomicAdd(&bstat[4], (unsigned long long)vs[4]);
     }
     __syncthreads();
     if (threadIdx.x < 5) {
@@ -278,6 +331,7 @@ __device__ __forceinline__ void hub_insert_tile(const SweepArgs &a, const HubArg
     const int64_t target = h.chunk0 + tile;
     const int64_t p = last_leq(h.cpre, h.s, h.e, target);
     const int32_t v = h.verts[p];
+    if (!sweeping(a, v)) return; // uniform over the block
     const int64_t rb = a.g.off[v], re = a.g.off[v + 1];
     const int64_t beg = rb + (target - h.cpre[p]) * HUB_CHUNK;
     const int64_t end = min(re, beg + HUB_CHUNK);
@@ -346,6 +400,8 @@ __device__ __forceinline__ void mid_hub_tile(const SweepArgs &a, const BinRange 
     int32_t *tkey = (int32_t *)smem;
     unsigned long long *tval = (unsigned long long *)(smem + HUB_LDS * sizeof(int32_t));
     const int32_t i = br.verts[tile];
+    if (!sweeping(a, i)) return; // uniform over the block
+    const int64_t two_m = two_m_of(a, i);
     const int64_t rb = a.g.off[i], re = a.g.off[i + 1];
     const int64_t t0 = f.hoff9[tile], S = f.hoff9[tile + 1] - t0;
     const int gshift = __ffsll((unsigned long long)S) - 1;
@@ -400,7 +456,7 @@ __device__ __forceinline__ void mid_hub_tile(const SweepArgs &a, const BinRange 
             eA = e;
             return;
         }
-        Best<GT> cand{(GT)a.two_m * (GT)e - (GT)ki * (GT)a.a[c], c, e};
+        Best<GT> cand{(GT)two_m * (GT)e - (GT)ki * (GT)a.a[c], c, e};
         if (better(cand, best)) best = cand;
     });
 #pragma unroll
@@ -429,11 +485,12 @@ __device__ __forceinline__ void mid_hub_tile(const SweepArgs &a, const BinRange 
             wself += se[w][1];
             distinct += se[w][2];
         }
-        const GT stay = (GT)a.two_m * (GT)eA - (GT)ki * (GT)(a.a[A] - ki);
+        const GT stay = (GT)two_m * (GT)eA - (GT)ki * (GT)(a.a[A] - ki);
         bool move = best.c >= 0 && best.g > stay;
         if (move && a.singlet && a.size[A] == 1 && a.size[best.c] == 1 && best.c > A) move = false;
         a.comm_next[i] = move ? best.c : A;
-        unsigned long long *st = (unsigned long long *)&br.stats->moves;
+        unsigned long long *st =
+            a.gid ? (unsigned long long *)&a.gstats[8 * (int64_t)a.gid[i]] : (unsigned long long *)&br.stats->moves;
         if (move) {
             atomicAdd(&st[0], 1ull);
             atomicAdd(&st[2], (unsigned long long)(2 * (best.e - eA)));
@@ -510,11 +567,12 @@ template <typename GT> __device__ void hub_decide_one(const SweepArgs &a, const 
     for (int t = 0; t < 5; ++t) __hip_atomic_store(&aux[t], (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int32_t A = a.comm_prev[v];
     const int64_t kv = a.k[v];
-    const GT stay = (GT)a.two_m * (GT)eA - (GT)kv * (GT)(a.a[A] - kv);
+    const GT stay = (GT)two_m_of(a, v) * (GT)eA - (GT)kv * (GT)(a.a[A] - kv);
     bool move = best.c >= 0 && best.g > stay;
     if (move && a.singlet && a.size[A] == 1 && a.size[best.c] == 1 && best.c > A) move = false;
     a.comm_next[v] = move ? best.c : A;
-    unsigned long long *st = (unsigned long long *)&a.stats->moves;
+    unsigned long long *st =
+        a.gid ? (unsigned long long *)&a.gstats[8 * (int64_t)a.gid[v]] : (unsigned long long *)&a.stats->moves;
     if (move) {
         atomicAdd(&st[0], 1ull);
         atomicAdd(&st[2], (unsigned long long)(2 * (best.e - eA)));
@@ -534,6 +592,8 @@ __global__ __launch_bounds__(BLOCK) void k_hub_scan(SweepArgs a, HubArgs h)
     const int64_t slice = h.slice0 + blockIdx.x;
     const int64_t p = last_leq(h.hoff, h.s, h.e, slice * HUB_SLICE);
     const int32_t v = h.verts[p];
+    if (!sweeping(a, v)) return; // uniform over the block
+    const int64_t two_m = two_m_of(a, v);
     const int32_t A = a.comm_prev[v];
     const int64_t kv = a.k[v];
     Best<GT> best{0, -1, 0};
@@ -545,7 +605,7 @@ __global__ __launch_bounds__(BLOCK) void k_hub_scan(SweepArgs a, HubArgs h)
             eA += e;
             return;
         }
-        Best<GT> cand{(GT)a.two_m * (GT)e - (GT)kv * (GT)a.a[c], c, e};
+        Best<GT> cand{(GT)two_m * (GT)e - (GT)kv * (GT)a.a[c], c, e};
         if (better(cand, best)) best = cand;
     });
 #pragma unroll

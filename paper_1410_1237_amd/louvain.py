@@ -71,12 +71,19 @@ class Result(ctypes.Structure):
                 ("phase", ctypes.POINTER(PhaseStats)), ("iter", ctypes.POINTER(IterStats))]
 
 
+class GraphResult(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("num_communities", ctypes.c_int64),
+                ("phases", ctypes.c_int64), ("iterations", ctypes.c_int64), ("q_num", I128), ("q_den", I128),
+                ("q0_num", I128), ("q", ctypes.c_double), ("n_vf", ctypes.c_int64)]
+
+
 _lib = None
 
 EXPORTS = ["louvain_params_default", "louvain_init_csr", "louvain_vf", "louvain_color", "louvain_sweep",
            "louvain_coarsen", "louvain_run", "louvain_destroy", "louvain_last_error", "louvain_get_info",
            "louvain_get_state", "louvain_get_graph", "louvain_get_colors", "louvain_get_map", "louvain_profile",
-           "louvain_profile_get"]
+           "louvain_profile_get", "louvain_batch_init", "louvain_batch_run", "louvain_batch_graph_stats",
+           "louvain_batch_destroy", "louvain_batch_last_error"]
 
 
 def lib():
@@ -123,6 +130,18 @@ def lib():
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double)]
     L.louvain_profile_get.restype = st
+    L.louvain_batch_init.argtypes = [i32, vp, i64, vp, vp, vp, u32, vp, ctypes.POINTER(vp)]
+    L.louvain_batch_init.restype = st
+    L.louvain_batch_run.argtypes = [vp, ctypes.POINTER(Params), vp, u32, vp]
+    L.louvain_batch_run.restype = st
+    L.louvain_batch_graph_stats.argtypes = [vp, i32, ctypes.POINTER(ctypes.POINTER(PhaseStats)),
+                                            ctypes.POINTER(i64), ctypes.POINTER(ctypes.POINTER(IterStats)),
+                                            ctypes.POINTER(i64)]
+    L.louvain_batch_graph_stats.restype = st
+    L.louvain_batch_destroy.argtypes = [vp]
+    L.louvain_batch_destroy.restype = None
+    L.louvain_batch_last_error.argtypes = [vp]
+    L.louvain_batch_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -388,3 +407,113 @@ class Graph:
                          "bytes": byts.value, "entries": ent.value})
             idx += 1
         return recs
+
+
+# ---- batched form ---------------------------------------------------------------
+def union_csr(graphs):
+    """Packs graphs into one disjoint-union CSR: (graph_off, offsets, cols, weights)."""
+    ns = [g.n for g in graphs]
+    goff = np.zeros(len(graphs) + 1, dtype=np.int64)
+    goff[1:] = np.cumsum(ns)
+    weighted = any(g.weights is not None for g in graphs)
+    offs, cols, ws = [np.zeros(1, dtype=np.int64)], [], []
+    base_e = 0
+    for gi, g in enumerate(graphs):
+        offs.append(g.offsets[1:] + base_e)
+        cols.append(g.cols.astype(np.int64) + goff[gi])
+        if weighted:
+            ws.append(np.ones(g.nnz, np.int32) if g.weights is None else g.weights)
+        base_e += g.nnz
+    off = np.concatenate(offs).astype(np.int64)
+    col = np.concatenate(cols).astype(np.int32) if cols else np.zeros(0, np.int32)
+    w = np.concatenate(ws).astype(np.int32) if weighted and ws else None
+    return goff, off, col, w
+
+
+def louvain_batch_init(num_graphs, graph_off, nnz, offsets, cols, weights=None, flags=VALIDATE, hip_stream=None):
+    def ptr(x):
+        if x is None:
+            return None
+        if isinstance(x, np.ndarray):
+            return x.ctypes.data
+        return int(x)
+    h = ctypes.c_void_p()
+    goff = np.ascontiguousarray(graph_off, dtype=np.int64)
+    st = lib().louvain_batch_init(int(num_graphs), goff.ctypes.data, int(nnz), ptr(offsets), ptr(cols), ptr(weights),
+                                  int(flags), _stream_ptr(hip_stream), ctypes.byref(h))
+    if st != OK:
+        raise LouvainError(st, lib().louvain_batch_last_error(None).decode())
+    return h.value
+
+
+class Batch:
+    """Many graphs run together by the batched kernels."""
+
+    def __init__(self, graphs, validate: bool = True, stream=None):
+        self.graphs = list(graphs)
+        goff, off, col, w = union_csr(self.graphs)
+        self.goff = goff
+        self.h = louvain_batch_init(len(self.graphs), goff, int(off[-1]), off, col, w,
+                                    VALIDATE if validate else 0, stream)
+
+    @classmethod
+    def from_union(cls, graph_off, offsets, cols, weights=None, device=True, stream=None):
+        """Device tensors (torch) of a union CSR already in HBM."""
+        self = cls.__new__(cls)
+        self.graphs = None
+        self.goff = np.ascontiguousarray(graph_off, dtype=np.int64)
+        self.h = louvain_batch_init(len(self.goff) - 1, self.goff, cols.numel(), offsets.data_ptr(),
+                                    cols.data_ptr(), None if weights is None else weights.data_ptr(),
+                                    DEVICE_PTRS, stream)
+        return self
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().louvain_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, p: Optional[Params] = None, labels=None, stats: bool = True, **kw):
+        """Returns (list of per-graph RunResult, labels array of the union) ;
+        labels may be a torch int32 device tensor (then results carry no labels)."""
+        p = p or params(**kw)
+        ng = len(self.goff) - 1
+        res = (GraphResult * max(ng, 1))()
+        n = int(self.goff[-1])
+        host = labels is None
+        out = np.zeros(max(n, 1), dtype=np.int32) if host else None
+        st = lib().louvain_batch_run(self.h, ctypes.byref(p), out.ctypes.data if host else labels.data_ptr(),
+                                     0 if host else 1, res)
+        if st != OK:
+            raise LouvainError(st, lib().louvain_batch_last_error(self.h).decode())
+        results = []
+        for gi in range(ng):
+            r = res[gi]
+            phases = []
+            if stats:
+                pp = ctypes.POINTER(PhaseStats)()
+                ip = ctypes.POINTER(IterStats)()
+                npn = ctypes.c_int64()
+                nin = ctypes.c_int64()
+                lib().louvain_batch_graph_stats(self.h, gi, ctypes.byref(pp), ctypes.byref(npn), ctypes.byref(ip),
+                                                ctypes.byref(nin))
+                iters = [ip[t] for t in range(nin.value)]
+                for q in range(npn.value):
+                    ph = pp[q]
+                    its = iters[ph.first_iter:ph.first_iter + ph.iterations]
+                    phases.append(PhaseInfo(n=ph.n, nnz=ph.nnz, colored=bool(ph.colored), num_colors=ph.num_colors,
+                                            iterations=ph.iterations, hit_max_iter=bool(ph.hit_max_iter),
+                                            moves=[it.moves for it in its], N_iter=[it.q_num.value() for it in its],
+                                            N_end=ph.q_num.value(), pairs=[it.pairs for it in its],
+                                            entries=[it.entries for it in its], ms_color=0.0, ms_sweep=0.0,
+                                            ms_coarsen=0.0))
+            lab = out[self.goff[gi]:self.goff[gi + 1]].copy() if host else None
+            results.append(RunResult(labels=lab, K=r.num_communities, N=r.q_num.value(), D=r.q_den.value(), q=r.q,
+                                     n_vf=r.n_vf, N0=r.q0_num.value(), sweep_entries=0, ms_total=0.0, ms_vf=0.0,
+                                     ms_color=0.0, ms_sweep=0.0, ms_coarsen=0.0, phases=phases))
+        return results
