@@ -269,6 +269,54 @@ louvain_status louvain_batch_graph_stats(louvain_batch_t b, int32_t graph, const
 void louvain_batch_destroy(louvain_batch_t b);
 const char *louvain_batch_last_error(louvain_batch_t b);
 
+/* ---- served form --------------------------------------------------------- */
+
+/*
+ * A request loop with continuous batching: jobs (host CSRs, copied at submit)
+ * queue FIFO; a scheduler thread admits jobs from the queue head into a new
+ * batch whenever fewer than max_inflight_batches batches run and the HBM
+ * budget covers the batch's estimated device footprint; each batch runs the
+ * batched form on its own worker thread and HIP stream, so batches admitted
+ * at different times overlap on the device, and memory returned by a
+ * finished batch admits the next jobs.  Each job's result equals the graph
+ * run alone.  A job larger than the whole budget fails with LOUVAIN_E_OOM.
+ * Uses the device current at louvain_server_create.
+ */
+typedef struct louvain_server_s *louvain_server_t;
+
+typedef struct {
+    uint64_t hbm_budget_bytes;     /* device memory the server may reserve (default 200 GiB) */
+    int32_t max_inflight_batches;  /* concurrent batches / streams (default 4) */
+    int32_t max_batch_graphs;      /* jobs per batch (default 4096) */
+    int64_t max_batch_vertices;    /* vertices per batch, 0 = no limit */
+} louvain_server_config;
+
+typedef struct {
+    louvain_graph_result result;
+    int32_t status;                /* louvain_status of the job */
+    int32_t reserved;
+    double t_submit, t_admit, t_done; /* seconds since the server started */
+    int64_t batch_id, batch_graphs;   /* the batch that ran the job and its size */
+} louvain_job_result;
+
+void louvain_server_config_default(louvain_server_config *cfg);
+/* cfg may be NULL (defaults); params->color must be 0 */
+louvain_status louvain_server_create(const louvain_server_config *cfg, const louvain_params *params,
+                                     louvain_server_t *out);
+louvain_status louvain_server_submit(louvain_server_t s, int64_t n, int64_t nnz, const int64_t *offsets,
+                                     const int32_t *cols, const int32_t *weights, uint64_t *ticket);
+/* *done = 1 once the job finished; then labels_out (n host entries, may be
+ * NULL) and *out (may be NULL) are filled */
+louvain_status louvain_server_poll(louvain_server_t s, uint64_t ticket, int32_t *labels_out, louvain_job_result *out,
+                                   int32_t *done);
+/* forgets a finished job */
+louvain_status louvain_server_release(louvain_server_t s, uint64_t ticket);
+/* blocks until every submitted job finished */
+louvain_status louvain_server_wait_all(louvain_server_t s);
+const char *louvain_server_last_error(louvain_server_t s);
+/* waits for the submitted jobs, then stops the loop */
+void louvain_server_destroy(louvain_server_t s);
+
 #ifdef __cplusplus
 }
 #endif

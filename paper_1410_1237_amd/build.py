@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblouvain.so")
 GEN_LIB = os.path.join(PKG, "_graphgen.so")
-SOURCES = ["prims.hip", "graph.hip", "sweep.hip", "color.hip", "batch.hip", "api.hip"]
+SOURCES = ["prims.hip", "graph.hip", "sweep.hip", "color.hip", "batch.hip", "api.hip", "serve.hip"]
 ARCH = os.environ.get("LOUVAIN_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

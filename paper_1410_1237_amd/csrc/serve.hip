@@ -1,0 +1,355 @@
+// Served form: a request loop that admits community-detection jobs into
+// batches while other batches are on the device.
+//
+// Jobs are queued FIFO with a copy of their CSR.  A scheduler thread forms
+// a batch from the queue head whenever a worker slot is free and the HBM
+// budget covers the batch's estimated footprint; each batch runs on its own
+// worker thread and HIP stream through the batched form, so batches admitted
+// at different times overlap on the device.  Memory is reserved at admission
+// and returned when the batch completes, which may admit the next jobs.
+// Every job's result is the one it gets alone (the batched form is exact per
+// graph).
+#include "louvain.h"
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+namespace {
+
+struct Job {
+    uint64_t ticket = 0;
+    int64_t n = 0, nnz = 0;
+    std::vector<int64_t> off;
+    std::vector<int32_t> col, w;
+    bool weighted = false;
+    uint64_t bytes = 0;
+    // outcome
+    int32_t status = -1; // -1 pending, else louvain_status
+    bool done = false;
+    louvain_graph_result res{};
+    std::vector<int32_t> labels;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int64_t batch_id = -1, batch_graphs = 0;
+};
+
+// device bytes a job adds to a batch (mirrors the handle's allocations:
+// three CSR copies, two coarse weight arrays, sort buffers, vertex arrays)
+uint64_t job_bytes(int64_t n, int64_t nnz)
+{
+    const uint64_t big = (uint64_t)(nnz > n ? nnz : n) + 1;
+    return 3ull * 8 * (n + 1) + 3ull * 4 * nnz + 2ull * 8 * nnz + 4ull * nnz + 5ull * 8 * big + 120ull * n;
+}
+
+} // namespace
+
+struct louvain_server_s {
+    louvain_server_config cfg{};
+    louvain_params params{};
+    int dev = 0;
+    std::chrono::steady_clock::time_point t0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<std::shared_ptr<Job>> queue;
+    std::map<uint64_t, std::shared_ptr<Job>> jobs;
+    uint64_t next_ticket = 1;
+    uint64_t reserved = 0;
+    int inflight = 0;
+    int64_t next_batch = 0;
+    bool stop = false;
+    int64_t pending = 0; // submitted and not done
+    std::thread scheduler;
+    struct Worker {
+        std::thread thread;
+        std::shared_ptr<std::atomic<bool>> finished;
+    };
+    std::vector<Worker> workers;
+    std::string err;
+
+    double now() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+typedef louvain_server_s S;
+typedef louvain_server_s::Worker Worker;
+
+void run_batch(S *s, std::vector<std::shared_ptr<Job>> batch, int64_t batch_id, uint64_t bytes)
+{
+    (void)hipSetDevice(s->dev);
+    hipStream_t st = nullptr;
+    (void)hipStreamCreate(&st); // default priority
+    const int32_t ng = (int32_t)batch.size();
+    std::vector<int64_t> goff(ng + 1, 0);
+    int64_t nnz = 0;
+    bool weighted = false;
+    for (int32_t i = 0; i < ng; ++i) {
+        goff[i + 1] = goff[i] + batch[i]->n;
+        nnz += batch[i]->nnz;
+        weighted |= batch[i]->weighted;
+    }
+    const int64_t n = goff[ng];
+    std::vector<int64_t> off(n + 1, 0);
+    std::vector<int32_t> col(nnz), w(weighted ? nnz : 0);
+    int64_t e = 0;
+    for (int32_t i = 0; i < ng; ++i) {
+        const Job &j = *batch[i];
+        for (int64_t v = 0; v < j.n; ++v) off[goff[i] + v + 1] = e + j.off[v + 1];
+        for (int64_t x = 0; x < j.nnz; ++x) {
+            col[e + x] = (int32_t)(j.col[x] + goff[i]);
+            if (weighted) w[e + x] = j.weighted ? j.w[x] : 1;
+        }
+        e += j.nnz;
+    }
+    std::vector<louvain_graph_result> res(ng);
+    std::vector<int32_t> labels(n > 0 ? n : 1);
+    louvain_batch_t b = nullptr;
+    louvain_status rc = louvain_batch_init(ng, goff.data(), nnz, off.data(), col.data(), weighted ? w.data() : nullptr,
+                                           LOUVAIN_VALIDATE, st, &b);
+    if (rc == LOUVAIN_OK) rc = louvain_batch_run(b, &s->params, labels.data(), 0, res.data());
+    std::string msg = rc == LOUVAIN_OK ? "" : louvain_batch_last_error(b);
+    louvain_batch_destroy(b);
+    (void)hipStreamDestroy(st);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        const double t = s->now();
+        for (int32_t i = 0; i < ng; ++i) {
+            Job &j = *batch[i];
+            j.status = rc;
+            if (rc == LOUVAIN_OK) {
+                j.res = res[i];
+                j.labels.assign(labels.begin() + goff[i], labels.begin() + goff[i + 1]);
+            }
+            j.t_done = t;
+            j.batch_id = batch_id;
+            j.batch_graphs = ng;
+            j.done = true;
+            j.off.clear();
+            j.off.shrink_to_fit();
+            j.col.clear();
+            j.col.shrink_to_fit();
+            j.w.clear();
+            j.w.shrink_to_fit();
+            s->pending -= 1;
+        }
+        if (rc != LOUVAIN_OK) s->err = msg;
+        s->reserved -= bytes;
+        s->inflight -= 1;
+    }
+    s->cv.notify_all();
+}
+
+void reap(S *s)
+{
+    // join worker threads that finished (called with the lock held; a finished
+    // worker has already released the lock for good)
+    for (auto it = s->workers.begin(); it != s->workers.end();) {
+        if (it->finished->load()) {
+            it->thread.join();
+            it = s->workers.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+void schedule(S *s)
+{
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        s->cv.wait(lk, [&] {
+            return s->stop || (!s->queue.empty() && s->inflight < s->cfg.max_inflight_batches);
+        });
+        reap(s);
+        if (s->queue.empty()) {
+            if (s->stop) break;
+            continue;
+        }
+        // admit from the queue head while the budget allows
+        std::vector<std::shared_ptr<Job>> batch;
+        uint64_t bytes = 0;
+        int64_t verts = 0;
+        while (!s->queue.empty() && (int64_t)batch.size() < s->cfg.max_batch_graphs) {
+            auto &j = s->queue.front();
+            if (j->bytes > s->cfg.hbm_budget_bytes) { // can never fit: fail it
+                j->status = LOUVAIN_E_OOM;
+                j->done = true;
+                j->t_done = s->now();
+                s->pending -= 1;
+                s->queue.pop_front();
+                s->cv.notify_all();
+                continue;
+            }
+            if (s->reserved + bytes + j->bytes > s->cfg.hbm_budget_bytes) break;
+            if (!batch.empty() && s->cfg.max_batch_vertices > 0 && verts + j->n > s->cfg.max_batch_vertices) break;
+            bytes += j->bytes;
+            verts += j->n;
+            j->t_admit = s->now();
+            batch.push_back(j);
+            s->queue.pop_front();
+        }
+        if (batch.empty()) {
+            // the head needs memory still held by running batches: wait for one to finish
+            if (s->queue.empty()) continue;
+            const int running = s->inflight;
+            s->cv.wait(lk, [&] { return s->stop || s->inflight < running; });
+            continue;
+        }
+        s->reserved += bytes;
+        s->inflight += 1;
+        const int64_t id = s->next_batch++;
+        Worker w;
+        w.finished = std::make_shared<std::atomic<bool>>(false);
+        auto flag = w.finished;
+        w.thread = std::thread([s, b = std::move(batch), id, bytes, flag]() mutable {
+            run_batch(s, std::move(b), id, bytes);
+            flag->store(true);
+            s->cv.notify_all();
+        });
+        s->workers.push_back(std::move(w));
+    }
+    reap(s);
+}
+
+} // namespace
+
+extern "C" {
+
+void louvain_server_config_default(louvain_server_config *c)
+{
+    if (!c) return;
+    std::memset(c, 0, sizeof(*c));
+    c->hbm_budget_bytes = 200ull << 30;
+    c->max_inflight_batches = 4;
+    c->max_batch_graphs = 4096;
+    c->max_batch_vertices = 0;
+}
+
+louvain_status louvain_server_create(const louvain_server_config *cfg, const louvain_params *params,
+                                     louvain_server_t *out)
+{
+    if (!out || !params) return LOUVAIN_E_INVALID_ARG;
+    *out = nullptr;
+    if (params->color) return LOUVAIN_E_INVALID_ARG;
+    S *s = new S();
+    if (cfg) s->cfg = *cfg;
+    else louvain_server_config_default(&s->cfg);
+    if (s->cfg.max_inflight_batches < 1 || s->cfg.max_batch_graphs < 1 || s->cfg.hbm_budget_bytes == 0) {
+        delete s;
+        return LOUVAIN_E_INVALID_ARG;
+    }
+    s->params = *params;
+    if (hipGetDevice(&s->dev) != hipSuccess) {
+        delete s;
+        return LOUVAIN_E_HIP;
+    }
+    s->t0 = std::chrono::steady_clock::now();
+    s->scheduler = std::thread(schedule, s);
+    *out = s;
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_server_submit(louvain_server_t s, int64_t n, int64_t nnz, const int64_t *offsets,
+                                     const int32_t *cols, const int32_t *weights, uint64_t *ticket)
+{
+    if (!s || !ticket || n < 0 || nnz < 0 || !offsets || (nnz > 0 && !cols)) return LOUVAIN_E_INVALID_ARG;
+    if (offsets[0] != 0 || offsets[n] != nnz) return LOUVAIN_E_BAD_CSR;
+    for (int64_t x = 0; x < nnz; ++x)
+        if (cols[x] < 0 || cols[x] >= n) return LOUVAIN_E_BAD_CSR;
+    auto j = std::make_shared<Job>();
+    j->n = n;
+    j->nnz = nnz;
+    j->off.assign(offsets, offsets + n + 1);
+    j->col.assign(cols, cols + nnz);
+    if (weights) {
+        j->w.assign(weights, weights + nnz);
+        j->weighted = true;
+    }
+    j->bytes = job_bytes(n, nnz);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        j->ticket = s->next_ticket++;
+        j->t_submit = s->now();
+        s->jobs[j->ticket] = j;
+        s->queue.push_back(j);
+        s->pending += 1;
+        *ticket = j->ticket;
+    }
+    s->cv.notify_all();
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_server_poll(louvain_server_t s, uint64_t ticket, int32_t *labels_out, louvain_job_result *out,
+                                   int32_t *done)
+{
+    if (!s || !done) return LOUVAIN_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) return LOUVAIN_E_INVALID_ARG;
+    Job &j = *it->second;
+    *done = j.done ? 1 : 0;
+    if (!j.done) return LOUVAIN_OK;
+    if (out) {
+        std::memset(out, 0, sizeof(*out));
+        out->result = j.res;
+        out->status = j.status;
+        out->t_submit = j.t_submit;
+        out->t_admit = j.t_admit;
+        out->t_done = j.t_done;
+        out->batch_id = j.batch_id;
+        out->batch_graphs = j.batch_graphs;
+    }
+    if (labels_out && j.status == LOUVAIN_OK && !j.labels.empty())
+        std::memcpy(labels_out, j.labels.data(), j.labels.size() * sizeof(int32_t));
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_server_release(louvain_server_t s, uint64_t ticket)
+{
+    if (!s) return LOUVAIN_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end() || !it->second->done) return LOUVAIN_E_INVALID_ARG;
+    s->jobs.erase(it);
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_server_wait_all(louvain_server_t s)
+{
+    if (!s) return LOUVAIN_E_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv.wait(lk, [&] { return s->pending == 0; });
+    return s->err.empty() ? LOUVAIN_OK : LOUVAIN_E_HIP;
+}
+
+const char *louvain_server_last_error(louvain_server_t s) { return s ? s->err.c_str() : ""; }
+
+void louvain_server_destroy(louvain_server_t s)
+{
+    if (!s) return;
+    louvain_server_wait_all(s);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv.notify_all();
+    if (s->scheduler.joinable()) s->scheduler.join();
+    for (auto &w : s->workers)
+        if (w.thread.joinable()) w.thread.join();
+    delete s;
+}
+
+} // extern "C"

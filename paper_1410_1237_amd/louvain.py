@@ -77,13 +77,26 @@ class GraphResult(ctypes.Structure):
                 ("q0_num", I128), ("q", ctypes.c_double), ("n_vf", ctypes.c_int64)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_inflight_batches", ctypes.c_int32),
+                ("max_batch_graphs", ctypes.c_int32), ("max_batch_vertices", ctypes.c_int64)]
+
+
+class JobResult(ctypes.Structure):
+    _fields_ = [("result", GraphResult), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("batch_id", ctypes.c_int64), ("batch_graphs", ctypes.c_int64)]
+
+
 _lib = None
 
 EXPORTS = ["louvain_params_default", "louvain_init_csr", "louvain_vf", "louvain_color", "louvain_sweep",
            "louvain_coarsen", "louvain_run", "louvain_destroy", "louvain_last_error", "louvain_get_info",
            "louvain_get_state", "louvain_get_graph", "louvain_get_colors", "louvain_get_map", "louvain_profile",
            "louvain_profile_get", "louvain_batch_init", "louvain_batch_run", "louvain_batch_graph_stats",
-           "louvain_batch_destroy", "louvain_batch_last_error"]
+           "louvain_batch_destroy", "louvain_batch_last_error", "louvain_server_config_default",
+           "louvain_server_create", "louvain_server_submit", "louvain_server_poll", "louvain_server_release",
+           "louvain_server_wait_all", "louvain_server_last_error", "louvain_server_destroy"]
 
 
 def lib():
@@ -142,6 +155,22 @@ def lib():
     L.louvain_batch_destroy.restype = None
     L.louvain_batch_last_error.argtypes = [vp]
     L.louvain_batch_last_error.restype = ctypes.c_char_p
+    L.louvain_server_config_default.argtypes = [ctypes.POINTER(ServerConfig)]
+    L.louvain_server_config_default.restype = None
+    L.louvain_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(Params), ctypes.POINTER(vp)]
+    L.louvain_server_create.restype = st
+    L.louvain_server_submit.argtypes = [vp, i64, i64, vp, vp, vp, ctypes.POINTER(u64)]
+    L.louvain_server_submit.restype = st
+    L.louvain_server_poll.argtypes = [vp, u64, vp, ctypes.POINTER(JobResult), ctypes.POINTER(i32)]
+    L.louvain_server_poll.restype = st
+    L.louvain_server_release.argtypes = [vp, u64]
+    L.louvain_server_release.restype = st
+    L.louvain_server_wait_all.argtypes = [vp]
+    L.louvain_server_wait_all.restype = st
+    L.louvain_server_last_error.argtypes = [vp]
+    L.louvain_server_last_error.restype = ctypes.c_char_p
+    L.louvain_server_destroy.argtypes = [vp]
+    L.louvain_server_destroy.restype = None
     _lib = L
     return L
 
@@ -517,3 +546,108 @@ class Batch:
                                      n_vf=r.n_vf, N0=r.q0_num.value(), sweep_entries=0, ms_total=0.0, ms_vf=0.0,
                                      ms_color=0.0, ms_sweep=0.0, ms_coarsen=0.0, phases=phases))
         return results
+
+
+@dataclass
+class JobInfo:
+    """Outcome of one served job."""
+    ticket: int
+    status: int
+    labels: Optional[np.ndarray]
+    K: int
+    N: int
+    D: int
+    q: float
+    n_vf: int
+    phases: int
+    iterations: int
+    t_submit: float
+    t_admit: float
+    t_done: float
+    batch_id: int
+    batch_graphs: int
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_submit
+
+
+def louvain_server_config_default() -> ServerConfig:
+    c = ServerConfig()
+    lib().louvain_server_config_default(ctypes.byref(c))
+    return c
+
+
+class Server:
+    """The served form: submit host CSRs, poll for results (continuous
+    batching under an HBM budget, batches overlapping on their own streams)."""
+
+    def __init__(self, p: Optional[Params] = None, hbm_budget_bytes: Optional[int] = None,
+                 max_inflight_batches: Optional[int] = None, max_batch_graphs: Optional[int] = None,
+                 max_batch_vertices: Optional[int] = None, **kw):
+        cfg = louvain_server_config_default()
+        if hbm_budget_bytes is not None:
+            cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        if max_inflight_batches is not None:
+            cfg.max_inflight_batches = int(max_inflight_batches)
+        if max_batch_graphs is not None:
+            cfg.max_batch_graphs = int(max_batch_graphs)
+        if max_batch_vertices is not None:
+            cfg.max_batch_vertices = int(max_batch_vertices)
+        self.p = p or params(**kw)
+        h = ctypes.c_void_p()
+        st = lib().louvain_server_create(ctypes.byref(cfg), ctypes.byref(self.p), ctypes.byref(h))
+        if st != OK:
+            raise LouvainError(st, "louvain_server_create rejected its arguments")
+        self.h = h.value
+        self.sizes = {}
+
+    def submit(self, g) -> int:
+        off = np.ascontiguousarray(g.offsets, dtype=np.int64)
+        col = np.ascontiguousarray(g.cols, dtype=np.int32)
+        w = None if g.weights is None else np.ascontiguousarray(g.weights, dtype=np.int32)
+        t = ctypes.c_uint64()
+        st = lib().louvain_server_submit(self.h, int(g.n), int(col.size), off.ctypes.data,
+                                         col.ctypes.data if col.size else None,
+                                         None if w is None else w.ctypes.data, ctypes.byref(t))
+        if st != OK:
+            raise LouvainError(st, "louvain_server_submit rejected the graph")
+        self.sizes[t.value] = int(g.n)
+        return t.value
+
+    def poll(self, ticket: int, labels: bool = True) -> Optional[JobInfo]:
+        n = self.sizes.get(ticket, 0)
+        out = np.zeros(max(n, 1), dtype=np.int32) if labels else None
+        r = JobResult()
+        done = ctypes.c_int32()
+        st = lib().louvain_server_poll(self.h, ticket, None if out is None else out.ctypes.data, ctypes.byref(r),
+                                       ctypes.byref(done))
+        if st != OK:
+            raise LouvainError(st, "unknown ticket")
+        if not done.value:
+            return None
+        g = r.result
+        return JobInfo(ticket=ticket, status=r.status, labels=None if out is None else out[:n],
+                       K=g.num_communities, N=g.q_num.value(), D=g.q_den.value(), q=g.q, n_vf=g.n_vf,
+                       phases=g.phases, iterations=g.iterations, t_submit=r.t_submit, t_admit=r.t_admit,
+                       t_done=r.t_done, batch_id=r.batch_id, batch_graphs=r.batch_graphs)
+
+    def release(self, ticket: int):
+        _ = lib().louvain_server_release(self.h, ticket)
+        self.sizes.pop(ticket, None)
+
+    def wait_all(self):
+        st = lib().louvain_server_wait_all(self.h)
+        if st != OK:
+            raise LouvainError(st, lib().louvain_server_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().louvain_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
