@@ -222,11 +222,11 @@ struct louvain_graph_s {
     bool bins_valid = false;
     bool bins_colored = false;
     int64_t *bin_offd = nullptr;  // device copy of bin_off (capacity bin_hist_cap + 1)
-    int64_t *hoff = nullptr, *cpre = nullptr, *htmp = nullptr;
-    int32_t *hkey = nullptr;
-    uint64_t *hval = nullptr;
-    int64_t *hpart = nullptr, *haux = nullptr;
-    int64_t hcap = 0;                       // table slots allocated
+    int64_t *cpre = nullptr, *bpre = nullptr, *xpre = nullptr; // hub prefixes per bin-list position
+    int32_t *pkey = nullptr, *boff = nullptr;
+    uint64_t *pval = nullptr;
+    int64_t *hpart = nullptr;
+    int64_t pcap = 0, xcap = 0, qcap = 0;   // pairs, bucket boundaries, buckets allocated
     std::vector<lv::HubArgs> hub_groups;    // per group (e <= s when the group has no hub)
 
     // coarsening
@@ -318,9 +318,9 @@ louvain_status sync(G *g)
 }
 
 // ---- profiling ----------------------------------------------------------------
-const char *kNames[] = {"sweep_small_bins1to5", "sweep_large_bins6to9_hub_insert", "sweep_all_bins_small_group",
-                        "sweep_hub_scan_decide", "commit", "coarsen", "color"};
-enum { PR_SMALL = 0, PR_LARGE = 1, PR_ALL = 2, PR_HUB_SCAN = 3, PR_COMMIT = 4, PR_COARSEN = 5, PR_COLOR = 6,
+const char *kNames[] = {"sweep_small_bins1to5", "sweep_large_bins6to8_hub_partition", "sweep_all_bins_small_group",
+                        "sweep_hub_aggregate_decide", "commit", "coarsen", "color"};
+enum { PR_SMALL = 0, PR_LARGE = 1, PR_ALL = 2, PR_HUB_AGG = 3, PR_COMMIT = 4, PR_COARSEN = 5, PR_COLOR = 6,
        PR_COUNT = 7 };
 constexpr double SMALL_GROUP = 65536; // vertices: one fused launch below this
 
@@ -376,13 +376,20 @@ void prof_collect(G *g, const lv::SweepStats *host_stats, int wb)
             // per vertex: list entry 4, offsets 16, comm 4, k 8, a[A] 8, sizes 8, comm_next 4
             // per entry: column 4 + weight wb + comm of the neighbour 4; per distinct community: a 8
             // (a slot sums all launches of its bin since the last read: counted once)
+            // hub rows: the entries are gathered by the pass-1 blocks of the
+            // large (or all-bins) launch, the distinct pairs read by pass 2
             r.bytes += 52.0 * p.bytes;
+            const bool hub_pass2 = p.rec == PR_HUB_AGG;
             for (int b = 0; b < lv::NBINS; ++b) {
                 if (!((p.stat_slot >> b) & 1) || slot_done[b]) continue;
                 const lv::SweepStats &s = host_stats[b];
-                r.bytes += (8.0 + wb) * (double)s.entries + 8.0 * (double)s.pairs;
-                r.entries += (double)s.entries;
-                slot_done[b] = true;
+                const bool hub = b >= 9;
+                if (!hub || !hub_pass2) {
+                    r.bytes += (8.0 + wb) * (double)s.entries;
+                    r.entries += (double)s.entries;
+                }
+                if (!hub || hub_pass2) r.bytes += 8.0 * (double)s.pairs;
+                if (!hub || hub_pass2) slot_done[b] = true;
             }
         } else {
             r.bytes += p.bytes;
@@ -452,19 +459,21 @@ louvain_status build_bins(G *g, bool by_color)
                    g->st);
     lv::narrow_ids(g->vals, g->bin_verts, n, g->st);
     lv::key_offsets(g->keys, n, nkeys, g->bin_offd, g->st);
-    lv::hub_prefix(g->cur, g->bin_verts, n, g->hoff, g->cpre, g->htmp, g->scratch, g->st);
+    lv::hub_prefix(g->cur, g->bin_verts, n, g->cpre, g->bpre, g->xpre, g->scratch, g->st);
     g->bin_off.assign(nkeys + 1, 0);
     HIPCHK(g, hipMemcpyAsync(g->bin_off.data(), g->bin_offd, (nkeys + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
                              g->st));
-    int64_t total_slots = 0;
-    HIPCHK(g, hipMemcpyAsync(&total_slots, g->hoff + n, sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
+    int64_t tot[3] = {0, 0, 0}; // chunks, buckets, bucket boundaries
+    HIPCHK(g, hipMemcpyAsync(&tot[0], g->cpre + n, sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
+    HIPCHK(g, hipMemcpyAsync(&tot[1], g->bpre + n, sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
+    HIPCHK(g, hipMemcpyAsync(&tot[2], g->xpre + n, sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
     louvain_status s = sync(g);
     if (s) return s;
-    // hub position ranges per group, and their table/chunk prefixes
+    // hub position ranges (bins 9 and 10) per group
     std::vector<int64_t> idx;
     std::vector<int> with_hubs;
     for (int grp = 0; grp < groups; ++grp) {
-        const int64_t hs = g->bin_off[grp * 16 + 10], he = g->bin_off[grp * 16 + 11];
+        const int64_t hs = g->bin_off[grp * 16 + 9], he = g->bin_off[grp * 16 + 11];
         if (he > hs) {
             with_hubs.push_back(grp);
             idx.push_back(hs);
@@ -472,31 +481,33 @@ louvain_status build_bins(G *g, bool by_color)
         }
     }
     g->hub_groups.assign(groups, lv::HubArgs{});
-    for (auto &h : g->hub_groups) h.s = h.e = 0;
-    if (total_slots > g->hcap) {
-        {
-            release_buffer(g, g->hkey);
-            release_buffer(g, g->hval);
-            release_buffer(g, g->hpart);
-            release_buffer(g, g->haux);
-            const int64_t cap = ((total_slots + total_slots / 4) / lv::HUB_SLICE + 1) * lv::HUB_SLICE;
-            const int64_t slices = cap / lv::HUB_SLICE;
-            if ((s = alloc(g, &g->hkey, cap)) || (s = alloc(g, &g->hval, cap)) || (s = alloc(g, &g->hpart, 4 * slices)) ||
-                (s = alloc(g, &g->haux, 8 * slices)))
-                return s;
-            g->hcap = cap;
-            lv::fill<int32_t>(g->hkey, -1, cap, g->st);
-            lv::fill<uint64_t>(g->hval, 0, cap, g->st);
-            lv::fill<int64_t>(g->haux, 0, 8 * slices, g->st);
-        }
+    const int64_t pairs = tot[0] * lv::HUB_CHUNK;
+    if (pairs > g->pcap) {
+        release_buffer(g, g->pkey);
+        release_buffer(g, g->pval);
+        const int64_t cap = pairs + pairs / 4 + lv::HUB_CHUNK;
+        if ((s = alloc(g, &g->pkey, cap)) || (s = alloc(g, &g->pval, cap))) return s;
+        g->pcap = cap;
+    }
+    if (tot[2] > g->xcap) {
+        release_buffer(g, g->boff);
+        const int64_t cap = tot[2] + tot[2] / 4 + 1024;
+        if ((s = alloc(g, &g->boff, cap))) return s;
+        g->xcap = cap;
+    }
+    if (tot[1] > g->qcap) {
+        release_buffer(g, g->hpart);
+        const int64_t cap = tot[1] + tot[1] / 4 + 64;
+        if ((s = alloc(g, &g->hpart, lv::HUB_REC * cap))) return s;
+        g->qcap = cap;
     }
     if (!with_hubs.empty()) {
         const int64_t m = (int64_t)idx.size();
-        // gather hoff and cpre at the range ends: device scratch in vals_alt (free here)
+        // gather cpre and bpre at the range ends: device scratch in vals_alt (free here)
         int64_t *didx = g->vals_alt, *dout = g->vals_alt + m;
         HIPCHK(g, hipMemcpyAsync(didx, idx.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, g->st));
-        lv::gather_i64(g->hoff, didx, m, dout, g->st);
-        lv::gather_i64(g->cpre, didx, m, dout + m, g->st);
+        lv::gather_i64(g->cpre, didx, m, dout, g->st);
+        lv::gather_i64(g->bpre, didx, m, dout + m, g->st);
         std::vector<int64_t> vals(2 * m);
         HIPCHK(g, hipMemcpyAsync(vals.data(), dout, 2 * m * sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
         if ((s = sync(g))) return s;
@@ -505,16 +516,17 @@ louvain_status build_bins(G *g, bool by_color)
             h.verts = g->bin_verts;
             h.s = idx[2 * t];
             h.e = idx[2 * t + 1];
-            h.hoff = g->hoff;
             h.cpre = g->cpre;
-            h.chunk0 = vals[m + 2 * t];
-            h.n_insert = vals[m + 2 * t + 1] - h.chunk0;
-            h.slice0 = vals[2 * t] / lv::HUB_SLICE;
-            h.n_scan = vals[2 * t + 1] / lv::HUB_SLICE - h.slice0;
-            h.hkey = g->hkey;
-            h.hval = g->hval;
+            h.bpre = g->bpre;
+            h.xpre = g->xpre;
+            h.chunk0 = vals[2 * t];
+            h.n_chunks = vals[2 * t + 1] - h.chunk0;
+            h.bucket0 = vals[m + 2 * t];
+            h.n_buckets = vals[m + 2 * t + 1] - h.bucket0;
+            h.pkey = g->pkey;
+            h.pval = g->pval;
+            h.boff = g->boff;
             h.part = g->hpart;
-            h.aux = g->haux;
         }
     }
     g->bin_groups = groups;
@@ -541,37 +553,35 @@ void sweep_group(G *g, int group, int singlet)
     a.gstats = g->b_gstats;
     a.verts = nullptr;
     a.count = 0;
-    a.stats = g->stats + 10;
+    a.stats = g->stats + 10 * lv::STAT_REP;
     const bool wide = wide_gains(g);
+    const bool narrow = g->kmax <= (int64_t)UINT32_MAX; // hub sums e <= k_i fit 32 bits
     lv::FusedBins f;
     double cnt_small = 0, cnt_large = 0;
-    for (int b = 1; b <= 9; ++b) {
+    for (int b = 1; b <= 8; ++b) {
         const int64_t s = g->bin_off[group * 16 + b], e = g->bin_off[group * 16 + b + 1];
         f.bins[b].verts = g->bin_verts + s;
         f.bins[b].count = e - s;
-        f.bins[b].stats = g->stats + b;
+        f.bins[b].stats = g->stats + b * lv::STAT_REP;
         (b <= 5 ? cnt_small : cnt_large) += (double)(e - s);
-        if (b == 9) f.hoff9 = g->hoff + s;
     }
-    f.hkey = g->hkey;
-    f.hval = g->hval;
     const lv::HubArgs &h = g->hub_groups[group];
     const double nhub = (double)(h.e > h.s ? h.e - h.s : 0);
     if (cnt_small + cnt_large + nhub <= SMALL_GROUP) {
         // small group (typical late colour class): one launch for every bin
-        ProfScope ps(g, PR_ALL, cnt_small + cnt_large + nhub, 0, 0x7fe);
-        lv::sweep_all(a, f, h, wide, g->st);
+        ProfScope ps(g, PR_ALL, cnt_small + cnt_large, 0, 0x7fe);
+        lv::sweep_all(a, f, h, wide, narrow, g->st);
     } else {
         {
             ProfScope ps(g, PR_SMALL, cnt_small, 0, 0x3e);
             lv::sweep_small(a, f, wide, g->st);
         }
-        ProfScope ps(g, PR_LARGE, cnt_large + nhub, 0, 0x7c0);
-        lv::sweep_large(a, f, h, wide, g->st);
+        ProfScope ps(g, PR_LARGE, cnt_large, 0, 0x7c0);
+        lv::sweep_large(a, f, h, wide, narrow, g->st);
     }
     if (h.e > h.s) {
-        ProfScope ps(g, PR_HUB_SCAN, 0, 0);
-        lv::sweep_hub_scan(a, h, wide, g->st);
+        ProfScope ps(g, PR_HUB_AGG, nhub, 0, 0x600);
+        lv::sweep_hub_agg(a, h, wide, narrow, g->st);
     }
 }
 
@@ -582,9 +592,22 @@ struct SweepSum {
 
 louvain_status read_stats(G *g, SweepSum &out, lv::SweepStats *host)
 {
-    HIPCHK(g, hipMemcpyAsync(host, g->stats, lv::NBINS * sizeof(lv::SweepStats), hipMemcpyDeviceToHost, g->st));
+    std::vector<lv::SweepStats> rep(lv::NBINS * lv::STAT_REP);
+    HIPCHK(g, hipMemcpyAsync(rep.data(), g->stats, rep.size() * sizeof(lv::SweepStats), hipMemcpyDeviceToHost,
+                             g->st));
     louvain_status s = sync(g);
     if (s) return s;
+    for (int b = 0; b < lv::NBINS; ++b) {
+        host[b] = lv::SweepStats{};
+        for (int r = 0; r < lv::STAT_REP; ++r) {
+            const lv::SweepStats &x = rep[b * lv::STAT_REP + r];
+            host[b].moves += x.moves;
+            host[b].sigma_prev += x.sigma_prev;
+            host[b].dsigma += x.dsigma;
+            host[b].pairs += x.pairs;
+            host[b].entries += x.entries;
+        }
+    }
     out = SweepSum();
     for (int b = 0; b < lv::NBINS; ++b) {
         out.moves += host[b].moves;
@@ -623,7 +646,7 @@ louvain_status commit_all(G *g)
 // state after the classes before it (Sec. 5.4 step 3)
 louvain_status colored_iteration(G *g, int singlet, SweepSum &sum, lv::SweepStats *host)
 {
-    lv::clear_stats(g->stats, lv::NBINS, g->st);
+    lv::clear_stats(g->stats, lv::NBINS * lv::STAT_REP, g->st);
     for (int c = 0; c < g->num_colors; ++c) {
         sweep_group(g, c, singlet);
         const int64_t s = g->bin_off[c * 16], e = g->bin_off[c * 16 + 16];
@@ -732,7 +755,7 @@ louvain_status run_phase_plain(G *g, const louvain_params *p, louvain_ratio th, 
     const i128 D = (i128)g->two_m * g->two_m;
     int t_end = 0;
     for (int s_idx = 1;; ++s_idx) {
-        lv::clear_stats(g->stats, lv::NBINS, g->st);
+        lv::clear_stats(g->stats, lv::NBINS * lv::STAT_REP, g->st);
         sweep_group(g, 0, p->singlet_rule);
         SweepSum sum;
         if ((s = read_stats(g, sum, host))) return s;
@@ -889,9 +912,9 @@ louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, 
         (s = alloc(g, &g->color, n)) || (s = alloc(g, &g->jp_cnt, 5 * n)) || (s = alloc(g, &g->front_a, n)) ||
         (s = alloc(g, &g->front_b, n)) || (s = alloc(g, &g->counters, 16)) || (s = alloc(g, &g->keys, big)) ||
         (s = alloc(g, &g->keys_alt, big)) || (s = alloc(g, &g->vals, big)) || (s = alloc(g, &g->vals_alt, big)) ||
-        (s = alloc(g, &g->run, big)) || (s = alloc(g, &g->bin_verts, n)) || (s = alloc(g, &g->hoff, n + 1)) ||
-        (s = alloc(g, &g->cpre, n + 1)) || (s = alloc(g, &g->htmp, n + 1)) || (s = alloc(g, &g->flag, n + 1)) || (s = alloc(g, &g->new_id, n + 1)) ||
-        (s = alloc(g, &g->stats, lv::NBINS)) || (s = alloc(g, &g->dscal, 16)) || (s = alloc(g, &g->vflag, 4)))
+        (s = alloc(g, &g->run, big)) || (s = alloc(g, &g->bin_verts, n)) || (s = alloc(g, &g->cpre, n + 1)) ||
+        (s = alloc(g, &g->bpre, n + 1)) || (s = alloc(g, &g->xpre, n + 1)) || (s = alloc(g, &g->flag, n + 1)) || (s = alloc(g, &g->new_id, n + 1)) ||
+        (s = alloc(g, &g->stats, lv::NBINS * lv::STAT_REP)) || (s = alloc(g, &g->dscal, 16)) || (s = alloc(g, &g->vflag, 4)))
         return bail(s);
     g->bin_hist_cap = 16 * 64;
     if ((s = alloc(g, &g->bin_hist, g->bin_hist_cap)) || (s = alloc(g, &g->bin_offd, g->bin_hist_cap + 1)))
@@ -1006,7 +1029,7 @@ louvain_status louvain_sweep(louvain_graph_t g, const louvain_params *p, louvain
     if (colored) {
         if ((s = colored_iteration(g, p->singlet_rule, sum, host))) return s;
     } else {
-        lv::clear_stats(g->stats, lv::NBINS, g->st);
+        lv::clear_stats(g->stats, lv::NBINS * lv::STAT_REP, g->st);
         sweep_group(g, 0, p->singlet_rule);
         if ((s = read_stats(g, sum, host))) return s;
         prof_collect(g, host, wbytes(g->cur));

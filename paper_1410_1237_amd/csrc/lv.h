@@ -170,11 +170,11 @@ void weights_i64(const Csr &g, int64_t *w_out, hipStream_t st);
 
 // ---- sweep (sweep.hip) -----------------------------------------------------
 
-// degree bins: 0 isolated, 1..8 LDS tables (rows up to 2048 entries), 9 mid
-// hubs (one workgroup, HBM table, rows up to MID_HUB_MAX), 10 giant hubs
-// (split across workgroups)
+// degree bins: 0 isolated, 1..8 LDS tables (rows up to 2048 entries), 9 and
+// 10 hubs (rows above 2048 entries, split across workgroups; bin 9 holds
+// rows up to HUB_BIN9_MAX entries, kept apart for the statistics only)
 constexpr int NBINS = 11;
-constexpr int64_t MID_HUB_MAX = 4096;
+constexpr int64_t HUB_BIN9_MAX = 4096;
 __host__ __device__ inline int degree_bin(int64_t d)
 {
     if (d == 0) return 0;
@@ -186,11 +186,14 @@ __host__ __device__ inline int degree_bin(int64_t d)
     if (d <= 256) return 6;
     if (d <= 1024) return 7;
     if (d <= 2048) return 8;
-    if (d <= MID_HUB_MAX) return 9;
+    if (d <= HUB_BIN9_MAX) return 9;
     return 10;
 }
 
-// device accumulators of one sweep launch group
+// device accumulators of one sweep launch group; every bin has STAT_REP
+// replicas (a block adds to replica blockIdx % STAT_REP) so that the blocks of
+// a launch do not all update the same five words; the host sums them
+constexpr int STAT_REP = 64;
 struct SweepStats {
     int64_t moves;
     int64_t sigma_prev;  // sum over swept vertices of e_{i->C(i)} + w_ii (state read)
@@ -221,24 +224,36 @@ struct SweepArgs {
     int64_t *gstats = nullptr;
 };
 
-// hub rows (bins 9, 10) use HBM tables of pow2_ceil(2 d) slots; giant hubs
-// (bin 10) are split in HUB_CHUNK-entry chunks for insertion and their tables
-// in HUB_SLICE-slot slices for the scan
+// Hub rows (bins 9, 10) run in two passes.  Pass 1: one workgroup per
+// HUB_CHUNK-entry chunk sums the chunk per community and writes the distinct
+// (community, weight) pairs to the chunk's region of pkey/pval, grouped by
+// the community's hash bucket (a hub has P = 2^k buckets, about one per
+// HUB_BUCKET entries, at most HUB_PMAX), with the P + 1 bucket boundaries in
+// boff.  Pass 2: one workgroup per (hub, bucket) sums the bucket's segments of
+// every chunk, evaluates the gains and leaves the bucket's best; the last
+// bucket of a hub decides.  Per-position prefixes over the sorted vertex
+// list: cpre (chunks), bpre (buckets), xpre (boundary entries).
 constexpr int HUB_CHUNK = 2048;
-constexpr int HUB_SLICE = 4096;
+constexpr int64_t HUB_BUCKET = 2048;
+constexpr int HUB_PMAX = 1024;
+__host__ __device__ inline int hub_buckets(int64_t d)
+{
+    const int64_t p = pow2_ceil((d + HUB_BUCKET - 1) / HUB_BUCKET);
+    return (int)(p < HUB_PMAX ? p : HUB_PMAX);
+}
 struct HubArgs {
-    const int32_t *verts;    // sorted vertex list (positions are absolute)
-    int64_t s, e;            // hub positions [s, e) of this launch group
-    const int64_t *hoff;     // prefix of table slots per position (n+1)
-    const int64_t *cpre;     // prefix of row chunks per position (n+1)
-    int64_t chunk0, n_insert; // cpre[s], cpre[e] - cpre[s]
-    int64_t slice0, n_scan;   // hoff[s] / HUB_SLICE, (hoff[e] - hoff[s]) / HUB_SLICE
-    int32_t *hkey;           // tables: key -1 = empty
-    uint64_t *hval;
-    int64_t *part;           // per slice: best gain (lo, hi), community, e
-    int64_t *aux;            // 8 per slice (used at a hub's first slice): w_self, entries, e_A,
-                             // distinct, slices done
+    const int32_t *verts = nullptr; // sorted vertex list (positions are absolute)
+    int64_t s = 0, e = 0;           // hub positions [s, e) of this launch group
+    const int64_t *cpre = nullptr, *bpre = nullptr, *xpre = nullptr; // n + 1 each
+    int64_t chunk0 = 0, n_chunks = 0;   // cpre[s], cpre[e] - cpre[s]
+    int64_t bucket0 = 0, n_buckets = 0; // bpre[s], bpre[e] - bpre[s]
+    int32_t *pkey = nullptr;        // HUB_CHUNK pairs per chunk
+    void *pval = nullptr;           // uint32 or uint64 per pair (the launch's value width)
+    int32_t *boff = nullptr;        // bucket boundaries, P + 1 per chunk
+    int64_t *part = nullptr;        // HUB_REC per bucket: best gain (lo, hi), community, e,
+                                    // e_A, distinct communities
 };
+constexpr int HUB_REC = 8;
 
 // vertices of one degree bin for a fused launch
 struct BinRange {
@@ -248,30 +263,28 @@ struct BinRange {
     SweepStats *stats = nullptr;
 };
 struct FusedBins {
-    BinRange bins[10];        // index = bin (1..9 used)
-    const int64_t *hoff9 = nullptr; // table offsets of the bin-9 vertices (count + 1, absolute slots)
-    int32_t *hkey = nullptr;        // HBM tables (shared with the giant hubs)
-    uint64_t *hval = nullptr;
-    int64_t hub_block0 = 0;   // first giant-hub insert block of the large launch
+    BinRange bins[9];         // index = bin (1..8 used)
+    int64_t hub_block0 = 0;   // first hub pass-1 block of the launch
 };
 
-// Fused sweep launches (wide = 128-bit gains); each returns false when it had
-// nothing to launch.  small: bins 1..5; large: bins 6..9 plus the giant-hub
-// chunk inserts; then the giant-hub table scan and decisions (stats in a.stats).
+// Fused sweep launches (wide = 128-bit gains, narrow = hub sums fit 32
+// bits); each returns false when it had nothing to launch.  small: bins 1..5;
+// large: bins 6..8 plus hub pass 1; all: bins 1..8 plus hub pass 1 (small
+// groups); then hub pass 2 and, in a launch of its own, the hub decisions
+// (stats in a.stats).
 bool sweep_small(const SweepArgs &a, FusedBins f, bool wide, hipStream_t st);
-bool sweep_large(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, hipStream_t st);
-bool sweep_hub_scan(const SweepArgs &a, const HubArgs &h, bool wide, hipStream_t st);
-// small and large bins (and giant-hub inserts) in one launch with the large LDS size
-bool sweep_all(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, hipStream_t st);
+bool sweep_large(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, bool narrow, hipStream_t st);
+bool sweep_all(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, bool narrow, hipStream_t st);
+bool sweep_hub_agg(const SweepArgs &a, const HubArgs &h, bool wide, bool narrow, hipStream_t st);
 // per-vertex degree bin keys for sorting: key = (group << 4) | bin, val = vertex
 void bin_keys(const Csr &g, const int32_t *group, uint64_t *keys, int64_t *vals, hipStream_t st);
 // off[key] = first index of the sorted keys with key >= key, key in [0, nkeys]
 void key_offsets(const uint64_t *keys, int64_t n, int64_t nkeys, int64_t *off, hipStream_t st);
 // vertex ids from sorted bin values (int64 -> int32)
 void narrow_ids(const int64_t *vals, int32_t *out, int64_t n, hipStream_t st);
-// per position of verts: hoff = prefix of hub table slots, cpre = prefix of hub
-// row chunks (both n+1; tmp needs n+1 entries)
-void hub_prefix(const Csr &g, const int32_t *verts, int64_t count, int64_t *hoff, int64_t *cpre, int64_t *tmp,
+// per position of verts: cpre, bpre, xpre = prefixes of hub chunks, buckets
+// and bucket-boundary entries (n + 1 each; the totals land at index count)
+void hub_prefix(const Csr &g, const int32_t *verts, int64_t count, int64_t *cpre, int64_t *bpre, int64_t *xpre,
                 Scratch &s, hipStream_t st);
 void gather_i64(const int64_t *src, const int64_t *idx, int64_t n, int64_t *out, hipStream_t st);
 // community degree/size updates for movers in the list (or all vertices if verts == null)

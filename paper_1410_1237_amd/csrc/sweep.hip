@@ -229,17 +229,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const BinRange &b
     __syncthreads();
     if (threadIdx.x < 5) {
         const unsigned long long v = bstat[threadIdx.x];
-        if (v) atomicAdd((unsigned long long *)&br.stats->moves + threadIdx.x, v);
+        if (v) atomicAdd((unsigned long long *)&br.stats[blockIdx.x % STAT_REP].moves + threadIdx.x, v);
     }
 }
 
 // hubs: rows longer than 2048 entries -----------------------------------------
-// (1) insert: each block pre-aggregates a 2048-entry chunk of one hub row in an
-// LDS table, then adds its distinct communities to the hub's HBM table;
-// (2) scan: each block reads a 4096-slot slice of one hub table, leaves it
-// clean and keeps the slice's best (G, -c); (3) decide: one thread per hub
-// reduces its slices and applies the same rule as the other bins.
-constexpr int HUB_LDS = 2 * HUB_CHUNK;
+// Pass 1 (partition) and pass 2 (aggregate) keep every per-community sum in
+// LDS; HBM only carries the chunks' distinct pairs between the passes, so no
+// HBM location is updated by more than one workgroup.
+constexpr int HUB_T1 = 2 * HUB_CHUNK; // pass-1 table slots (2^12)
+constexpr int HUB_T2 = 4096;          // pass-2 table slots (2^12)
+constexpr int HUB_CAP2 = 3072;        // distinct keys one pass-2 round may hold
+constexpr int HUB_BLOCK2 = 512;
+constexpr int HUB_SEGS = 1024;        // chunk segments a pass-2 block stages at a time
 
 __device__ __forceinline__ int64_t last_leq(const int64_t *arr, int64_t lo, int64_t hi, int64_t x)
 {
@@ -251,259 +253,138 @@ __device__ __forceinline__ int64_t last_leq(const int64_t *arr, int64_t lo, int6
     return lo;
 }
 
-// Merges the occupied slots of a block's LDS table (HUB_LDS slots) into an
-// HBM table of S slots.  Each thread holds its PER slots in registers and
-// issues their compare-and-swaps together, so up to PER device-coherent
-// atomics per thread are in flight instead of one.
-constexpr int FLUSH_PER = HUB_LDS / BLOCK;
-
-__device__ __forceinline__ void flush_to_hbm(const int32_t *tkey, const unsigned long long *tval, int32_t *gkey,
-                                             unsigned long long *gval, int64_t S, int gshift)
+// bucket of community c among 2^lp (top bits of the Fibonacci hash)
+__device__ __forceinline__ int hub_bucket(int32_t c, int lp)
 {
-    int32_t kc[FLUSH_PER];
-    unsigned long long kv[FLUSH_PER];
-    uint32_t kq[FLUSH_PER];
-    uint32_t pend = 0;
-#pragma unroll
-    for (int j = 0; j < FLUSH_PER; ++j) {
-        const int s = threadIdx.x + j * BLOCK;
-        kc[j] = tkey[s];
-        kv[j] = tval[s];
-        kq[j] = kc[j] >= 0 ? slot_hash(kc[j], gshift) : 0;
-        if (kc[j] >= 0) pend |= 1u << j;
-    }
-    while (pend) {
-        int32_t old[FLUSH_PER];
-#pragma unroll
-        for (int j = 0; j < FLUSH_PER; ++j)
-            if ((pend >> j) & 1) old[j] = atomicCAS(&gkey[kq[j]], -1, kc[j]);
-#pragma unroll
-        for (int j = 0; j < FLUSH_PER; ++j) {
-            if (!((pend >> j) & 1)) continue;
-            if (old[j] == -1 || old[j] == kc[j]) {
-                atomicAdd(&gval[kq[j]], kv[j]);
-                pend &= ~(1u << j);
-            } else {
-                kq[j] = (kq[j] + 1) & (uint32_t)(S - 1);
-            }
-        }
-    }
+    return lp ? (int)(((uint32_t)c * 0x9E3779B1u) >> (32 - lp)) : 0;
 }
 
-// Reads (and clears) HBM table slots [base, base + count) with SCAN_PER
-// independent loads in flight per thread; calls f(community, weight) for
-// each occupied slot.
-constexpr int SCAN_PER = 16;
-
-template <class F>
-__device__ __forceinline__ void scan_hbm(int32_t *gkey, unsigned long long *gval, int64_t count, F f)
+// MurmurHash3 finalizer: pass-2 slots (top bits) and rounds (low bits),
+// independent of the bucket bits
+__device__ __forceinline__ uint32_t fmix32(uint32_t h)
 {
-    for (int64_t base = 0; base < count; base += (int64_t)BLOCK * SCAN_PER) {
-        int32_t c[SCAN_PER];
-#pragma unroll
-        for (int j = 0; j < SCAN_PER; ++j) {
-            const int64_t s = base + threadIdx.x + (int64_t)j * BLOCK;
-            c[j] = s < count ? __hip_atomic_load(&gkey[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
-        }
-        unsigned long long w[SCAN_PER];
-#pragma unroll
-        for (int j = 0; j < SCAN_PER; ++j) {
-            const int64_t s = base + threadIdx.x + (int64_t)j * BLOCK;
-            w[j] = c[j] >= 0 ? __hip_atomic_load(&gval[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
-        }
-#pragma unroll
-        for (int j = 0; j < SCAN_PER; ++j) {
-            if (c[j] < 0) continue;
-            const int64_t s = base + threadIdx.x + (int64_t)j * BLOCK;
-            gkey[s] = -1; // leave the table clean for the next sweep
-            gval[s] = 0;
-            f(c[j], (int64_t)w[j]);
-        }
-    }
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
 }
 
-template <int WK>
-__device__ __forceinline__ void hub_insert_tile(const SweepArgs &a, const HubArgs &h, int64_t tile, unsigned char *smem,
-                                                int64_t *red)
+// exclusive scan of x[0, len) in LDS by NT threads (len <= K * NT); x[len] = total
+template <int NT, int K> __device__ __forceinline__ void lds_exscan(int32_t *x, int len, int32_t *wsum)
 {
+    const int t = threadIdx.x;
+    int32_t v[K], s = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = K * t + k;
+        v[k] = i < len ? x[i] : 0;
+        s += v[k];
+    }
+    int32_t inc = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(inc, o, 64);
+        if ((t & 63) >= o) inc += y;
+    }
+    if ((t & 63) == 63) wsum[t >> 6] = inc;
+    __syncthreads();
+    int32_t run = inc - s, tot = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+        if (w < (t >> 6)) run += wsum[w];
+        tot += wsum[w];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = K * t + k;
+        if (i < len) x[i] = run;
+        run += v[k];
+    }
+    if (t == 0) x[len] = tot;
+    __syncthreads();
+}
+
+// LDS bytes of a pass-1 block
+template <typename VT> constexpr size_t hub_part_lds()
+{
+    return (size_t)HUB_T1 * (sizeof(int32_t) + sizeof(VT)) + sizeof(int32_t) * (HUB_PMAX + 1);
+}
+
+template <int WK, typename VT>
+__device__ __forceinline__ void hub_part_tile(const SweepArgs &a, const HubArgs &h, int64_t tile, unsigned char *smem)
+{
+    __shared__ int32_t wsum[BLOCK / 64];
     int32_t *tkey = (int32_t *)smem;
-    unsigned long long *tval = (unsigned long long *)(smem + HUB_LDS * sizeof(int32_t));
+    VT *tval = (VT *)(smem + HUB_T1 * sizeof(int32_t));
+    int32_t *hist = (int32_t *)(smem + HUB_T1 * (sizeof(int32_t) + sizeof(VT)));
     const int64_t target = h.chunk0 + tile;
     const int64_t p = last_leq(h.cpre, h.s, h.e, target);
     const int32_t v = h.verts[p];
     if (!sweeping(a, v)) return; // uniform over the block
+    const int64_t lc = target - h.cpre[p];
     const int64_t rb = a.g.off[v], re = a.g.off[v + 1];
-    const int64_t beg = rb + (target - h.cpre[p]) * HUB_CHUNK;
+    const int64_t beg = rb + lc * HUB_CHUNK;
     const int64_t end = min(re, beg + HUB_CHUNK);
-    for (int s = threadIdx.x; s < HUB_LDS; s += BLOCK) {
+    const int P = (int)(h.bpre[p + 1] - h.bpre[p]);
+    const int lp = __ffs(P) - 1;
+    for (int s = threadIdx.x; s < HUB_T1; s += BLOCK) {
         tkey[s] = -1;
         tval[s] = 0;
     }
+    for (int b = threadIdx.x; b <= P; b += BLOCK) hist[b] = 0;
     __syncthreads();
-    constexpr int shift = 12; // log2(HUB_LDS)
-    int64_t wself = 0;
     for (int64_t e = beg + threadIdx.x; e < end; e += BLOCK) {
         const int32_t j = a.g.col[e];
         const int64_t w = WLoad<WK>::at(a.g.w, e);
-        if (j == v) {
-            wself += w;
-            continue;
-        }
+        if (j == v) continue; // the self-loop is read by the decision
         const int32_t c = a.comm_prev[j];
-        uint32_t q = slot_hash(c, shift);
+        uint32_t q = slot_hash(c, 12);
         for (;;) {
             int32_t cur = tkey[q];
             if (cur == c) {
-                atomicAdd(&tval[q], (unsigned long long)w);
+                atomicAdd(&tval[q], (VT)w);
                 break;
             }
             if (cur == -1) {
                 cur = atomicCAS(&tkey[q], -1, c);
                 if (cur == -1 || cur == c) {
-                    atomicAdd(&tval[q], (unsigned long long)w);
+                    atomicAdd(&tval[q], (VT)w);
                     break;
                 }
             }
-            q = (q + 1) & (HUB_LDS - 1);
+            q = (q + 1) & (HUB_T1 - 1);
         }
     }
     __syncthreads();
-    const int64_t t0 = h.hoff[p], S = h.hoff[p + 1] - t0;
-    const int gshift = __ffsll((unsigned long long)S) - 1;
-    int32_t *gkey = h.hkey + t0;
-    unsigned long long *gval = (unsigned long long *)h.hval + t0;
-    flush_to_hbm(tkey, tval, gkey, gval, S, gshift);
-    // self-loop weight and entry count of the chunk
-    int64_t x = wself;
+    // rank of every distinct community inside its bucket, then bucket starts
+    constexpr int PER = HUB_T1 / BLOCK;
+    int32_t rk[PER];
 #pragma unroll
-    for (int m = 32; m > 0; m >>= 1) x += shfl_xor_t(x, m, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    for (int j = 0; j < PER; ++j) {
+        const int32_t c = tkey[threadIdx.x + j * BLOCK];
+        rk[j] = c >= 0 ? atomicAdd(&hist[hub_bucket(c, lp)], 1) : 0;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t t = 0;
-        for (int w = 0; w < BLOCK / 64; ++w) t += red[w];
-        int64_t *aux = h.aux + 8 * (t0 / HUB_SLICE);
-        if (t) atomicAdd((unsigned long long *)&aux[0], (unsigned long long)t);
-        atomicAdd((unsigned long long *)&aux[1], (unsigned long long)(end - beg));
-    }
-}
-
-// mid hubs (bin 9): one workgroup per vertex; the row is pre-aggregated per
-// 2048-entry chunk in LDS, merged into the vertex's HBM table, and the same
-// workgroup scans (and clears) the table and decides.
-template <int WK, typename GT>
-__device__ __forceinline__ void mid_hub_tile(const SweepArgs &a, const BinRange &br, const FusedBins &f,
-                                             int64_t tile, unsigned char *smem, unsigned long long *bstat)
-{
-    __shared__ Best<GT> sb[BLOCK / 64];
-    __shared__ int64_t se[BLOCK / 64][3];
-    int32_t *tkey = (int32_t *)smem;
-    unsigned long long *tval = (unsigned long long *)(smem + HUB_LDS * sizeof(int32_t));
-    const int32_t i = br.verts[tile];
-    if (!sweeping(a, i)) return; // uniform over the block
-    const int64_t two_m = two_m_of(a, i);
-    const int64_t rb = a.g.off[i], re = a.g.off[i + 1];
-    const int64_t t0 = f.hoff9[tile], S = f.hoff9[tile + 1] - t0;
-    const int gshift = __ffsll((unsigned long long)S) - 1;
-    int32_t *gkey = f.hkey + t0;
-    unsigned long long *gval = (unsigned long long *)f.hval + t0;
-    (void)bstat;
-    int64_t wself = 0;
-    for (int64_t cb = rb; cb < re; cb += HUB_CHUNK) {
-        const int64_t ce = min(re, cb + HUB_CHUNK);
-        for (int s = threadIdx.x; s < HUB_LDS; s += BLOCK) {
-            tkey[s] = -1;
-            tval[s] = 0;
-        }
-        __syncthreads();
-        for (int64_t e = cb + threadIdx.x; e < ce; e += BLOCK) {
-            const int32_t j = a.g.col[e];
-            const int64_t w = WLoad<WK>::at(a.g.w, e);
-            if (j == i) {
-                wself += w;
-                continue;
-            }
-            const int32_t c = a.comm_prev[j];
-            uint32_t q = slot_hash(c, 12);
-            for (;;) {
-                int32_t cur = tkey[q];
-                if (cur == c) {
-                    atomicAdd(&tval[q], (unsigned long long)w);
-                    break;
-                }
-                if (cur == -1) {
-                    cur = atomicCAS(&tkey[q], -1, c);
-                    if (cur == -1 || cur == c) {
-                        atomicAdd(&tval[q], (unsigned long long)w);
-                        break;
-                    }
-                }
-                q = (q + 1) & (HUB_LDS - 1);
-            }
-        }
-        __syncthreads();
-        flush_to_hbm(tkey, tval, gkey, gval, S, gshift);
-        __threadfence();
-        __syncthreads();
-    }
-    const int32_t A = a.comm_prev[i];
-    const int64_t ki = a.k[i];
-    Best<GT> best{0, -1, 0};
-    int64_t eA = 0, distinct = 0;
-    scan_hbm(gkey, gval, S, [&](int32_t c, int64_t e) {
-        ++distinct;
-        if (c == A) {
-            eA = e;
-            return;
-        }
-        Best<GT> cand{(GT)two_m * (GT)e - (GT)ki * (GT)a.a[c], c, e};
-        if (better(cand, best)) best = cand;
-    });
+    lds_exscan<BLOCK, 4>(hist, P, wsum);
+    const int64_t base = target * HUB_CHUNK;
+    VT *pval = (VT *)h.pval;
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-        Best<GT> o;
-        o.g = shfl_xor_t(best.g, m, 64);
-        o.c = shfl_xor_t(best.c, m, 64);
-        o.e = shfl_xor_t(best.e, m, 64);
-        if (better(o, best)) best = o;
-        eA += shfl_xor_t(eA, m, 64);
-        wself += shfl_xor_t(wself, m, 64);
-        distinct += shfl_xor_t(distinct, m, 64);
+    for (int j = 0; j < PER; ++j) {
+        const int s = threadIdx.x + j * BLOCK;
+        const int32_t c = tkey[s];
+        if (c < 0) continue;
+        const int64_t at = base + hist[hub_bucket(c, lp)] + rk[j];
+        h.pkey[at] = c;
+        pval[at] = tval[s];
     }
-    const int wid = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        sb[wid] = best;
-        se[wid][0] = eA;
-        se[wid][1] = wself;
-        se[wid][2] = distinct;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < BLOCK / 64; ++w) {
-            if (better(sb[w], best)) best = sb[w];
-            eA += se[w][0];
-            wself += se[w][1];
-            distinct += se[w][2];
-        }
-        const GT stay = (GT)two_m * (GT)eA - (GT)ki * (GT)(a.a[A] - ki);
-        bool move = best.c >= 0 && best.g > stay;
-        if (move && a.singlet && a.size[A] == 1 && a.size[best.c] == 1 && best.c > A) move = false;
-        a.comm_next[i] = move ? best.c : A;
-        unsigned long long *st =
-            a.gid ? (unsigned long long *)&a.gstats[8 * (int64_t)a.gid[i]] : (unsigned long long *)&br.stats->moves;
-        if (move) {
-            atomicAdd(&st[0], 1ull);
-            atomicAdd(&st[2], (unsigned long long)(2 * (best.e - eA)));
-        }
-        atomicAdd(&st[1], (unsigned long long)(eA + wself));
-        atomicAdd(&st[3], (unsigned long long)distinct);
-        atomicAdd(&st[4], (unsigned long long)(re - rb));
-    }
+    int32_t *bo = h.boff + h.xpre[p] + lc * (P + 1);
+    for (int b = threadIdx.x; b <= P; b += BLOCK) bo[b] = hist[b];
 }
 
 // Fused launches: blocks are assigned to bins by block ranges.
 //  small: bins 1..5 (4..64 lanes per vertex, 512 LDS slots per block)
-//  large: bins 6..8 (64 or 256 lanes per vertex, up to 4096 slots) and the hub chunk inserts
+//  large: bins 6..8 (64 or 256 lanes per vertex, up to 4096 slots) and hub pass 1
 template <int WK, typename GT>
 __global__ __launch_bounds__(BLOCK) void k_sweep_small(SweepArgs a, FusedBins f)
 {
@@ -522,92 +403,220 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_small(SweepArgs a, FusedBins f)
     }
 }
 
-template <int WK, typename GT>
+template <int WK, typename GT, typename VT>
 __global__ __launch_bounds__(BLOCK) void k_sweep_large(SweepArgs a, FusedBins f, HubArgs h)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long bstat[5];
-    __shared__ int64_t red[BLOCK / 64];
     const int64_t blk = blockIdx.x;
     if (blk >= f.hub_block0) {
-        hub_insert_tile<WK>(a, h, blk - f.hub_block0, smem, red);
+        hub_part_tile<WK, VT>(a, h, blk - f.hub_block0, smem);
         return;
     }
     int b = 6;
-    while (b < 9 && blk >= f.bins[b + 1].block0) ++b;
+    while (b < 8 && blk >= f.bins[b + 1].block0) ++b;
     const int64_t tile = blk - f.bins[b].block0;
     switch (b) {
     case 6: sweep_tile<64, WK, GT>(a, f.bins[6], tile, 9, smem, bstat); break;
     case 7: sweep_tile<256, WK, GT>(a, f.bins[7], tile, 11, smem, bstat); break;
-    case 8: sweep_tile<256, WK, GT>(a, f.bins[8], tile, 12, smem, bstat); break;
-    default: mid_hub_tile<WK, GT>(a, f.bins[9], f, tile, smem, bstat); break;
+    default: sweep_tile<256, WK, GT>(a, f.bins[8], tile, 12, smem, bstat); break;
     }
 }
 
-// decision of giant hub p from its slice records (called by the last slice block)
-template <typename GT> __device__ void hub_decide_one(const SweepArgs &a, const HubArgs &h, int64_t p)
+template <int WK, typename GT, typename VT>
+__global__ __launch_bounds__(BLOCK) void k_sweep_all(SweepArgs a, FusedBins f, HubArgs h)
 {
-    const int32_t v = h.verts[p];
-    const int64_t first = h.hoff[p] / HUB_SLICE, last = h.hoff[p + 1] / HUB_SLICE;
-    Best<GT> best{0, -1, 0};
-    for (int64_t q = first; q < last; ++q) {
-        int64_t *rec = h.part + 4 * q;
-        const uint64_t lo = (uint64_t)__hip_atomic_load(&rec[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int64_t hi = __hip_atomic_load(&rec[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const i128 g = (i128)(((u128)(uint64_t)hi << 64) | (u128)lo);
-        Best<GT> cand{(GT)g, (int32_t)__hip_atomic_load(&rec[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                      __hip_atomic_load(&rec[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
-        if (better(cand, best)) best = cand;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ unsigned long long bstat[5];
+    const int64_t blk = blockIdx.x;
+    if (blk >= f.hub_block0) {
+        hub_part_tile<WK, VT>(a, h, blk - f.hub_block0, smem);
+        return;
     }
-    int64_t *aux = h.aux + 8 * first;
-    const int64_t wself = __hip_atomic_load(&aux[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int64_t entries = __hip_atomic_load(&aux[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int64_t eA = __hip_atomic_load(&aux[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int64_t distinct = __hip_atomic_load(&aux[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int t = 0; t < 5; ++t) __hip_atomic_store(&aux[t], (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int b = 1;
+    while (b < 8 && blk >= f.bins[b + 1].block0) ++b;
+    const int64_t tile = blk - f.bins[b].block0;
+    switch (b) {
+    case 1: sweep_tile<4, WK, GT>(a, f.bins[1], tile, 3, smem, bstat); break;
+    case 2: sweep_tile<8, WK, GT>(a, f.bins[2], tile, 4, smem, bstat); break;
+    case 3: sweep_tile<16, WK, GT>(a, f.bins[3], tile, 5, smem, bstat); break;
+    case 4: sweep_tile<32, WK, GT>(a, f.bins[4], tile, 6, smem, bstat); break;
+    case 5: sweep_tile<64, WK, GT>(a, f.bins[5], tile, 7, smem, bstat); break;
+    case 6: sweep_tile<64, WK, GT>(a, f.bins[6], tile, 9, smem, bstat); break;
+    case 7: sweep_tile<256, WK, GT>(a, f.bins[7], tile, 11, smem, bstat); break;
+    default: sweep_tile<256, WK, GT>(a, f.bins[8], tile, 12, smem, bstat); break;
+    }
+}
+
+// decisions of the hubs: one thread per hub reduces its bucket records
+// (written by the previous launch) and applies the rule of the other bins
+template <typename GT> __global__ __launch_bounds__(BLOCK) void k_hub_decide(SweepArgs a, HubArgs h)
+{
+    const int64_t p = h.s + (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= h.e) return;
+    const int32_t v = h.verts[p];
+    if (!sweeping(a, v)) return;
+    Best<GT> best{0, -1, 0};
+    int64_t eA = 0, distinct = 0;
+    for (int64_t q = h.bpre[p]; q < h.bpre[p + 1]; ++q) {
+        const int64_t *rec = h.part + HUB_REC * q;
+        const i128 g = (i128)(((u128)(uint64_t)rec[1] << 64) | (u128)(uint64_t)rec[0]);
+        Best<GT> cand{(GT)g, (int32_t)rec[2], rec[3]};
+        if (better(cand, best)) best = cand;
+        eA += rec[4];
+        distinct += rec[5];
+    }
+    // self-loop weight: the row's columns are sorted
+    const int64_t rb = a.g.off[v], re = a.g.off[v + 1];
+    int64_t lo = rb, hi = re, wself = 0;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const int32_t c = a.g.col[mid];
+        if (c == v) {
+            wself = a.g.wk == W_UNIT ? 1 : (a.g.wk == W_I32 ? (int64_t)((const int32_t *)a.g.w)[mid]
+                                                              : ((const int64_t *)a.g.w)[mid]);
+            break;
+        }
+        if (c < v) lo = mid + 1; else hi = mid;
+    }
     const int32_t A = a.comm_prev[v];
     const int64_t kv = a.k[v];
     const GT stay = (GT)two_m_of(a, v) * (GT)eA - (GT)kv * (GT)(a.a[A] - kv);
     bool move = best.c >= 0 && best.g > stay;
     if (move && a.singlet && a.size[A] == 1 && a.size[best.c] == 1 && best.c > A) move = false;
     a.comm_next[v] = move ? best.c : A;
-    unsigned long long *st =
-        a.gid ? (unsigned long long *)&a.gstats[8 * (int64_t)a.gid[v]] : (unsigned long long *)&a.stats->moves;
+    unsigned long long *st = a.gid ? (unsigned long long *)&a.gstats[8 * (int64_t)a.gid[v]]
+                                   : (unsigned long long *)&a.stats[p % STAT_REP].moves;
     if (move) {
         atomicAdd(&st[0], 1ull);
         atomicAdd(&st[2], (unsigned long long)(2 * (best.e - eA)));
     }
     atomicAdd(&st[1], (unsigned long long)(eA + wself));
     atomicAdd(&st[3], (unsigned long long)distinct);
-    atomicAdd(&st[4], (unsigned long long)entries);
+    atomicAdd(&st[4], (unsigned long long)(re - rb));
 }
 
-// scan of one 4096-slot slice of a giant-hub table; the last slice block of a
-// hub (counted in aux[4]) makes the hub's decision
-template <typename GT>
-__global__ __launch_bounds__(BLOCK) void k_hub_scan(SweepArgs a, HubArgs h)
+// Pass 2: one block per (hub, bucket).  The bucket's pairs from every chunk
+// of the hub are summed in an LDS table of HUB_T2 slots.  A round holds at
+// most HUB_CAP2 distinct communities; if a bucket has more, it is redone in
+// R = 2, 4, ... rounds, each taking the communities whose hash has low bits r
+// (and, past R = 2^16, in rounds over id ranges of 2048, which always fit).
+template <typename GT, typename VT>
+__global__ __launch_bounds__(HUB_BLOCK2) void k_hub_agg(SweepArgs a, HubArgs h)
 {
-    __shared__ Best<GT> sb[BLOCK / 64];
-    __shared__ int64_t se[BLOCK / 64][2];
-    const int64_t slice = h.slice0 + blockIdx.x;
-    const int64_t p = last_leq(h.hoff, h.s, h.e, slice * HUB_SLICE);
+    __shared__ int32_t tkey[HUB_T2];
+    __shared__ VT tval[HUB_T2];
+    __shared__ int32_t s_cnt, s_over;
+    __shared__ int32_t seg_lo[HUB_SEGS], seg_pre[HUB_SEGS + 1];
+    __shared__ int32_t wsum[HUB_BLOCK2 / 64];
+    __shared__ Best<GT> sb[HUB_BLOCK2 / 64];
+    __shared__ int64_t se[HUB_BLOCK2 / 64][2];
+    const int64_t q = h.bucket0 + blockIdx.x;
+    const int64_t p = last_leq(h.bpre, h.s, h.e, q);
     const int32_t v = h.verts[p];
     if (!sweeping(a, v)) return; // uniform over the block
-    const int64_t two_m = two_m_of(a, v);
+    const int P = (int)(h.bpre[p + 1] - h.bpre[p]);
+    const int b = (int)(q - h.bpre[p]);
+    const int64_t c0 = h.cpre[p], nch = h.cpre[p + 1] - c0;
+    const int32_t *bo = h.boff + h.xpre[p];
+    const VT *pval = (const VT *)h.pval;
     const int32_t A = a.comm_prev[v];
-    const int64_t kv = a.k[v];
+    const int64_t two_m = two_m_of(a, v), kv = a.k[v];
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    constexpr int NW = HUB_BLOCK2 / 64;
     Best<GT> best{0, -1, 0};
     int64_t eA = 0, distinct = 0;
-    const int64_t base = slice * HUB_SLICE;
-    scan_hbm(h.hkey + base, (unsigned long long *)h.hval + base, HUB_SLICE, [&](int32_t c, int64_t e) {
-        ++distinct;
-        if (c == A) {
-            eA += e;
-            return;
+    for (int64_t R = 1;; R <<= 1) {
+        const bool by_range = R > (1 << 16);
+        const int64_t rounds = by_range ? ((int64_t)a.g.n + 2047) / 2048 : R;
+        bool over = false;
+        best = Best<GT>{0, -1, 0};
+        eA = 0;
+        distinct = 0;
+        for (int64_t r = 0; r < rounds && !over; ++r) {
+            for (int s = tid; s < HUB_T2; s += HUB_BLOCK2) {
+                tkey[s] = -1;
+                tval[s] = 0;
+            }
+            if (tid == 0) {
+                s_cnt = 0;
+                s_over = 0;
+            }
+            __syncthreads();
+            // the bucket's segments of up to HUB_SEGS chunks at a time, as one
+            // flat range over the threads
+            for (int64_t cb = 0; cb < nch; cb += HUB_SEGS) {
+                const int nb = (int)min((int64_t)HUB_SEGS, nch - cb);
+                for (int k = tid; k < nb; k += HUB_BLOCK2) {
+                    const int32_t *bk = bo + (cb + k) * (P + 1) + b;
+                    seg_lo[k] = bk[0];
+                    seg_pre[k] = bk[1] - bk[0];
+                }
+                __syncthreads();
+                lds_exscan<HUB_BLOCK2, HUB_SEGS / HUB_BLOCK2>(seg_pre, nb, wsum);
+                const int32_t total = seg_pre[nb];
+                for (int32_t t = tid; t < total; t += HUB_BLOCK2) {
+                    int lo = 0, hi = nb; // largest k with seg_pre[k] <= t
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (seg_pre[mid] <= t) lo = mid; else hi = mid;
+                    }
+                    const int64_t at = (c0 + cb + lo) * HUB_CHUNK + seg_lo[lo] + (t - seg_pre[lo]);
+                    const int32_t c = h.pkey[at];
+                    const uint32_t hc = fmix32((uint32_t)c);
+                    if (by_range ? (int64_t)(c >> 11) != r : (int64_t)(hc & (uint32_t)(R - 1)) != r) continue;
+                    const VT w = pval[at];
+                    uint32_t slot = hc >> 20; // top 12 bits: HUB_T2 slots
+                    for (;;) {
+                        int32_t cur = tkey[slot];
+                        if (cur == c) {
+                            atomicAdd(&tval[slot], w);
+                            break;
+                        }
+                        if (cur == -1) {
+                            // reserve room first: occupied slots never exceed HUB_CAP2 < HUB_T2,
+                            // so every probe sequence meets an empty slot
+                            if (atomicAdd(&s_cnt, 1) >= HUB_CAP2) {
+                                s_over = 1;
+                                break;
+                            }
+                            cur = atomicCAS(&tkey[slot], -1, c);
+                            if (cur == -1) {
+                                atomicAdd(&tval[slot], w);
+                                break;
+                            }
+                            atomicSub(&s_cnt, 1);
+                            if (cur == c) {
+                                atomicAdd(&tval[slot], w);
+                                break;
+                            }
+                        }
+                        slot = (slot + 1) & (HUB_T2 - 1);
+                    }
+                }
+                __syncthreads(); // segment arrays are rewritten by the next batch
+            }
+            __syncthreads();
+            const bool ov = s_over != 0;
+            if (!ov) {
+                for (int s = tid; s < HUB_T2; s += HUB_BLOCK2) {
+                    const int32_t c = tkey[s];
+                    if (c < 0) continue;
+                    const int64_t e = (int64_t)tval[s];
+                    ++distinct;
+                    if (c == A) {
+                        eA += e;
+                        continue;
+                    }
+                    Best<GT> cand{(GT)two_m * (GT)e - (GT)kv * (GT)a.a[c], c, e};
+                    if (better(cand, best)) best = cand;
+                }
+            }
+            __syncthreads(); // table and flag are read by all before the next round clears them
+            over = ov;
         }
-        Best<GT> cand{(GT)two_m * (GT)e - (GT)kv * (GT)a.a[c], c, e};
-        if (better(cand, best)) best = cand;
-    });
+        if (!over) break;
+    }
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) {
         Best<GT> o;
@@ -618,62 +627,26 @@ __global__ __launch_bounds__(BLOCK) void k_hub_scan(SweepArgs a, HubArgs h)
         eA += shfl_xor_t(eA, m, 64);
         distinct += shfl_xor_t(distinct, m, 64);
     }
-    const int wid = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
         sb[wid] = best;
         se[wid][0] = eA;
         se[wid][1] = distinct;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < BLOCK / 64; ++w) {
+    if (tid == 0) {
+        for (int w = 1; w < NW; ++w) {
             if (better(sb[w], best)) best = sb[w];
             eA += se[w][0];
             distinct += se[w][1];
         }
-        int64_t *rec = h.part + 4 * slice;
+        int64_t *rec = h.part + HUB_REC * q;
         const i128 g = (i128)best.g;
-        __hip_atomic_store(&rec[0], (int64_t)(uint64_t)(u128)g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&rec[1], (int64_t)(g >> 64), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&rec[2], (int64_t)best.c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&rec[3], best.e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int64_t first = h.hoff[p] / HUB_SLICE, nsl = h.hoff[p + 1] / HUB_SLICE - first;
-        int64_t *aux = h.aux + 8 * first;
-        if (eA) atomicAdd((unsigned long long *)&aux[2], (unsigned long long)eA);
-        if (distinct) atomicAdd((unsigned long long *)&aux[3], (unsigned long long)distinct);
-        __threadfence();
-        const int64_t done = __hip_atomic_fetch_add(&aux[4], (int64_t)1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (done == nsl - 1) {
-            __threadfence();
-            hub_decide_one<GT>(a, h, p);
-        }
-    }
-}
-
-template <int WK, typename GT>
-__global__ __launch_bounds__(BLOCK) void k_sweep_all(SweepArgs a, FusedBins f, HubArgs h)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ unsigned long long bstat[5];
-    __shared__ int64_t red[BLOCK / 64];
-    const int64_t blk = blockIdx.x;
-    if (blk >= f.hub_block0) {
-        hub_insert_tile<WK>(a, h, blk - f.hub_block0, smem, red);
-        return;
-    }
-    int b = 1;
-    while (b < 9 && blk >= f.bins[b + 1].block0) ++b;
-    const int64_t tile = blk - f.bins[b].block0;
-    switch (b) {
-    case 1: sweep_tile<4, WK, GT>(a, f.bins[1], tile, 3, smem, bstat); break;
-    case 2: sweep_tile<8, WK, GT>(a, f.bins[2], tile, 4, smem, bstat); break;
-    case 3: sweep_tile<16, WK, GT>(a, f.bins[3], tile, 5, smem, bstat); break;
-    case 4: sweep_tile<32, WK, GT>(a, f.bins[4], tile, 6, smem, bstat); break;
-    case 5: sweep_tile<64, WK, GT>(a, f.bins[5], tile, 7, smem, bstat); break;
-    case 6: sweep_tile<64, WK, GT>(a, f.bins[6], tile, 9, smem, bstat); break;
-    case 7: sweep_tile<256, WK, GT>(a, f.bins[7], tile, 11, smem, bstat); break;
-    case 8: sweep_tile<256, WK, GT>(a, f.bins[8], tile, 12, smem, bstat); break;
-    default: mid_hub_tile<WK, GT>(a, f.bins[9], f, tile, smem, bstat); break;
+        rec[0] = (int64_t)(uint64_t)(u128)g;
+        rec[1] = (int64_t)(g >> 64);
+        rec[2] = (int64_t)best.c;
+        rec[3] = best.e;
+        rec[4] = eA;
+        rec[5] = distinct;
     }
 }
 
@@ -687,18 +660,45 @@ template <typename GT> static void small_t(const SweepArgs &a, const FusedBins &
     }
 }
 
-template <typename GT>
-static void large_t(const SweepArgs &a, const FusedBins &f, const HubArgs &h, int64_t blocks, hipStream_t st)
+// dynamic LDS of a fused launch with bins up to 8 and hub pass 1
+template <int WK, typename VT> static size_t fused_lds()
 {
-    const size_t lds = (size_t)HUB_LDS * 12; // 4096 slots: int32 key + 64-bit value
+    const size_t bin8 = (size_t)4096 * (WK == W_UNIT ? 8 : 12);
+    const size_t part = hub_part_lds<VT>();
+    return bin8 > part ? bin8 : part;
+}
+
+template <bool ALL, int WK, typename GT, typename VT>
+static void fused_launch(const SweepArgs &a, const FusedBins &f, const HubArgs &h, int64_t blocks, hipStream_t st)
+{
+    if (ALL) k_sweep_all<WK, GT, VT><<<(unsigned)blocks, BLOCK, fused_lds<WK, VT>(), st>>>(a, f, h);
+    else k_sweep_large<WK, GT, VT><<<(unsigned)blocks, BLOCK, fused_lds<WK, VT>(), st>>>(a, f, h);
+}
+
+template <bool ALL, typename GT, typename VT>
+static void fused_t(const SweepArgs &a, const FusedBins &f, const HubArgs &h, int64_t blocks, hipStream_t st)
+{
     switch (a.g.wk) {
-    case W_UNIT: k_sweep_large<W_UNIT, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h); break;
-    case W_I32: k_sweep_large<W_I32, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h); break;
-    default: k_sweep_large<W_I64, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h); break;
+    case W_UNIT: fused_launch<ALL, W_UNIT, GT, VT>(a, f, h, blocks, st); break;
+    case W_I32: fused_launch<ALL, W_I32, GT, VT>(a, f, h, blocks, st); break;
+    default: fused_launch<ALL, W_I64, GT, VT>(a, f, h, blocks, st); break;
     }
 }
 
-static const int kLanes[10] = {0, 4, 8, 16, 32, 64, 64, 256, 256, 256};
+template <bool ALL>
+static void fused(const SweepArgs &a, const FusedBins &f, const HubArgs &h, int64_t blocks, bool wide, bool narrow,
+                  hipStream_t st)
+{
+    if (wide) {
+        if (narrow) fused_t<ALL, i128, uint32_t>(a, f, h, blocks, st);
+        else fused_t<ALL, i128, unsigned long long>(a, f, h, blocks, st);
+    } else {
+        if (narrow) fused_t<ALL, int64_t, uint32_t>(a, f, h, blocks, st);
+        else fused_t<ALL, int64_t, unsigned long long>(a, f, h, blocks, st);
+    }
+}
+
+static const int kLanes[9] = {0, 4, 8, 16, 32, 64, 64, 256, 256};
 
 bool sweep_small(const SweepArgs &a, FusedBins f, bool wide, hipStream_t st)
 {
@@ -713,52 +713,48 @@ bool sweep_small(const SweepArgs &a, FusedBins f, bool wide, hipStream_t st)
     return true;
 }
 
-bool sweep_large(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, hipStream_t st)
+bool sweep_large(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, bool narrow, hipStream_t st)
 {
     int64_t blocks = 0;
-    for (int b = 6; b <= 9; ++b) {
+    for (int b = 6; b <= 8; ++b) {
         f.bins[b].block0 = blocks;
         blocks += (f.bins[b].count + BLOCK / kLanes[b] - 1) / (BLOCK / kLanes[b]);
     }
     f.hub_block0 = blocks;
-    if (h.e > h.s) blocks += h.n_insert;
+    if (h.e > h.s) blocks += h.n_chunks;
     if (blocks == 0) return false;
-    if (wide) large_t<i128>(a, f, h, blocks, st);
-    else large_t<int64_t>(a, f, h, blocks, st);
+    fused<false>(a, f, h, blocks, wide, narrow, st);
     return true;
 }
 
-bool sweep_hub_scan(const SweepArgs &a, const HubArgs &h, bool wide, hipStream_t st)
-{
-    if (h.e <= h.s) return false;
-    if (wide) k_hub_scan<i128><<<(unsigned)h.n_scan, BLOCK, 0, st>>>(a, h);
-    else k_hub_scan<int64_t><<<(unsigned)h.n_scan, BLOCK, 0, st>>>(a, h);
-    return true;
-}
-
-template <typename GT>
-static void all_t(const SweepArgs &a, const FusedBins &f, const HubArgs &h, int64_t blocks, hipStream_t st)
-{
-    const size_t lds = (size_t)HUB_LDS * 12;
-    switch (a.g.wk) {
-    case W_UNIT: k_sweep_all<W_UNIT, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h); break;
-    case W_I32: k_sweep_all<W_I32, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h); break;
-    default: k_sweep_all<W_I64, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h); break;
-    }
-}
-
-bool sweep_all(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, hipStream_t st)
+bool sweep_all(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, bool narrow, hipStream_t st)
 {
     int64_t blocks = 0;
-    for (int b = 1; b <= 9; ++b) {
+    for (int b = 1; b <= 8; ++b) {
         f.bins[b].block0 = blocks;
         blocks += (f.bins[b].count + BLOCK / kLanes[b] - 1) / (BLOCK / kLanes[b]);
     }
     f.hub_block0 = blocks;
-    if (h.e > h.s) blocks += h.n_insert;
+    if (h.e > h.s) blocks += h.n_chunks;
     if (blocks == 0) return false;
-    if (wide) all_t<i128>(a, f, h, blocks, st);
-    else all_t<int64_t>(a, f, h, blocks, st);
+    fused<true>(a, f, h, blocks, wide, narrow, st);
+    return true;
+}
+
+bool sweep_hub_agg(const SweepArgs &a, const HubArgs &h, bool wide, bool narrow, hipStream_t st)
+{
+    if (h.e <= h.s || h.n_buckets == 0) return false;
+    const unsigned g = (unsigned)h.n_buckets;
+    const unsigned gd = grid_for(h.e - h.s, BLOCK);
+    if (wide) {
+        if (narrow) k_hub_agg<i128, uint32_t><<<g, HUB_BLOCK2, 0, st>>>(a, h);
+        else k_hub_agg<i128, unsigned long long><<<g, HUB_BLOCK2, 0, st>>>(a, h);
+        k_hub_decide<i128><<<gd, BLOCK, 0, st>>>(a, h);
+    } else {
+        if (narrow) k_hub_agg<int64_t, uint32_t><<<g, HUB_BLOCK2, 0, st>>>(a, h);
+        else k_hub_agg<int64_t, unsigned long long><<<g, HUB_BLOCK2, 0, st>>>(a, h);
+        k_hub_decide<int64_t><<<gd, BLOCK, 0, st>>>(a, h);
+    }
     return true;
 }
 
@@ -813,32 +809,38 @@ void narrow_ids(const int64_t *vals, int32_t *out, int64_t n, hipStream_t st)
 }
 
 __global__ __launch_bounds__(BLOCK) void k_hub_sizes(const int64_t *off, const int32_t *verts, int64_t count,
-                                                     int64_t *slots, int64_t *chunks)
+                                                     int64_t *chunks, int64_t *buckets, int64_t *bounds)
 {
     for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < count; p += (int64_t)gridDim.x * BLOCK) {
         const int32_t v = verts[p];
         const int64_t d = off[v + 1] - off[v];
-        const int bin = degree_bin(d);
-        slots[p] = bin >= 9 ? pow2_ceil(2 * d) : 0; // >= 8192, a multiple of HUB_SLICE
-        chunks[p] = bin == 10 ? (d + HUB_CHUNK - 1) / HUB_CHUNK : 0;
+        const bool hub = degree_bin(d) >= 9;
+        const int64_t c = hub ? (d + HUB_CHUNK - 1) / HUB_CHUNK : 0;
+        const int64_t P = hub ? hub_buckets(d) : 0;
+        chunks[p] = c;
+        buckets[p] = P;
+        bounds[p] = c * (P + 1);
     }
 }
 
-void hub_prefix(const Csr &g, const int32_t *verts, int64_t count, int64_t *hoff, int64_t *cpre, int64_t *tmp,
+void hub_prefix(const Csr &g, const int32_t *verts, int64_t count, int64_t *cpre, int64_t *bpre, int64_t *xpre,
                 Scratch &s, hipStream_t st)
 {
     if (count == 0) {
-        fill<int64_t>(hoff, 0, 1, st);
         fill<int64_t>(cpre, 0, 1, st);
+        fill<int64_t>(bpre, 0, 1, st);
+        fill<int64_t>(xpre, 0, 1, st);
         return;
     }
     unsigned gb = grid_for(count, BLOCK * 4);
     if (gb > 65536) gb = 65536;
-    k_hub_sizes<<<gb, BLOCK, 0, st>>>(g.off, verts, count, tmp, cpre);
-    scan_i64(tmp, hoff, count, hoff + count, s, st);
-    scan_i64(cpre, tmp, count, tmp + count, s, st);  // chunk prefix lands in tmp ...
-    hipMemcpyAsync(cpre, tmp, (count + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, st); // ... then cpre
+    k_hub_sizes<<<gb, BLOCK, 0, st>>>(g.off, verts, count, cpre, bpre, xpre);
+    // in place: each scan block reads its own tile before writing it
+    scan_i64(cpre, cpre, count, cpre + count, s, st);
+    scan_i64(bpre, bpre, count, bpre + count, s, st);
+    scan_i64(xpre, xpre, count, xpre + count, s, st);
 }
+
 
 __global__ __launch_bounds__(BLOCK) void k_gather_i64(const int64_t *src, const int64_t *idx, int64_t n, int64_t *out)
 {

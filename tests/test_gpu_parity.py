@@ -263,3 +263,33 @@ def test_profiling_records(L):
     assert swept == res.sweep_entries
     assert all(r["ms"] >= 0 for r in recs.values())
     gs.close()
+
+
+def overflow_hub_graph(seed=17, n=100_000, extra=50_000):
+    """Hubs whose neighbours' communities all fall in one hash bucket, so a
+    bucket holds more distinct communities than one aggregation round may
+    (degree 4,000 in bucket 0 of 2, degree 9,000 in bucket 0 of 8): their
+    buckets are summed in several rounds."""
+    rng = np.random.default_rng(seed)
+    ids = np.arange(2, n, dtype=np.uint64)
+    fib = (ids * np.uint64(0x9E3779B1)) & np.uint64(0xFFFFFFFF)
+    edges = set()
+    for hub, deg, bits in ((0, 4000, 1), (1, 9000, 3)):
+        pool = ids[(fib >> np.uint64(32 - bits)) == 0]
+        for v in rng.choice(pool, size=deg, replace=False):
+            edges.add((hub, int(v)))
+    while len(edges) < 13000 + extra:
+        u, v = (int(x) for x in rng.integers(2, n, 2))
+        if u != v:
+            edges.add((min(u, v), max(u, v)))
+    edges = sorted(edges)
+    w = rng.integers(1, 30, size=len(edges))
+    return SG.from_edges(n, edges, w, name="overflow_hub_graph")
+
+
+@pytest.mark.parametrize("pi", [0, 2])
+def test_hub_bucket_overflow(L, O, pi):
+    g = overflow_hub_graph()
+    print(f"[parity] overflow hubs n={g.n} nnz={g.nnz} params {PARAM_SETS[pi]}", flush=True)
+    res = L.Graph.from_csr(g).run(L.params(**PARAM_SETS[pi]))
+    compare_run(res, O.run(g, oracle.Params(**PARAM_SETS[pi])), "overflow hubs")
