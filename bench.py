@@ -11,7 +11,9 @@ Printed value: local-move GTEPS = CSR entries gathered by all sweeps of a
 step / wall time of the step (so coloring, rebuilding and ingest count
 against it); ms_per_step is the time to converge.  The roofline object is
 for the sweep kernel with the largest device time, from HIP events recorded
-by the library around every launch on its stream during the timed steps.
+by the library around every launch on its stream during one more, untimed
+step.  --form batched and --form served measure the batched and served
+forms (graphs/s; p50/p99 latency for the served form).
 """
 from __future__ import annotations
 
@@ -105,6 +107,189 @@ def cpu_baseline(g, seconds_target=15.0):
     }
 
 
+def _gen_many(fn, idx, threads):
+    """Generates graphs fn(i) for i in idx on a thread pool (the generator
+    releases the GIL)."""
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(fn, idx))
+
+
+def _host_threads():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def cpu_baseline_graphs(graphs, params, seconds_target=15.0):
+    """The oracle's graphs/s: independent graphs of the sample spread over
+    the host cores (still serial per graph), until about seconds_target."""
+    import concurrent.futures as cf
+    import oracle
+    O = oracle.default()
+    P = oracle.Params(**params)
+    threads = _host_threads()
+    done, t0 = 0, time.time()
+    it = iter(graphs)
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        running = set()
+        for g in it:
+            running.add(ex.submit(O.run, g, P))
+            if len(running) >= threads:
+                fin, running = cf.wait(running, return_when=cf.FIRST_COMPLETED)
+                done += len(fin)
+                if time.time() - t0 > seconds_target:
+                    break
+        fin, _ = cf.wait(running)
+        done += len(fin)
+    dt = time.time() - t0
+    return {"value": round(done / dt, 2), "unit": "graphs/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} graphs of the same mix, serial oracle per graph, {threads} threads, {dt:.1f} s",
+            "cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
+
+
+def bench_batched(args):
+    """Many planted-partition SBMs of uneven sizes in one disjoint-union CSR,
+    run by the batched form; against the same graphs run one at a time."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")  # one generator thread per graph
+    import numpy as np
+    import torch
+    from paper_1410_1237_amd import graphs as G
+    from paper_1410_1237_amd import louvain as L
+
+    t = time.time()
+    gs = _gen_many(G.batch_sbm, range(args.graphs), _host_threads())
+    goff, off, col, w = L.union_csr(gs)
+    print(f"[bench] batched: {len(gs)} SBMs, n={int(goff[-1])} nnz={len(col)} generated in {time.time() - t:.1f}s",
+          file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    d_off = torch.from_numpy(off).to(dev)
+    d_col = torch.from_numpy(col).to(dev)
+    d_w = torch.from_numpy(w).to(dev) if w is not None else None
+    labels = torch.empty(int(goff[-1]), dtype=torch.int32, device=dev)
+    p = L.params()
+
+    def step():
+        b = L.Batch.from_union(goff, d_off, d_col, d_w)
+        res = b.run(p, labels=labels, stats=False)
+        b.close()
+        return res
+
+    for i in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    gps = args.steps * len(gs) / elapsed
+
+    # one at a time: sequential louvain_run per graph on one stream, CSR resident
+    sample = list(range(0, len(gs), max(1, len(gs) // args.solo_sample)))[:args.solo_sample]
+    dev_graphs = [(torch.from_numpy(gs[i].offsets).to(dev), torch.from_numpy(gs[i].cols).to(dev),
+                   torch.from_numpy(gs[i].weights).to(dev) if gs[i].weights is not None else None) for i in sample]
+    solo_labels = torch.empty(max(g.n for g in gs), dtype=torch.int32, device=dev)
+
+    def solo(j):
+        o, c, ww = dev_graphs[j]
+        h = L.Graph.from_tensors(o, c, ww, validate=False)
+        r = h.run(p, labels=solo_labels[:o.numel() - 1])
+        h.close()
+        return r
+
+    solo(0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    solo_res = [solo(j) for j in range(len(sample))]
+    torch.cuda.synchronize()
+    solo_gps = len(sample) / (time.perf_counter() - t1)
+    for j, i in enumerate(sample):  # identical outputs (exact modularity, communities)
+        assert (solo_res[j].N, solo_res[j].D, solo_res[j].K) == (res[i].N, res[i].D, res[i].K), f"graph {i}"
+    sizes = np.array([g.n for g in gs])
+    out = {
+        "metric": "batched graphs/s", "value": round(gps, 2), "unit": "graphs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"batch_sbm x{len(gs)}", "graphs": len(gs), "n_total": int(goff[-1]),
+                   "nnz_total": int(len(col)), "n_min": int(sizes.min()), "n_median": int(np.median(sizes)),
+                   "n_max": int(sizes.max()), "heuristics": "plain"},
+        "one_at_a_time": {"value": round(solo_gps, 2), "unit": "graphs/s",
+                          "sample": f"{len(sample)} graphs (every {max(1, len(gs) // args.solo_sample)}th), "
+                                    "sequential louvain_run on one stream, CSR resident",
+                          "batched_over_one_at_a_time": round(gps / solo_gps, 2)},
+        "roofline": None,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_graphs(gs, {}, args.cpu_seconds),
+    }
+    print(json.dumps(out))
+
+
+def bench_served(args):
+    """The request loop: a job mix of SBM and R-MAT graphs from 1e3 to 2e6
+    vertices.  First all jobs at once (capacity), then Poisson arrivals at 80 %
+    of that capacity: p50 / p99 latency (completion - submission) and
+    completed graphs/s."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import numpy as np
+    import torch
+    from paper_1410_1237_amd import graphs as G
+    from paper_1410_1237_amd import louvain as L
+
+    t = time.time()
+    jobs = _gen_many(G.served_job, range(args.jobs), _host_threads())
+    tot_n, tot_e = sum(g.n for g in jobs), sum(g.nnz for g in jobs)
+    print(f"[bench] served: {len(jobs)} jobs, n={tot_n} nnz={tot_e} generated in {time.time() - t:.1f}s",
+          file=sys.stderr, flush=True)
+    p = L.params()
+    torch.cuda.init()
+
+    def run(rate):
+        s = L.Server(p)
+        rng = np.random.default_rng(6)
+        gaps = rng.exponential(1.0 / rate, size=len(jobs)) if rate else np.zeros(len(jobs))
+        t0 = time.perf_counter()
+        due = 0.0
+        tickets = []
+        for g, gap in zip(jobs, gaps):
+            due += gap
+            wait = due - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            tickets.append(s.submit(g))
+        s.wait_all()
+        infos = [s.poll(tk, labels=False) for tk in tickets]
+        s.close()
+        assert all(i.status == L.OK for i in infos)
+        lat = np.array([i.t_done - i.t_submit for i in infos])
+        span = max(i.t_done for i in infos) - min(i.t_submit for i in infos)
+        return infos, lat, span
+
+    run(0)  # warm-up
+    infos, lat, span = run(0)
+    capacity = len(jobs) / span
+    rate = 0.8 * capacity
+    infos, lat, span = run(rate)
+    # spot check: a few jobs equal their solo runs
+    for j in range(0, len(jobs), max(1, len(jobs) // 4)):
+        h = L.Graph.from_csr(jobs[j])
+        r = h.run(p)
+        h.close()
+        assert (r.N, r.D, r.K) == (infos[j].N, infos[j].D, infos[j].K), f"job {j}"
+    out = {
+        "metric": "served graphs/s", "value": round(len(jobs) / span, 2), "unit": "graphs/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": round(span * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"served_job x{len(jobs)}", "jobs": len(jobs), "n_total": tot_n, "nnz_total": tot_e,
+                   "arrivals": "Poisson", "rate_per_s": round(rate, 2), "capacity_per_s": round(capacity, 2),
+                   "hbm_budget_bytes": 200 << 30, "max_inflight_batches": 4, "heuristics": "plain"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                       "p99": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                       "max": round(float(lat.max()) * 1e3, 2)},
+        "batches": len({i.batch_id for i in infos}),
+        "roofline": None,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_graphs(jobs, {}, args.cpu_seconds),
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,12 +299,21 @@ def main():
     ap.add_argument("--heuristics", default="full", choices=sorted(HEURISTICS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-profile", action="store_true", help="time without per-launch events")
+    ap.add_argument("--no-profile", action="store_true", help="skip the profiled step after the timed ones")
+    ap.add_argument("--form", default="single", choices=["single", "batched", "served"],
+                    help="single graph (default); batched: many SBMs in one batched run; served: request loop")
+    ap.add_argument("--graphs", type=int, default=4096, help="batched form: graphs in the batch")
+    ap.add_argument("--jobs", type=int, default=128, help="served form: jobs")
+    ap.add_argument("--solo-sample", type=int, default=256, help="batched form: graphs timed one at a time")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
               "(multi-GPU sharding is a design, not part of it); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.form == "batched":
+        return bench_batched(args)
+    if args.form == "served":
+        return bench_served(args)
 
     import numpy as np
     import torch
@@ -154,17 +348,11 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     entries = 0
-    all_recs = {}
     results = []
     for i in range(args.steps):
-        res, recs = step(profile=not args.no_profile)
+        res, _ = step()
         entries += res.sweep_entries
         results.append(res)
-        if recs:
-            for r in recs:
-                a = all_recs.setdefault(r["name"], {"launches": 0, "ms": 0.0, "bytes": 0.0, "entries": 0.0})
-                for k in ("launches", "ms", "bytes", "entries"):
-                    a[k] += r[k]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
@@ -172,6 +360,17 @@ def main():
     last = results[-1]
     assert all(r.N == last.N and r.K == last.K for r in results), "steps disagree"
 
+    # one more step, untimed, with HIP events around every launch on the
+    # library's stream: per-kernel durations and algorithmic bytes
+    all_recs = {}
+    prof_steps = 0 if args.no_profile else 1
+    for i in range(prof_steps):
+        res, recs = step(profile=True)
+        assert res.N == last.N and res.K == last.K, "profiled step disagrees"
+        for r in recs:
+            a = all_recs.setdefault(r["name"], {"launches": 0, "ms": 0.0, "bytes": 0.0, "entries": 0.0})
+            for k in ("launches", "ms", "bytes", "entries"):
+                a[k] += r[k]
     sweep_recs = {k: v for k, v in all_recs.items() if k.startswith("sweep") and v["launches"]}
     roofline = None
     if sweep_recs:
@@ -186,7 +385,7 @@ def main():
                     "algorithmic_bytes_per_launch": round(per_launch_bytes)}
         tot_ms = sum(v["ms"] for v in sweep_recs.values())
         tot_b = sum(v["bytes"] for v in sweep_recs.values())
-        roofline["all_sweep_kernels"] = {"ms": round(tot_ms / args.steps, 3),
+        roofline["all_sweep_kernels"] = {"ms": round(tot_ms / prof_steps, 3),
                                          "GBps": round(tot_b / (tot_ms * 1e-3) / 1e9, 1),
                                          "frac": round(tot_b / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
@@ -206,7 +405,7 @@ def main():
                    "phase_shape": [[ph.n, ph.nnz, int(ph.colored), ph.num_colors, ph.iterations] for ph in last.phases]},
         "time_split_ms": {"vf": round(last.ms_vf, 2), "color": round(last.ms_color, 2),
                           "sweep": round(last.ms_sweep, 2), "coarsen": round(last.ms_coarsen, 2)},
-        "kernels": {k: {"launches": v["launches"] // args.steps, "ms": round(v["ms"] / args.steps, 3)}
+        "kernels": {k: {"launches": v["launches"] // max(prof_steps, 1), "ms": round(v["ms"] / max(prof_steps, 1), 3)}
                     for k, v in all_recs.items() if v["launches"]},
         "roofline": roofline,
         "cpu_baseline": None,
