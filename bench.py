@@ -10,9 +10,11 @@ modularity, threshold cycling, and graph rebuilding between phases.
 Printed value: local-move GTEPS = CSR entries gathered by all sweeps of a
 step / wall time of the step (so coloring, rebuilding and ingest count
 against it); ms_per_step is the time to converge.  The roofline object is
-for the sweep kernel with the largest device time, from HIP events recorded
-by the library around every launch on its stream during one more, untimed
-step.  --form batched and --form served measure the batched and served
+for the sweep kernel with the largest device time in the bandwidth run
+(plain synchronous sweeps over the same graph: no colour classes), from HIP
+events recorded by the library around every launch on its stream during an
+untimed step; roofline_timed_config gives the same for the timed
+configuration.  --form batched and --form served measure the batched and served
 forms (graphs/s; p50/p99 latency for the served form).
 """
 from __future__ import annotations
@@ -305,6 +307,9 @@ def main():
     ap.add_argument("--graphs", type=int, default=4096, help="batched form: graphs in the batch")
     ap.add_argument("--jobs", type=int, default=128, help="served form: jobs")
     ap.add_argument("--solo-sample", type=int, default=256, help="batched form: graphs timed one at a time")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB three times (a plain copy kernel of "
+                         "known size, to calibrate HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
@@ -332,17 +337,17 @@ def main():
     p = L.params(**HEURISTICS[args.heuristics])
     stream = torch.cuda.current_stream()
 
-    def step(profile=False):
+    def step(params, profile=False):
         gr = L.Graph.from_tensors(off, col, w, validate=False, stream=stream)
         if profile:
             gr.profile(True)
-        res = gr.run(p, labels=labels)
+        res = gr.run(params, labels=labels)
         recs = gr.profile_records() if profile else None
         gr.close()
         return res, recs
 
     for i in range(args.warmup):
-        res, _ = step()
+        res, _ = step(p)
         print(f"[bench] warmup {i}: {res.ms_total:.1f} ms K={res.K} q={res.q:.6f}", file=sys.stderr, flush=True)
 
     torch.cuda.synchronize()
@@ -350,7 +355,7 @@ def main():
     entries = 0
     results = []
     for i in range(args.steps):
-        res, _ = step()
+        res, _ = step(p)
         entries += res.sweep_entries
         results.append(res)
     torch.cuda.synchronize()
@@ -360,34 +365,47 @@ def main():
     last = results[-1]
     assert all(r.N == last.N and r.K == last.K for r in results), "steps disagree"
 
-    # one more step, untimed, with HIP events around every launch on the
-    # library's stream: per-kernel durations and algorithmic bytes
-    all_recs = {}
-    prof_steps = 0 if args.no_profile else 1
-    for i in range(prof_steps):
-        res, recs = step(profile=True)
-        assert res.N == last.N and res.K == last.K, "profiled step disagrees"
+    def profiled(params):
+        """One untimed step with HIP events around every launch on the
+        library's stream: per-record launches, ms, algorithmic bytes."""
+        res, recs = step(params, profile=True)
+        out = {}
         for r in recs:
-            a = all_recs.setdefault(r["name"], {"launches": 0, "ms": 0.0, "bytes": 0.0, "entries": 0.0})
-            for k in ("launches", "ms", "bytes", "entries"):
-                a[k] += r[k]
-    sweep_recs = {k: v for k, v in all_recs.items() if k.startswith("sweep") and v["launches"]}
-    roofline = None
-    if sweep_recs:
-        name, r = max(sweep_recs.items(), key=lambda kv: kv[1]["ms"])
-        per_launch_bytes = r["bytes"] / r["launches"]
+            if r["launches"]:
+                out[r["name"]] = {k: r[k] for k in ("launches", "ms", "bytes", "entries")}
+        return res, out
+
+    def roofline_of(recs, run):
+        sweep = {k: v for k, v in recs.items() if k.startswith("sweep")}
+        if not sweep:
+            return None
+        name, r = max(sweep.items(), key=lambda kv: kv[1]["ms"])
+        per_launch = r["bytes"] / r["launches"]
         avg_ms = r["ms"] / r["launches"]
-        achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": load_traffic(name, args.workload, args.heuristics),
-                    "launches": r["launches"], "avg_launch_ms": round(avg_ms, 4),
-                    "algorithmic_bytes_per_launch": round(per_launch_bytes)}
-        tot_ms = sum(v["ms"] for v in sweep_recs.values())
-        tot_b = sum(v["bytes"] for v in sweep_recs.values())
-        roofline["all_sweep_kernels"] = {"ms": round(tot_ms / prof_steps, 3),
-                                         "GBps": round(tot_b / (tot_ms * 1e-3) / 1e9, 1),
-                                         "frac": round(tot_b / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        tot_ms = sum(v["ms"] for v in sweep.values())
+        tot_b = sum(v["bytes"] for v in sweep.values())
+        return {"bound": "hbm", "kernel": name, "run": run, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": load_traffic(name, args.workload, run),
+                "launches": r["launches"], "avg_launch_ms": round(avg_ms, 4),
+                "algorithmic_bytes_per_launch": round(per_launch),
+                "all_sweep_kernels": {"ms": round(tot_ms, 3), "GBps": round(tot_b / (tot_ms * 1e-3) / 1e9, 1),
+                                      "frac": round(tot_b / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+
+    kernels, roofline, roofline_timed = {}, None, None
+    if not args.no_profile:
+        # the bandwidth figure is taken on plain synchronous sweeps (no colour
+        # classes), the timed configuration's own dominant kernel beside it
+        res_t, recs_t = profiled(p)
+        assert res_t.N == last.N and res_t.K == last.K, "profiled step disagrees"
+        kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in recs_t.items()}
+        roofline_timed = roofline_of(recs_t, args.heuristics)
+        if args.heuristics == "plain":
+            roofline = roofline_timed
+        else:
+            _, recs_p = profiled(L.params(**HEURISTICS["plain"]))
+            roofline = roofline_of(recs_p, "plain")
 
     out = {
         "metric": "local-move GTEPS", "value": round(gteps, 4), "unit": "GTEPS", "n_gpus": 1,
@@ -405,11 +423,19 @@ def main():
                    "phase_shape": [[ph.n, ph.nnz, int(ph.colored), ph.num_colors, ph.iterations] for ph in last.phases]},
         "time_split_ms": {"vf": round(last.ms_vf, 2), "color": round(last.ms_color, 2),
                           "sweep": round(last.ms_sweep, 2), "coarsen": round(last.ms_coarsen, 2)},
-        "kernels": {k: {"launches": v["launches"] // max(prof_steps, 1), "ms": round(v["ms"] / max(prof_steps, 1), 3)}
-                    for k, v in all_recs.items() if v["launches"]},
+        "kernels": kernels,
         "roofline": roofline,
+        "roofline_timed_config": roofline_timed,
         "cpu_baseline": None,
     }
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib << 20
+        src = torch.empty(nb, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = nb
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
         out["cpu_baseline"]["gpu_over_cpu"] = round(gteps / out["cpu_baseline"]["value"], 1)

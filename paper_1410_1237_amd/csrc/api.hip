@@ -209,6 +209,9 @@ struct louvain_graph_s {
 
     // coloring
     int32_t *color = nullptr, *jp_cnt = nullptr, *front_a = nullptr, *front_b = nullptr, *counters = nullptr;
+    int32_t *jp_chunk = nullptr;            // two chunk lists
+    uint64_t *jp_bm = nullptr;              // colour bitmaps of long rows (kept zero)
+    int64_t jp_chunk_cap = 0, jp_bm_cap = 0;
     int32_t num_colors = 0;
     bool colored = false;
 
@@ -666,8 +669,8 @@ louvain_status coarsen_current(G *g, const int32_t *comm, int64_t &n_new)
     int64_t nnz_new = 0;
     {
         ProfScope ps(g, PR_COARSEN, 0, (double)g->cur.nnz);
-        lv::coarsen(g->cur, comm, g->orig_map, g->n0, b, g->off_b[dst], g->col_b[dst], g->w_b[dst], &n_new, &nnz_new,
-                    g->scratch, g->st);
+        lv::coarsen(g->cur, comm, g->orig_map, g->n0, b, g->off_b[dst], g->col_b[dst], g->w_b[dst], g->k, g->dscal,
+                    &n_new, &nnz_new, g->scratch, g->st);
     }
     g->cur.n = n_new;
     g->cur.nnz = nnz_new;
@@ -677,7 +680,6 @@ louvain_status coarsen_current(G *g, const int32_t *comm, int64_t &n_new)
     g->cur.wk = lv::W_I64;
     g->cur_buf = dst;
     g->level += 1;
-    lv::degrees(g->cur, g->k, g->dscal, g->st);
     int64_t h[3];
     HIPCHK(g, hipMemcpyAsync(h, g->dscal, sizeof(h), hipMemcpyDeviceToHost, g->st));
     louvain_status s = sync(g);
@@ -693,7 +695,33 @@ louvain_status do_color(G *g, uint64_t seed)
 {
     {
         ProfScope ps(g, PR_COLOR, 0, (double)g->cur.nnz);
-        g->num_colors = lv::color_jp(g->cur, seed, g->color, g->jp_cnt, g->front_a, g->front_b, g->counters, g->st);
+        const int64_t n = g->cur.n;
+        const int64_t pairs = lv::color_chunk_pairs(g->cur), words = lv::color_bitmap_words(g->cur);
+        louvain_status s;
+        if (pairs > g->jp_chunk_cap) {
+            release_buffer(g, g->jp_chunk);
+            if ((s = alloc(g, &g->jp_chunk, 4 * pairs))) return s;
+            g->jp_chunk_cap = pairs;
+        }
+        if (words > g->jp_bm_cap) {
+            release_buffer(g, g->jp_bm);
+            if ((s = alloc(g, &g->jp_bm, words))) return s;
+            g->jp_bm_cap = words;
+            lv::fill<uint64_t>(g->jp_bm, 0, words, g->st);
+        }
+        lv::ColorBufs c;
+        c.color = g->color;
+        c.cnt = g->jp_cnt;
+        c.long_id = g->jp_cnt + n;
+        c.lng[0] = g->jp_cnt + 2 * n;
+        c.lng[1] = g->jp_cnt + 3 * n;
+        c.light[0] = g->front_a;
+        c.light[1] = g->front_b;
+        c.counters = g->counters;
+        c.chunk[0] = g->jp_chunk;
+        c.chunk[1] = g->jp_chunk + 2 * g->jp_chunk_cap;
+        c.bm = (unsigned long long *)g->jp_bm;
+        g->num_colors = lv::color_jp(g->cur, seed, c, g->scratch, g->st);
     }
     louvain_status s = sync(g);
     if (s) return s;
@@ -924,6 +952,7 @@ louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, 
     if ((s = alloc(g, &g->scratch.part, part))) return bail(s);
     g->scratch.part_cap = part;
     if ((s = alloc(g, &g->scratch.scalar, 8))) return bail(s);
+    if ((s = alloc(g, &g->scratch.rep, 8 * lv::RED_REP + 8))) return bail(s);
     g->recs.resize(PR_COUNT);
     for (int r = 0; r < PR_COUNT; ++r) g->recs[r].name = kNames[r];
 
@@ -968,7 +997,7 @@ louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, 
             return bail(LOUVAIN_E_BAD_CSR);
         }
     }
-    lv::degrees(in, g->k0, g->dscal, g->st);
+    lv::degrees(in, g->k0, g->dscal, g->scratch, g->st);
     int64_t h[3];
     if (hipMemcpyAsync(h, g->dscal, sizeof(h), hipMemcpyDeviceToHost, g->st) != hipSuccess ||
         hipStreamSynchronize(g->st) != hipSuccess) {
@@ -1037,7 +1066,7 @@ louvain_status louvain_sweep(louvain_graph_t g, const louvain_params *p, louvain
     }
     i128 S2;
     if ((s = sum_sq(g, g->a, g->cur.n, S2))) return s;
-    lv::internal_weight(g->cur, g->comm_prev, g->dscal + 8, g->st);
+    lv::internal_weight(g->cur, g->comm_prev, g->dscal + 8, g->scratch, g->st);
     int64_t sigma = 0;
     HIPCHK(g, hipMemcpyAsync(&sigma, g->dscal + 8, sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
     if ((s = sync(g))) return s;

@@ -7,23 +7,28 @@
 //
 // Each vertex keeps the count of its uncoloured higher-priority neighbours;
 // colouring a vertex decrements its lower-priority neighbours and those
-// reaching zero form the next round's frontier.  One wavefront colours one
-// frontier vertex with a row of up to 256 entries (64-colour register windows),
-// a 256-thread workgroup one with up to 4096 entries and a 1024-thread
-// workgroup a longer one (LDS bitmap of 4096 colours per window), so every
-// row is read a bounded number of times.  Rounds are launched in batches without host synchronisation: the
-// frontier sizes live in a small device ring indexed by round; round r reads
-// slot r, counts the next frontier into slot r+1 and clears slot r+2 for the
-// round after.
+// reaching zero form the next round's frontier.  The number of rounds is the
+// longest priority-descending path, so a round must be short rather than
+// wide.  One launch per round: one wavefront colours a frontier vertex with a
+// row of up to JP_LIGHT entries (64-colour register windows); longer rows are
+// cut into JP_CHUNK-entry chunks, one workgroup each, which OR the colours of
+// their higher-priority neighbours (below 4096) into the vertex's bitmap in
+// HBM and do their decrements, so a round takes about as long as one chunk.
+// A small second launch turns each long row's bitmap into its colour.
+// Frontier sizes live in a device ring indexed by round, so rounds are
+// launched in batches without host synchronisation: round r reads slot r,
+// counts the next frontier into slot r+1 and clears slot r+2.
 #include "lv.h"
 
 namespace lv {
 
-constexpr int JP_WINDOW_WORDS = 64; // 64 x 64 = 4096 colours per window
-constexpr unsigned JP_GRID = 512;        // light: 2048 waves per round, grid-stride over the frontier
-constexpr unsigned JP_MEDIUM_GRID = 512; // medium: one vertex per 256-thread block, grid-stride
-constexpr unsigned JP_HEAVY_GRID = 128;  // heavy: one vertex per 1024-thread block, grid-stride
-constexpr int64_t JP_RING = 4; // frontier sizes by round: slots 3 (r % JP_RING) + (light, medium, heavy)
+constexpr int64_t JP_LIGHT = 256;         // rows up to this length: one wavefront per vertex
+constexpr int64_t JP_CHUNK = 1024;        // entries of a long row per workgroup
+constexpr int JP_BM_WORDS = 64;           // 64 x 64 = 4096 colours in a long row's bitmap
+constexpr unsigned JP_LIGHT_BLOCKS = 512; // 2048 waves, grid-stride over the light frontier
+constexpr unsigned JP_CHUNK_BLOCKS = 1024;
+constexpr unsigned JP_FINAL_BLOCKS = 64;
+constexpr int64_t JP_RING = 4;            // slots of 3 counts: light, long vertices, chunks
 
 __device__ __forceinline__ uint64_t jp_priority(uint64_t seed, int64_t v)
 {
@@ -33,39 +38,92 @@ __device__ __forceinline__ uint64_t jp_priority(uint64_t seed, int64_t v)
     return z ^ (z >> 31);
 }
 
-// cnt[v] = number of neighbours u != v with pi(u) > pi(v)
+// cnt[v] = number of neighbours u != v with pi(u) > pi(v); each thread sums a
+// run of consecutive entries per row, rows inside the tile are summed in LDS
 __global__ __launch_bounds__(BLOCK) void k_jp_count(Csr g, uint64_t seed, int32_t *cnt)
 {
     __shared__ int64_t s_off[ROWCAP + 1];
     __shared__ int64_t s_meta[2];
+    __shared__ int32_t s_acc[ROWCAP + 1];
     const int64_t e0 = (int64_t)blockIdx.x * ETILE;
     const int64_t e1 = min(e0 + ETILE, g.nnz) - 1;
     TileRows t = tile_rows(g.off, g.n, e0, e1, s_off, s_meta);
-    for (int r = 0; r < EITEMS; ++r) {
-        const int64_t e = e0 + r * BLOCK + threadIdx.x;
-        if (e > e1) break;
-        const int64_t v = tile_row(t, g.off, s_off, e);
-        const int32_t u = g.col[e];
-        if (u == v) continue;
-        if (jp_priority(seed, u) > jp_priority(seed, v)) atomicAdd(&cnt[v], 1);
+    const int64_t nrows = t.rhi - t.rlo + 1;
+    if (t.cached)
+        for (int64_t j = threadIdx.x; j < nrows; j += BLOCK) s_acc[j] = 0;
+    __syncthreads();
+    const int64_t b = e0 + (int64_t)threadIdx.x * EITEMS;
+    const int64_t e_end = min(b + EITEMS, e1 + 1);
+    if (b <= e1) {
+        int64_t row = tile_row(t, g.off, s_off, b);
+        int64_t next = tile_off(t, g.off, s_off, row + 1);
+        uint64_t prow = jp_priority(seed, row);
+        int32_t acc = 0;
+        for (int64_t e = b; e < e_end; ++e) {
+            while (e >= next) {
+                if (acc) {
+                    if (t.cached) atomicAdd(&s_acc[row - t.rlo], acc);
+                    else atomicAdd(&cnt[row], acc);
+                }
+                acc = 0;
+                ++row;
+                next = tile_off(t, g.off, s_off, row + 1);
+                prow = jp_priority(seed, row);
+            }
+            const int32_t u = g.col[e];
+            if (u != row && jp_priority(seed, u) > prow) ++acc;
+        }
+        if (acc) {
+            if (t.cached) atomicAdd(&s_acc[row - t.rlo], acc);
+            else atomicAdd(&cnt[row], acc);
+        }
     }
+    __syncthreads();
+    if (t.cached)
+        for (int64_t j = threadIdx.x; j < nrows; j += BLOCK)
+            if (s_acc[j]) atomicAdd(&cnt[t.rlo + j], s_acc[j]);
 }
 
-// vertices without higher-priority neighbours start the frontier; a vertex
-// with no neighbour other than itself takes colour 0 at once.  Frontier
-// lists are split by row length into light, medium and heavy.
-constexpr int64_t JP_MEDIUM = 256;  // rows above: a 256-thread workgroup
-constexpr int64_t JP_HEAVY = 4096;  // rows above: a 1024-thread workgroup
+// 1 for the vertices whose rows are longer than JP_LIGHT (their ranks, from a
+// scan, index the colour bitmaps)
+__global__ __launch_bounds__(BLOCK) void k_jp_long_flags(const int64_t *off, int64_t n, int32_t *flag)
+{
+    for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK)
+        flag[v] = off[v + 1] - off[v] > JP_LIGHT ? 1 : 0;
+}
 
+// frontier lists of one round
 struct JpLists {
-    int32_t *list[3]; // light, medium, heavy
+    int32_t *light; // vertices
+    int32_t *lng;   // long vertices (coloured after the round)
+    int32_t *chunk; // (vertex, chunk index) pairs of the long vertices
 };
 
-__device__ __forceinline__ void jp_push(const Csr &g, int32_t u, const JpLists &out, int32_t *counts)
+// appends u (where push) to the next frontier; called by every active lane
+// of the wave together: one counter update per wave for the light list
+__device__ __forceinline__ void jp_push(const Csr &g, bool push, int32_t u, const JpLists &out, int32_t *counts)
 {
-    const int64_t d = g.off[u + 1] - g.off[u];
-    const int k = d > JP_HEAVY ? 2 : (d > JP_MEDIUM ? 1 : 0);
-    out.list[k][atomicAdd(&counts[k], 1)] = u;
+    int64_t d = 0;
+    if (push) d = g.off[u + 1] - g.off[u];
+    const bool light = push && d <= JP_LIGHT;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long m = __ballot(light);
+    if (m) {
+        const int leader = __ffsll(m) - 1;
+        int32_t base = 0;
+        if (lane == leader) base = atomicAdd(&counts[0], __popcll(m));
+        base = __shfl(base, leader, 64);
+        if (light) out.light[base + __popcll(m & ((1ull << lane) - 1))] = u;
+    }
+    if (push && !light) {
+        out.lng[atomicAdd(&counts[1], 1)] = u;
+        const int32_t nch = (int32_t)((d + JP_CHUNK - 1) / JP_CHUNK);
+        const int32_t c0 = atomicAdd(&counts[2], nch);
+        for (int32_t j = 0; j < nch; ++j) {
+            out.chunk[2 * (int64_t)(c0 + j)] = u;
+            out.chunk[2 * (int64_t)(c0 + j) + 1] = j;
+        }
+    }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_jp_start(Csr g, const int32_t *cnt, int32_t *color, JpLists out,
@@ -75,44 +133,8 @@ __global__ __launch_bounds__(BLOCK) void k_jp_start(Csr g, const int32_t *cnt, i
         const int64_t b = g.off[v], e = g.off[v + 1];
         const bool alone = (e == b) || (e - b == 1 && g.col[b] == v);
         color[v] = alone ? 0 : -1;
-        if (!alone && cnt[v] == 0) jp_push(g, (int32_t)v, out, ring);
+        jp_push(g, !alone && cnt[v] == 0, (int32_t)v, out, ring);
     }
-}
-
-// smallest colour not used by the higher-priority neighbours of v, computed
-// by the NT threads of the block with an LDS bitmap per window of 4096 colours
-template <int NT>
-__device__ __forceinline__ int32_t jp_mex(const Csr &g, uint64_t seed, int32_t v, uint64_t pv, int64_t b, int64_t e,
-                                          const int32_t *color, unsigned long long *bm, int32_t *s_c)
-{
-    int32_t c = -1;
-    for (int32_t base = 0; c < 0; base += JP_WINDOW_WORDS * 64) {
-        if (threadIdx.x < JP_WINDOW_WORDS) bm[threadIdx.x] = 0;
-        __syncthreads();
-        for (int64_t x = b + threadIdx.x; x < e; x += NT) {
-            const int32_t u = g.col[x];
-            if (u == v || jp_priority(seed, u) < pv) continue;
-            const int32_t cu = color[u] - base;
-            if (cu >= 0 && cu < JP_WINDOW_WORDS * 64) atomicOr(&bm[cu >> 6], 1ull << (cu & 63));
-        }
-        __syncthreads();
-        if (threadIdx.x < 64) {
-            const unsigned long long word = bm[threadIdx.x];
-            const unsigned long long open = __ballot(word != ~0ull);
-            if (threadIdx.x == 0) {
-                int32_t r = -1;
-                if (open) {
-                    const int l = __ffsll(open) - 1;
-                    r = base + l * 64 + __ffsll(~bm[l]) - 1;
-                }
-                *s_c = r;
-            }
-        }
-        __syncthreads();
-        c = *s_c;
-        __syncthreads();
-    }
-    return c;
 }
 
 __device__ __forceinline__ unsigned long long wave_or(unsigned long long x)
@@ -126,64 +148,113 @@ __device__ __forceinline__ unsigned long long wave_or(unsigned long long x)
     return x;
 }
 
-// light rows: one wavefront per frontier vertex, colours in 64-colour register
-// windows OR-reduced across the wave; waves of a block are independent
-__global__ __launch_bounds__(BLOCK) void k_jp_light(Csr g, uint64_t seed, const int32_t *in, int32_t *ring, int64_t r,
-                                                    JpLists out, int32_t *color, int32_t *cnt)
+// smallest colour from `base` on that no higher-priority neighbour of v in
+// [b, e) uses, by one wavefront in 64-colour windows
+__device__ __forceinline__ int32_t jp_wave_mex(const Csr &g, uint64_t seed, int32_t v, uint64_t pv, int64_t b,
+                                               int64_t e, const int32_t *color, int32_t base)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
-    const int64_t nwaves = (int64_t)gridDim.x * (BLOCK / 64);
-    int32_t *cur = ring + 3 * (r % JP_RING);
-    int32_t *next = ring + 3 * ((r + 1) % JP_RING);
-    const int64_t nf = cur[0];
-    if (blockIdx.x == 0 && threadIdx.x < 3) ring[3 * ((r + 2) % JP_RING) + threadIdx.x] = 0;
-    for (int64_t f = wave; f < nf; f += nwaves) {
-        const int32_t v = in[f];
-        const int64_t b = g.off[v], e = g.off[v + 1];
-        const uint64_t pv = jp_priority(seed, v);
-        int32_t c = -1;
-        for (int32_t base = 0; c < 0; base += 64) {
-            unsigned long long used = 0;
-            for (int64_t x = b + lane; x < e; x += 64) {
-                const int32_t u = g.col[x];
-                if (u == v || jp_priority(seed, u) < pv) continue;
-                const int32_t cu = color[u] - base;
-                if (cu >= 0 && cu < 64) used |= 1ull << cu;
-            }
-            used = wave_or(used);
-            if (used != ~0ull) c = base + __ffsll(~used) - 1;
-        }
-        if (lane == 0) color[v] = c;
+    for (;; base += 64) {
+        unsigned long long used = 0;
         for (int64_t x = b + lane; x < e; x += 64) {
             const int32_t u = g.col[x];
-            if (u != v && jp_priority(seed, u) < pv)
-                if (atomicSub(&cnt[u], 1) == 1) jp_push(g, u, out, next);
+            if (u == v || jp_priority(seed, u) < pv) continue;
+            const int32_t cu = color[u] - base;
+            if (cu >= 0 && cu < 64) used |= 1ull << cu;
         }
+        used = wave_or(used);
+        if (used != ~0ull) return base + __ffsll(~used) - 1;
     }
 }
 
-// medium and heavy rows: one NT-thread workgroup per frontier vertex
-template <int NT, int K>
-__global__ __launch_bounds__(NT) void k_jp_block(Csr g, uint64_t seed, const int32_t *in, int32_t *ring, int64_t r,
-                                                 JpLists out, int32_t *color, int32_t *cnt)
+// one round: light vertices by wavefronts (blocks [0, JP_LIGHT_BLOCKS)),
+// chunks of long rows by workgroups (the other blocks)
+__global__ __launch_bounds__(BLOCK) void k_jp_round(Csr g, uint64_t seed, JpLists in, JpLists out, int32_t *ring,
+                                                    int64_t r, int32_t *color, int32_t *cnt, const int32_t *long_id,
+                                                    unsigned long long *bm)
 {
-    __shared__ unsigned long long bm[JP_WINDOW_WORDS];
-    __shared__ int32_t s_c;
-    int32_t *cur = ring + 3 * (r % JP_RING);
+    __shared__ unsigned long long s_bm[JP_BM_WORDS];
+    const int32_t *cur = ring + 3 * (r % JP_RING);
     int32_t *next = ring + 3 * ((r + 1) % JP_RING);
-    const int64_t nf = cur[K];
-    for (int64_t f = blockIdx.x; f < nf; f += gridDim.x) {
-        const int32_t v = in[f];
-        const int64_t b = g.off[v], e = g.off[v + 1];
-        const uint64_t pv = jp_priority(seed, v);
-        const int32_t c = jp_mex<NT>(g, seed, v, pv, b, e, color, bm, &s_c);
-        if (threadIdx.x == 0) color[v] = c;
-        for (int64_t x = b + threadIdx.x; x < e; x += NT) {
-            const int32_t u = g.col[x];
-            if (u != v && jp_priority(seed, u) < pv)
-                if (atomicSub(&cnt[u], 1) == 1) jp_push(g, u, out, next);
+    if (blockIdx.x == 0 && threadIdx.x < 3) ring[3 * ((r + 2) % JP_RING) + threadIdx.x] = 0;
+    const int lane = threadIdx.x & 63;
+    if (blockIdx.x < JP_LIGHT_BLOCKS) {
+        const int64_t nf = cur[0];
+        const int64_t wave = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+        const int64_t nwaves = (int64_t)JP_LIGHT_BLOCKS * (BLOCK / 64);
+        for (int64_t f = wave; f < nf; f += nwaves) {
+            const int32_t v = in.light[f];
+            const int64_t b = g.off[v], e = g.off[v + 1];
+            const uint64_t pv = jp_priority(seed, v);
+            const int32_t c = jp_wave_mex(g, seed, v, pv, b, e, color, 0);
+            if (lane == 0) color[v] = c;
+            for (int64_t x = b + lane; x < e; x += 64) {
+                const int32_t u = g.col[x];
+                const bool ready = u != v && jp_priority(seed, u) < pv && atomicSub(&cnt[u], 1) == 1;
+                jp_push(g, ready, u, out, next);
+            }
         }
+        return;
+    }
+    const int64_t nc = cur[2];
+    for (int64_t q = blockIdx.x - JP_LIGHT_BLOCKS; q < nc; q += gridDim.x - JP_LIGHT_BLOCKS) {
+        const int32_t v = in.chunk[2 * q], j = in.chunk[2 * q + 1];
+        const int64_t b = g.off[v] + (int64_t)j * JP_CHUNK;
+        const int64_t e = min(g.off[v + 1], b + JP_CHUNK);
+        const uint64_t pv = jp_priority(seed, v);
+        if (threadIdx.x < JP_BM_WORDS) s_bm[threadIdx.x] = 0;
+        __syncthreads();
+        // decrements first (every lane of a wave takes part in the push),
+        // colours of the higher-priority neighbours into the LDS bitmap
+        for (int64_t x0 = b; x0 < e; x0 += BLOCK) {
+            const int64_t x = x0 + threadIdx.x;
+            bool ready = false;
+            int32_t u = 0;
+            if (x < e) {
+                u = g.col[x];
+                if (u != v) {
+                    if (jp_priority(seed, u) > pv) {
+                        const int32_t cu = color[u];
+                        if (cu < JP_BM_WORDS * 64) atomicOr(&s_bm[cu >> 6], 1ull << (cu & 63));
+                    } else {
+                        ready = atomicSub(&cnt[u], 1) == 1;
+                    }
+                }
+            }
+            jp_push(g, ready, u, out, next);
+        }
+        __syncthreads();
+        if (threadIdx.x < JP_BM_WORDS && s_bm[threadIdx.x])
+            atomicOr(&bm[(int64_t)long_id[v] * JP_BM_WORDS + threadIdx.x], s_bm[threadIdx.x]);
+        __syncthreads();
+    }
+}
+
+// colours of the round's long vertices from their bitmaps (one wavefront
+// each); a full bitmap (4096 colours taken) continues by 64-colour windows
+__global__ __launch_bounds__(BLOCK) void k_jp_final(Csr g, uint64_t seed, const int32_t *lng, const int32_t *ring,
+                                                    int64_t r, int32_t *color, const int32_t *long_id,
+                                                    unsigned long long *bm)
+{
+    static_assert(JP_BM_WORDS == 64, "one bitmap word per lane");
+    const int64_t nl = ring[3 * (r % JP_RING) + 1];
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    for (int64_t f = wave; f < nl; f += (int64_t)gridDim.x * (BLOCK / 64)) {
+        const int32_t v = lng[f];
+        unsigned long long *w = bm + (int64_t)long_id[v] * JP_BM_WORDS;
+        const unsigned long long word = w[lane];
+        w[lane] = 0; // clean for the next colouring
+        const unsigned long long open = __ballot(word != ~0ull);
+        int32_t c;
+        if (open) {
+            const int l = __ffsll(open) - 1;
+            const unsigned long long wl = __shfl(word, l, 64);
+            c = l * 64 + __ffsll(~wl) - 1;
+        } else {
+            c = jp_wave_mex(g, seed, v, jp_priority(seed, v), g.off[v], g.off[v + 1], color, JP_BM_WORDS * 64);
+        }
+        if (lane == 0) color[v] = c;
     }
 }
 
@@ -192,31 +263,45 @@ __global__ __launch_bounds__(BLOCK) void k_color_max(const int32_t *color, int64
     int32_t m = -1;
     for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK)
         m = max(m, color[v]);
-    atomicMax(out, m);
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) m = max(m, __shfl_xor(m, d, 64));
+    if ((threadIdx.x & 63) == 0 && m >= 0) atomicMax(out, m);
 }
 
-// ring needs 3 JP_RING + 1 entries (<= 16); cnt needs 5n entries (counts, then
-// the medium and heavy frontier lists, two each); front_a / front_b are the
-// light lists (n each)
-int32_t color_jp(const Csr &g, uint64_t seed, int32_t *color, int32_t *cnt, int32_t *front_a, int32_t *front_b,
-                 int32_t *ring, hipStream_t st)
+int64_t color_bitmap_words(const Csr &g)
+{
+    // long rows x bitmap words: a long row has more than JP_LIGHT entries
+    return (g.nnz / JP_LIGHT + 1) * JP_BM_WORDS;
+}
+
+int64_t color_chunk_pairs(const Csr &g)
+{
+    // (vertex, chunk) pairs of one frontier: each long row has at most
+    // 1 + len / JP_CHUNK chunks
+    return g.nnz / JP_CHUNK + g.nnz / JP_LIGHT + 1;
+}
+
+int32_t color_jp(const Csr &g, uint64_t seed, const ColorBufs &c, Scratch &s, hipStream_t st)
 {
     if (g.n == 0) return 0;
-    fill<int32_t>(cnt, 0, g.n, st);
+    int32_t *ring = c.counters;
+    fill<int32_t>(c.cnt, 0, g.n, st);
     fill<int32_t>(ring, 0, 3 * JP_RING + 1, st);
-    if (g.nnz > 0) k_jp_count<<<grid_for(g.nnz, ETILE), BLOCK, 0, st>>>(g, seed, cnt);
     unsigned gv = grid_for(g.n, BLOCK * 4);
-    if (gv > 65536) gv = 65536;
-    JpLists lists[2] = {{{front_a, cnt + g.n, cnt + 3 * g.n}}, {{front_b, cnt + 2 * g.n, cnt + 4 * g.n}}};
-    k_jp_start<<<gv, BLOCK, 0, st>>>(g, cnt, color, lists[0], ring);
+    if (gv > 4096) gv = 4096;
+    k_jp_long_flags<<<gv, BLOCK, 0, st>>>(g.off, g.n, c.long_id);
+    scan_i32_to_i32(c.long_id, c.long_id, g.n, s.scalar, s, st);
+    if (g.nnz > 0) k_jp_count<<<grid_for(g.nnz, ETILE), BLOCK, 0, st>>>(g, seed, c.cnt);
+    JpLists lists[2] = {{c.light[0], c.lng[0], c.chunk[0]}, {c.light[1], c.lng[1], c.chunk[1]}};
+    k_jp_start<<<gv, BLOCK, 0, st>>>(g, c.cnt, c.color, lists[0], ring);
     int64_t r = 0;     // next round to launch
     int64_t batch = 4; // rounds launched per host check, doubled up to 256
     for (;;) {
         for (int64_t i = 0; i < batch; ++i, ++r) {
             const JpLists &in = lists[r & 1], &out = lists[(r + 1) & 1];
-            k_jp_light<<<JP_GRID, BLOCK, 0, st>>>(g, seed, in.list[0], ring, r, out, color, cnt);
-            k_jp_block<BLOCK, 1><<<JP_MEDIUM_GRID, BLOCK, 0, st>>>(g, seed, in.list[1], ring, r, out, color, cnt);
-            k_jp_block<1024, 2><<<JP_HEAVY_GRID, 1024, 0, st>>>(g, seed, in.list[2], ring, r, out, color, cnt);
+            k_jp_round<<<JP_LIGHT_BLOCKS + JP_CHUNK_BLOCKS, BLOCK, 0, st>>>(g, seed, in, out, ring, r, c.color, c.cnt,
+                                                                           c.long_id, c.bm);
+            k_jp_final<<<JP_FINAL_BLOCKS, BLOCK, 0, st>>>(g, seed, in.lng, ring, r, c.color, c.long_id, c.bm);
         }
         int32_t nf[3] = {0, 0, 0};
         hipMemcpyAsync(nf, ring + 3 * (r % JP_RING), 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st);
@@ -226,7 +311,7 @@ int32_t color_jp(const Csr &g, uint64_t seed, int32_t *color, int32_t *cnt, int3
     }
     int32_t *mx_slot = ring + 3 * JP_RING;
     fill<int32_t>(mx_slot, -1, 1, st);
-    k_color_max<<<gv, BLOCK, 0, st>>>(color, g.n, mx_slot);
+    k_color_max<<<gv, BLOCK, 0, st>>>(c.color, g.n, mx_slot);
     int32_t mx = -1;
     hipMemcpyAsync(&mx, mx_slot, sizeof(int32_t), hipMemcpyDeviceToHost, st);
     hipStreamSynchronize(st);

@@ -93,7 +93,7 @@ void validate_entries(const Csr &g, bool full, int32_t *flag, hipStream_t st)
 // combined in LDS when the tile's rows are cached (one global atomic per row
 // and block), else added to k directly.
 template <int WK>
-__global__ __launch_bounds__(BLOCK) void k_degrees(Csr g, int64_t *k, int64_t *stats)
+__global__ __launch_bounds__(BLOCK) void k_degrees(Csr g, int64_t *k, int64_t *rep)
 {
     __shared__ int64_t s_off[ROWCAP + 1];
     __shared__ int64_t s_meta[2];
@@ -140,8 +140,8 @@ __global__ __launch_bounds__(BLOCK) void k_degrees(Csr g, int64_t *k, int64_t *s
     tot = block_total(tot, s_red);
     self = block_total(self, s_red);
     if (threadIdx.x == 0) {
-        atomicAdd((unsigned long long *)&stats[0], (unsigned long long)tot);
-        atomicAdd((unsigned long long *)&stats[2], (unsigned long long)self);
+        rep_add(rep, 0, tot);
+        rep_add(rep, 2, self);
     }
 }
 
@@ -166,18 +166,44 @@ __global__ __launch_bounds__(BLOCK) void k_max(const int64_t *k, int64_t n, int6
     }
 }
 
-void degrees(const Csr &g, int64_t *k, int64_t *stats, hipStream_t st)
+constexpr int REP_FOLD_THREADS = 64 * 8; // one wave per counter, one lane per replica
+
+__global__ __launch_bounds__(REP_FOLD_THREADS) void k_rep_fold(const int64_t *rep, int count, int64_t *out)
+{
+    const int c = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (c >= count) return;
+    int64_t v = rep[8 * lane + c];
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        int lo = __shfl_xor((int)(uint32_t)v, d, 64);
+        int hi = __shfl_xor((int)(v >> 32), d, 64);
+        v += (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    }
+    if (lane == 0) out[c] = v;
+}
+
+void rep_clear(int64_t *rep, hipStream_t st) { fill<int64_t>(rep, 0, 8 * RED_REP, st); }
+
+void rep_fold(const int64_t *rep, int count, int64_t *out, hipStream_t st)
+{
+    static_assert(RED_REP == 64, "one lane per replica");
+    k_rep_fold<<<1, REP_FOLD_THREADS, 0, st>>>(rep, count, out);
+}
+
+void degrees(const Csr &g, int64_t *k, int64_t *stats, Scratch &s, hipStream_t st)
 {
     fill<int64_t>(k, 0, g.n, st);
     fill<int64_t>(stats, 0, 3, st);
+    rep_clear(s.rep, st);
     if (g.nnz > 0) {
         unsigned ge = grid_for(g.nnz, ETILE);
         switch (g.wk) {
-        case W_UNIT: k_degrees<W_UNIT><<<ge, BLOCK, 0, st>>>(g, k, stats); break;
-        case W_I32: k_degrees<W_I32><<<ge, BLOCK, 0, st>>>(g, k, stats); break;
-        default: k_degrees<W_I64><<<ge, BLOCK, 0, st>>>(g, k, stats); break;
+        case W_UNIT: k_degrees<W_UNIT><<<ge, BLOCK, 0, st>>>(g, k, s.rep); break;
+        case W_I32: k_degrees<W_I32><<<ge, BLOCK, 0, st>>>(g, k, s.rep); break;
+        default: k_degrees<W_I64><<<ge, BLOCK, 0, st>>>(g, k, s.rep); break;
         }
     }
+    rep_fold(s.rep, 3, stats, st); // 2m, 0 (the maximum comes next), self-loops
     if (g.n > 0) {
         unsigned gm = grid_for(g.n, BLOCK * 16);
         if (gm > 4096) gm = 4096;
@@ -233,7 +259,7 @@ void sum_squares(const int64_t *a, int64_t n, int64_t *out, Scratch &s, hipStrea
 
 // ---- internal weight of a partition -----------------------------------------
 template <int WK>
-__global__ __launch_bounds__(BLOCK) void k_internal(Csr g, const int32_t *comm, int64_t *out)
+__global__ __launch_bounds__(BLOCK) void k_internal(Csr g, const int32_t *comm, int64_t *rep)
 {
     __shared__ int64_t s_off[ROWCAP + 1];
     __shared__ int64_t s_meta[2];
@@ -249,19 +275,21 @@ __global__ __launch_bounds__(BLOCK) void k_internal(Csr g, const int32_t *comm, 
         if (comm[u] == comm[g.col[e]]) acc += WLoad<WK>::at(g.w, e);
     }
     acc = block_total(acc, s_red);
-    if (threadIdx.x == 0 && acc) atomicAdd((unsigned long long *)out, (unsigned long long)acc);
+    if (threadIdx.x == 0) rep_add(rep, 0, acc);
 }
 
-void internal_weight(const Csr &g, const int32_t *comm, int64_t *out, hipStream_t st)
+void internal_weight(const Csr &g, const int32_t *comm, int64_t *out, Scratch &s, hipStream_t st)
 {
-    fill<int64_t>(out, 0, 1, st);
-    if (g.nnz == 0) return;
-    unsigned ge = grid_for(g.nnz, ETILE);
-    switch (g.wk) {
-    case W_UNIT: k_internal<W_UNIT><<<ge, BLOCK, 0, st>>>(g, comm, out); break;
-    case W_I32: k_internal<W_I32><<<ge, BLOCK, 0, st>>>(g, comm, out); break;
-    default: k_internal<W_I64><<<ge, BLOCK, 0, st>>>(g, comm, out); break;
+    rep_clear(s.rep, st);
+    if (g.nnz > 0) {
+        unsigned ge = grid_for(g.nnz, ETILE);
+        switch (g.wk) {
+        case W_UNIT: k_internal<W_UNIT><<<ge, BLOCK, 0, st>>>(g, comm, s.rep); break;
+        case W_I32: k_internal<W_I32><<<ge, BLOCK, 0, st>>>(g, comm, s.rep); break;
+        default: k_internal<W_I64><<<ge, BLOCK, 0, st>>>(g, comm, s.rep); break;
+        }
     }
+    rep_fold(s.rep, 1, out, st);
 }
 
 // ---- vertex following -----------------------------------------------------------
@@ -335,11 +363,33 @@ __global__ __launch_bounds__(BLOCK) void k_runs(const uint64_t *keys, const int6
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_run_weights(const int64_t *rstart, int64_t nruns, const int64_t *pref,
-                                                       int64_t *w_out)
+// weight of every run (summed entries of one (C(u), C(v)) pair); the
+// diagonal runs (self-loops of the coarse graph) are also summed into rep
+__global__ __launch_bounds__(BLOCK) void k_run_weights(const uint64_t *keys, int bits, const int64_t *rstart,
+                                                       int64_t nruns, const int64_t *pref, int64_t *w_out,
+                                                       int64_t *rep)
 {
-    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < nruns; r += (int64_t)gridDim.x * BLOCK)
-        w_out[r] = pref ? pref[rstart[r + 1]] - pref[rstart[r]] : rstart[r + 1] - rstart[r];
+    __shared__ int64_t s_red[BLOCK / 64];
+    const uint64_t mask = (bits >= 64) ? ~0ull : ((1ull << bits) - 1);
+    int64_t diag = 0;
+    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < nruns; r += (int64_t)gridDim.x * BLOCK) {
+        const int64_t w = pref ? pref[rstart[r + 1]] - pref[rstart[r]] : rstart[r + 1] - rstart[r];
+        w_out[r] = w;
+        const uint64_t key = keys[rstart[r]];
+        if ((key >> bits) == (key & mask)) diag += w;
+    }
+    diag = block_total(diag, s_red);
+    if (threadIdx.x == 0) rep_add(rep, 0, diag);
+}
+
+// weighted degrees of the coarse graph: the sum of the sorted entries of row c
+__global__ __launch_bounds__(BLOCK) void k_coarse_degrees(const int64_t *off, const int64_t *rstart, const int64_t *pref,
+                                                          int64_t n, int64_t *k)
+{
+    for (int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x; c < n; c += (int64_t)gridDim.x * BLOCK) {
+        const int64_t lo = rstart[off[c]], hi = rstart[off[c + 1]];
+        k[c] = pref ? pref[hi] - pref[lo] : hi - lo;
+    }
 }
 
 // coarse row offsets: off[c] = first run whose row is >= c
@@ -361,9 +411,10 @@ static int bits_for(int64_t n)
 }
 
 void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_orig, CoarsenBufs &b,
-             int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *n_new, int64_t *nnz_new, Scratch &s,
-             hipStream_t st)
+             int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *k_out, int64_t *stats, int64_t *n_new,
+             int64_t *nnz_new, Scratch &s, hipStream_t st)
 {
+    fill<int64_t>(stats, 0, 3, st);
     const int64_t n = g.n, nnz = g.nnz;
     // renumber non-empty communities in ascending id
     fill<int32_t>(b.flag, 0, n + 1, st);
@@ -380,6 +431,7 @@ void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_ori
     *n_new = nn;
     if (nnz == 0) {
         fill<int64_t>(off_out, 0, nn + 1, st);
+        fill<int64_t>(k_out, 0, nn, st);
         *nnz_new = 0;
         return;
     }
@@ -408,11 +460,25 @@ void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_ori
     }
     unsigned gw = grid_for(nruns, BLOCK * 4);
     if (gw > 65536) gw = 65536;
-    k_run_weights<<<gw, BLOCK, 0, st>>>(rstart, nruns, pref, w_out);
+    rep_clear(s.rep, st);
+    k_run_weights<<<gw, BLOCK, 0, st>>>(b.keys, bits, rstart, nruns, pref, w_out, s.rep);
     unsigned go = grid_for(nruns + 1, BLOCK * 4);
     if (go > 65536) go = 65536;
     k_row_offsets<<<go, BLOCK, 0, st>>>(b.keys, rstart, nruns, bits, nn, off_out);
     *nnz_new = nruns;
+    // weighted degrees, 2m (the total weight: unchanged by coarsening), the
+    // largest degree and the self-loop total of the coarse graph
+    if (nn > 0) {
+        unsigned gk = grid_for(nn, BLOCK * 4);
+        if (gk > 65536) gk = 65536;
+        k_coarse_degrees<<<gk, BLOCK, 0, st>>>(off_out, rstart, pref, nn, k_out);
+        unsigned gm = grid_for(nn, BLOCK * 16);
+        if (gm > 4096) gm = 4096;
+        k_max<<<gm, BLOCK, 0, st>>>(k_out, nn, stats + 1);
+    }
+    if (pref) hipMemcpyAsync(stats, pref + nnz, sizeof(int64_t), hipMemcpyDeviceToDevice, st);
+    else fill<int64_t>(stats, nnz, 1, st);
+    rep_fold(s.rep, 1, stats + 2, st);
 }
 
 template <int WK>

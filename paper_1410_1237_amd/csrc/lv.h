@@ -119,7 +119,20 @@ struct Scratch {
     int64_t *part = nullptr;   // scan partials
     int64_t part_cap = 0;
     int64_t *scalar = nullptr; // a few device scalars (scan totals etc.)
+    int64_t *rep = nullptr;    // RED_REP x 8 replicated counters (rep_add / rep_fold)
 };
+
+// Block totals summed into one of RED_REP replicas of up to 8 counters
+// (replica r holds counter c at rep[8 r + c], one 64-byte line per replica),
+// so that the blocks of a large launch do not all update one word.
+constexpr int RED_REP = 64;
+__device__ __forceinline__ void rep_add(int64_t *rep, int c, int64_t v)
+{
+    if (v) atomicAdd((unsigned long long *)&rep[8 * (blockIdx.x % RED_REP) + c], (unsigned long long)v);
+}
+// out[c] = sum of the replicas of counter c, for c in [0, count)
+void rep_fold(const int64_t *rep, int count, int64_t *out, hipStream_t st);
+void rep_clear(int64_t *rep, hipStream_t st);
 
 // exclusive scans of n values; *total (device pointer, may be null) gets the sum
 void scan_i32_to_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *total, Scratch &s, hipStream_t st);
@@ -145,11 +158,11 @@ void iota_i32(int32_t *p, int64_t n, hipStream_t st);
 void validate_csr(const Csr &g, int32_t *flag, hipStream_t st);
 void validate_entries(const Csr &g, bool full, int32_t *flag, hipStream_t st);
 // k_i = row sums; stats[0] += sum k, stats[1] = max k (atomic), stats[2] += self-loop weights
-void degrees(const Csr &g, int64_t *k, int64_t *stats, hipStream_t st);
+void degrees(const Csr &g, int64_t *k, int64_t *stats, Scratch &s, hipStream_t st);
 // sum of a_c^2 over c in [0, n) into a 128-bit accumulator (out[0] = lo, out[1] = hi)
 void sum_squares(const int64_t *a, int64_t n, int64_t *out, Scratch &s, hipStream_t st);
 // internal weight of a partition: sum over entries with comm[u] == comm[v]
-void internal_weight(const Csr &g, const int32_t *comm, int64_t *out, hipStream_t st);
+void internal_weight(const Csr &g, const int32_t *comm, int64_t *out, Scratch &s, hipStream_t st);
 // vertex following: map[i] = representative (Sec. 5.3)
 void vf_map(const Csr &g, int32_t *map, hipStream_t st);
 
@@ -160,11 +173,12 @@ struct CoarsenBufs {
     int64_t *vals, *vals_alt;
     int64_t *run;        // nnz (run id of each sorted entry)
 };
-// builds the community graph of g under comm into (off_out, col_out, w_out);
-// returns n' and nnz' (synchronizes); composes orig_map (n_orig entries)
+// builds the community graph of g under comm into (off_out, col_out, w_out)
+// with its weighted degrees k_out and stats = {2m, max degree, self-loop
+// total}; returns n' and nnz' (synchronizes); composes orig_map (n_orig entries)
 void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_orig, CoarsenBufs &b,
-             int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *n_new, int64_t *nnz_new, Scratch &s,
-             hipStream_t st);
+             int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *k_out, int64_t *stats, int64_t *n_new,
+             int64_t *nnz_new, Scratch &s, hipStream_t st);
 // expands weights of g to int64
 void weights_i64(const Csr &g, int64_t *w_out, hipStream_t st);
 
@@ -309,8 +323,20 @@ void local_labels(const int32_t *orig_map, const int32_t *gid0, int64_t n0, cons
 
 // ---- coloring (color.hip) ---------------------------------------------------
 
+// device buffers of a colouring (n = vertices of the graph)
+struct ColorBufs {
+    int32_t *color;          // n: the colours
+    int32_t *cnt;            // n: uncoloured higher-priority neighbours
+    int32_t *long_id;        // n: rank among the rows longer than the light limit
+    int32_t *counters;       // 16: frontier-size ring and the colour maximum
+    int32_t *light[2];       // n each: light frontier lists (ping-pong)
+    int32_t *lng[2];         // n each: long-row frontier lists
+    int32_t *chunk[2];       // 2 x color_chunk_pairs each: (vertex, chunk) pairs
+    unsigned long long *bm;  // color_bitmap_words, zero: colour bitmaps of long rows (left zero)
+};
+int64_t color_bitmap_words(const Csr &g);
+int64_t color_chunk_pairs(const Csr &g);
 // Jones-Plassmann coloring; returns the number of colors (synchronizes)
-int32_t color_jp(const Csr &g, uint64_t seed, int32_t *color, int32_t *cnt, int32_t *front_a, int32_t *front_b,
-                 int32_t *counters, hipStream_t st);
+int32_t color_jp(const Csr &g, uint64_t seed, const ColorBufs &c, Scratch &s, hipStream_t st);
 
 } // namespace lv

@@ -77,3 +77,12 @@ def test_server_config_and_host_rejection():
     with pytest.raises(L.LouvainError) as e:
         L.Server(L.params(), max_inflight_batches=0)
     assert e.value.status == L.E_INVALID_ARG
+
+
+def test_library_has_no_undefined_internal_symbols():
+    # every internal routine the library calls is defined in it (a missing
+    # template instance would only fail when the library is loaded)
+    import subprocess
+    from paper_1410_1237_amd import louvain as L
+    out = subprocess.run(["nm", "-C", "--undefined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    assert "lv::" not in out, out
