@@ -228,7 +228,7 @@ struct louvain_graph_s {
     int64_t *cpre = nullptr, *bpre = nullptr, *xpre = nullptr; // hub prefixes per bin-list position
     int32_t *pkey = nullptr, *boff = nullptr;
     uint64_t *pval = nullptr;
-    int64_t *hpart = nullptr;
+    int64_t *hpart = nullptr, *hself = nullptr;
     int64_t pcap = 0, xcap = 0, qcap = 0;   // pairs, bucket boundaries, buckets allocated
     std::vector<lv::HubArgs> hub_groups;    // per group (e <= s when the group has no hub)
 
@@ -500,9 +500,11 @@ louvain_status build_bins(G *g, bool by_color)
     }
     if (tot[1] > g->qcap) {
         release_buffer(g, g->hpart);
+        release_buffer(g, g->hself);
         const int64_t cap = tot[1] + tot[1] / 4 + 64;
-        if ((s = alloc(g, &g->hpart, lv::HUB_REC * cap))) return s;
+        if ((s = alloc(g, &g->hpart, lv::HUB_REC * cap)) || (s = alloc(g, &g->hself, cap))) return s;
         g->qcap = cap;
+        lv::fill<int64_t>(g->hself, 0, cap, g->st); // the hub decisions leave it zero
     }
     if (!with_hubs.empty()) {
         const int64_t m = (int64_t)idx.size();
@@ -530,6 +532,7 @@ louvain_status build_bins(G *g, bool by_color)
             h.pval = g->pval;
             h.boff = g->boff;
             h.part = g->hpart;
+            h.self = g->hself;
         }
     }
     g->bin_groups = groups;
@@ -539,7 +542,8 @@ louvain_status build_bins(G *g, bool by_color)
 }
 
 // launches the sweep kernels of one group (all bins); per-bin stats slots
-void sweep_group(G *g, int group, int singlet)
+// the sweep arguments of the current state
+lv::SweepArgs sweep_args(G *g, int singlet)
 {
     lv::SweepArgs a;
     a.g = g->cur;
@@ -554,9 +558,14 @@ void sweep_group(G *g, int group, int singlet)
     a.two_m_g = g->b_two_m;
     a.active_g = g->b_active;
     a.gstats = g->b_gstats;
-    a.verts = nullptr;
-    a.count = 0;
     a.stats = g->stats + 10 * lv::STAT_REP;
+    return a;
+}
+
+// decide_hubs = false: the hub decisions are left to the commit of the group
+void sweep_group(G *g, int group, int singlet, bool decide_hubs = true)
+{
+    const lv::SweepArgs a = sweep_args(g, singlet);
     const bool wide = wide_gains(g);
     const bool narrow = g->kmax <= (int64_t)UINT32_MAX; // hub sums e <= k_i fit 32 bits
     lv::FusedBins f;
@@ -584,7 +593,7 @@ void sweep_group(G *g, int group, int singlet)
     }
     if (h.e > h.s) {
         ProfScope ps(g, PR_HUB_AGG, nhub, 0, 0x600);
-        lv::sweep_hub_agg(a, h, wide, narrow, g->st);
+        lv::sweep_hub_agg(a, h, wide, narrow, decide_hubs, g->st);
     }
 }
 
@@ -650,11 +659,13 @@ louvain_status commit_all(G *g)
 louvain_status colored_iteration(G *g, int singlet, SweepSum &sum, lv::SweepStats *host)
 {
     lv::clear_stats(g->stats, lv::NBINS * lv::STAT_REP, g->st);
+    const lv::SweepArgs a = sweep_args(g, singlet);
+    const bool wide = wide_gains(g);
     for (int c = 0; c < g->num_colors; ++c) {
-        sweep_group(g, c, singlet);
+        sweep_group(g, c, singlet, false);
         const int64_t s = g->bin_off[c * 16], e = g->bin_off[c * 16 + 16];
         ProfScope ps(g, PR_COMMIT, 8.0 * (double)(e - s), 0);
-        lv::commit(g->bin_verts + s, e - s, g->comm_prev, g->comm_next, g->k, g->a, g->size, g->st);
+        lv::commit_hubs(a, g->hub_groups[c], g->bin_verts + s, s, e - s, wide, g->st);
     }
     louvain_status st = read_stats(g, sum, host);
     prof_collect(g, host, wbytes(g->cur));

@@ -329,9 +329,16 @@ __global__ __launch_bounds__(BLOCK) void k_compose(int32_t *orig_map, int64_t n_
         orig_map[x] = new_id[comm[orig_map[x]]];
 }
 
+// cmap[v] = new id of the community of v
+__global__ __launch_bounds__(BLOCK) void k_cmap(const int32_t *comm, const int32_t *new_id, int64_t n, int32_t *cmap)
+{
+    for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK)
+        cmap[v] = new_id[comm[v]];
+}
+
 template <int WK, bool HV>
-__global__ __launch_bounds__(BLOCK) void k_coarse_keys(Csr g, const int32_t *comm, const int32_t *new_id, int bits,
-                                                       uint64_t *keys, int64_t *vals)
+__global__ __launch_bounds__(BLOCK) void k_coarse_keys(Csr g, const int32_t *cmap, int bits, uint64_t *keys,
+                                                       int64_t *vals)
 {
     __shared__ int64_t s_off[ROWCAP + 1];
     __shared__ int64_t s_meta[2];
@@ -342,8 +349,8 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_keys(Csr g, const int32_t *com
         const int64_t e = e0 + r * BLOCK + threadIdx.x;
         if (e > e1) break;
         const int64_t u = tile_row(t, g.off, s_off, e);
-        const uint64_t cu = (uint32_t)new_id[comm[u]];
-        const uint64_t cv = (uint32_t)new_id[comm[g.col[e]]];
+        const uint64_t cu = (uint32_t)cmap[u];
+        const uint64_t cv = (uint32_t)cmap[g.col[e]];
         keys[e] = (cu << bits) | cv;
         if (HV) vals[e] = WLoad<WK>::at(g.w, e);
     }
@@ -437,11 +444,13 @@ void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_ori
     }
     const int bits = bits_for(nn > 1 ? nn : 2);
     const bool hv = g.wk != W_UNIT;
+    int32_t *cmap = b.flag; // free after the renumbering scan
+    k_cmap<<<gv, BLOCK, 0, st>>>(comm, b.new_id, n, cmap);
     unsigned ge = grid_for(nnz, ETILE);
     switch (g.wk) {
-    case W_UNIT: k_coarse_keys<W_UNIT, false><<<ge, BLOCK, 0, st>>>(g, comm, b.new_id, bits, b.keys, nullptr); break;
-    case W_I32: k_coarse_keys<W_I32, true><<<ge, BLOCK, 0, st>>>(g, comm, b.new_id, bits, b.keys, b.vals); break;
-    default: k_coarse_keys<W_I64, true><<<ge, BLOCK, 0, st>>>(g, comm, b.new_id, bits, b.keys, b.vals); break;
+    case W_UNIT: k_coarse_keys<W_UNIT, false><<<ge, BLOCK, 0, st>>>(g, cmap, bits, b.keys, nullptr); break;
+    case W_I32: k_coarse_keys<W_I32, true><<<ge, BLOCK, 0, st>>>(g, cmap, bits, b.keys, b.vals); break;
+    default: k_coarse_keys<W_I64, true><<<ge, BLOCK, 0, st>>>(g, cmap, bits, b.keys, b.vals); break;
     }
     radix_sort(b.keys, b.keys_alt, hv ? b.vals : nullptr, b.vals_alt, nnz, 2 * bits, s, st);
     scan_heads(b.keys, b.run, nnz, s.scalar, s, st);

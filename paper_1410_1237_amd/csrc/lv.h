@@ -265,9 +265,12 @@ struct HubArgs {
     void *pval = nullptr;           // uint32 or uint64 per pair (the launch's value width)
     int32_t *boff = nullptr;        // bucket boundaries, P + 1 per chunk
     int64_t *part = nullptr;        // HUB_REC per bucket: best gain (lo, hi), community, e,
-                                    // e_A, distinct communities
+                                    // e_A, distinct communities, size of the best community,
+                                    // a and size of the hub's own community (state read)
+    int64_t *self = nullptr;        // per bucket, used at a hub's first: self-loop weight
+                                    // (written by the chunk holding it, cleared by the decision)
 };
-constexpr int HUB_REC = 8;
+constexpr int HUB_REC = 10;
 
 // vertices of one degree bin for a fused launch
 struct BinRange {
@@ -289,7 +292,12 @@ struct FusedBins {
 bool sweep_small(const SweepArgs &a, FusedBins f, bool wide, hipStream_t st);
 bool sweep_large(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, bool narrow, hipStream_t st);
 bool sweep_all(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, bool narrow, hipStream_t st);
-bool sweep_hub_agg(const SweepArgs &a, const HubArgs &h, bool wide, bool narrow, hipStream_t st);
+// decide = false leaves the hub decisions to commit_hubs
+bool sweep_hub_agg(const SweepArgs &a, const HubArgs &h, bool wide, bool narrow, bool decide, hipStream_t st);
+// commit of a colour class (positions [pos0, pos0 + count) of the sorted
+// vertex list) that first makes the decisions of the class's hubs
+void commit_hubs(const SweepArgs &a, const HubArgs &h, const int32_t *list, int64_t pos0, int64_t count, bool wide,
+                 hipStream_t st);
 // per-vertex degree bin keys for sorting: key = (group << 4) | bin, val = vertex
 void bin_keys(const Csr &g, const int32_t *group, uint64_t *keys, int64_t *vals, hipStream_t st);
 // off[key] = first index of the sorted keys with key >= key, key in [0, nkeys]

@@ -337,7 +337,10 @@ __device__ __forceinline__ void hub_part_tile(const SweepArgs &a, const HubArgs 
     for (int64_t e = beg + threadIdx.x; e < end; e += BLOCK) {
         const int32_t j = a.g.col[e];
         const int64_t w = WLoad<WK>::at(a.g.w, e);
-        if (j == v) continue; // the self-loop is read by the decision
+        if (j == v) { // the only chunk holding the self-loop leaves it for the decision
+            h.self[h.bpre[p]] = w;
+            continue;
+        }
         const int32_t c = a.comm_prev[j];
         uint32_t q = slot_hash(c, 12);
         for (;;) {
@@ -448,52 +451,74 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_all(SweepArgs a, FusedBins f, H
     }
 }
 
-// decisions of the hubs: one thread per hub reduces its bucket records
-// (written by the previous launch) and applies the rule of the other bins
-template <typename GT> __global__ __launch_bounds__(BLOCK) void k_hub_decide(SweepArgs a, HubArgs h)
+// decision of hub p from its bucket records and self-loop slot, by one
+// wavefront (lanes read the records in parallel); reads no community state
+// (the records carry what the rule needs), so it may run while other
+// vertices of its class are being committed.  Returns the decision to all
+// lanes.
+template <typename GT> __device__ __forceinline__ int32_t hub_decide(const SweepArgs &a, const HubArgs &h, int64_t p)
 {
-    const int64_t p = h.s + (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= h.e) return;
+    const int lane = threadIdx.x & 63;
     const int32_t v = h.verts[p];
-    if (!sweeping(a, v)) return;
+    const int32_t A = a.comm_prev[v];
+    const int64_t q0 = h.bpre[p], q1 = h.bpre[p + 1];
     Best<GT> best{0, -1, 0};
-    int64_t eA = 0, distinct = 0;
-    for (int64_t q = h.bpre[p]; q < h.bpre[p + 1]; ++q) {
+    int64_t eA = 0, distinct = 0, size_best = 0;
+    for (int64_t q = q0 + lane; q < q1; q += 64) {
         const int64_t *rec = h.part + HUB_REC * q;
         const i128 g = (i128)(((u128)(uint64_t)rec[1] << 64) | (u128)(uint64_t)rec[0]);
         Best<GT> cand{(GT)g, (int32_t)rec[2], rec[3]};
-        if (better(cand, best)) best = cand;
+        if (better(cand, best)) {
+            best = cand;
+            size_best = rec[6];
+        }
         eA += rec[4];
         distinct += rec[5];
     }
-    // self-loop weight: the row's columns are sorted
-    const int64_t rb = a.g.off[v], re = a.g.off[v + 1];
-    int64_t lo = rb, hi = re, wself = 0;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        const int32_t c = a.g.col[mid];
-        if (c == v) {
-            wself = a.g.wk == W_UNIT ? 1 : (a.g.wk == W_I32 ? (int64_t)((const int32_t *)a.g.w)[mid]
-                                                              : ((const int64_t *)a.g.w)[mid]);
-            break;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        Best<GT> o;
+        o.g = shfl_xor_t(best.g, m, 64);
+        o.c = shfl_xor_t(best.c, m, 64);
+        o.e = shfl_xor_t(best.e, m, 64);
+        const int64_t os = shfl_xor_t(size_best, m, 64);
+        if (better(o, best)) {
+            best = o;
+            size_best = os;
         }
-        if (c < v) lo = mid + 1; else hi = mid;
+        eA += shfl_xor_t(eA, m, 64);
+        distinct += shfl_xor_t(distinct, m, 64);
     }
-    const int32_t A = a.comm_prev[v];
+    const int64_t *rec0 = h.part + HUB_REC * q0;
+    const int64_t aA = rec0[7], sizeA = rec0[8];
+    const int64_t wself = h.self[q0];
     const int64_t kv = a.k[v];
-    const GT stay = (GT)two_m_of(a, v) * (GT)eA - (GT)kv * (GT)(a.a[A] - kv);
+    const GT stay = (GT)two_m_of(a, v) * (GT)eA - (GT)kv * (GT)(aA - kv);
     bool move = best.c >= 0 && best.g > stay;
-    if (move && a.singlet && a.size[A] == 1 && a.size[best.c] == 1 && best.c > A) move = false;
-    a.comm_next[v] = move ? best.c : A;
-    unsigned long long *st = a.gid ? (unsigned long long *)&a.gstats[8 * (int64_t)a.gid[v]]
-                                   : (unsigned long long *)&a.stats[p % STAT_REP].moves;
-    if (move) {
-        atomicAdd(&st[0], 1ull);
-        atomicAdd(&st[2], (unsigned long long)(2 * (best.e - eA)));
+    if (move && a.singlet && sizeA == 1 && size_best == 1 && best.c > A) move = false;
+    const int32_t dest = move ? best.c : A;
+    if (lane == 0) {
+        h.self[q0] = 0;
+        a.comm_next[v] = dest;
+        unsigned long long *st = a.gid ? (unsigned long long *)&a.gstats[8 * (int64_t)a.gid[v]]
+                                       : (unsigned long long *)&a.stats[p % STAT_REP].moves;
+        if (move) {
+            atomicAdd(&st[0], 1ull);
+            atomicAdd(&st[2], (unsigned long long)(2 * (best.e - eA)));
+        }
+        atomicAdd(&st[1], (unsigned long long)(eA + wself));
+        atomicAdd(&st[3], (unsigned long long)distinct);
+        atomicAdd(&st[4], (unsigned long long)(a.g.off[v + 1] - a.g.off[v]));
     }
-    atomicAdd(&st[1], (unsigned long long)(eA + wself));
-    atomicAdd(&st[3], (unsigned long long)distinct);
-    atomicAdd(&st[4], (unsigned long long)(re - rb));
+    return dest;
+}
+
+// one wavefront per hub
+template <typename GT> __global__ __launch_bounds__(BLOCK) void k_hub_decide(SweepArgs a, HubArgs h)
+{
+    const int64_t nw = (int64_t)gridDim.x * (BLOCK / 64);
+    for (int64_t p = h.s + (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); p < h.e; p += nw)
+        if (sweeping(a, h.verts[p])) hub_decide<GT>(a, h, p);
 }
 
 // Pass 2: one block per (hub, bucket).  The bucket's pairs from every chunk
@@ -647,6 +672,9 @@ __global__ __launch_bounds__(HUB_BLOCK2) void k_hub_agg(SweepArgs a, HubArgs h)
         rec[3] = best.e;
         rec[4] = eA;
         rec[5] = distinct;
+        rec[6] = best.c >= 0 ? a.size[best.c] : 0;
+        rec[7] = a.a[A];
+        rec[8] = a.size[A];
     }
 }
 
@@ -741,19 +769,20 @@ bool sweep_all(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, boo
     return true;
 }
 
-bool sweep_hub_agg(const SweepArgs &a, const HubArgs &h, bool wide, bool narrow, hipStream_t st)
+bool sweep_hub_agg(const SweepArgs &a, const HubArgs &h, bool wide, bool narrow, bool decide, hipStream_t st)
 {
     if (h.e <= h.s || h.n_buckets == 0) return false;
     const unsigned g = (unsigned)h.n_buckets;
-    const unsigned gd = grid_for(h.e - h.s, BLOCK);
+    unsigned gd = grid_for(h.e - h.s, BLOCK / 64);
+    if (gd > 1024) gd = 1024;
     if (wide) {
         if (narrow) k_hub_agg<i128, uint32_t><<<g, HUB_BLOCK2, 0, st>>>(a, h);
         else k_hub_agg<i128, unsigned long long><<<g, HUB_BLOCK2, 0, st>>>(a, h);
-        k_hub_decide<i128><<<gd, BLOCK, 0, st>>>(a, h);
+        if (decide) k_hub_decide<i128><<<gd, BLOCK, 0, st>>>(a, h);
     } else {
         if (narrow) k_hub_agg<int64_t, uint32_t><<<g, HUB_BLOCK2, 0, st>>>(a, h);
         else k_hub_agg<int64_t, unsigned long long><<<g, HUB_BLOCK2, 0, st>>>(a, h);
-        k_hub_decide<int64_t><<<gd, BLOCK, 0, st>>>(a, h);
+        if (decide) k_hub_decide<int64_t><<<gd, BLOCK, 0, st>>>(a, h);
     }
     return true;
 }
@@ -880,6 +909,58 @@ void commit(const int32_t *verts, int64_t count, int32_t *comm_prev, const int32
     unsigned gc = grid_for(count, BLOCK * 4);
     if (gc > 65536) gc = 65536;
     k_commit<<<gc, BLOCK, 0, st>>>(verts, count, comm_prev, comm_next, k, a, size);
+}
+
+// commit of a colour class: blocks [0, nb) commit the vertices before the
+// class's hubs (positions [pos0, pos0 + count), hubs last in the class), the
+// other blocks give one wavefront per hub, which decides and commits it
+__device__ __forceinline__ void commit_one(int32_t i, int32_t B, int32_t *comm_prev, const int64_t *k, int64_t *ca,
+                                           int32_t *size)
+{
+    const int32_t A = comm_prev[i];
+    if (A == B) return;
+    const int64_t ki = k[i];
+    atomicAdd((unsigned long long *)&ca[A], (unsigned long long)(-ki));
+    atomicAdd((unsigned long long *)&ca[B], (unsigned long long)ki);
+    atomicSub(&size[A], 1);
+    atomicAdd(&size[B], 1);
+    comm_prev[i] = B;
+}
+
+template <typename GT>
+__global__ __launch_bounds__(BLOCK) void k_commit_hubs(SweepArgs a, HubArgs h, const int32_t *list, int64_t pos0,
+                                                       int64_t count, int64_t nplain, unsigned nb)
+{
+    int32_t *comm_prev = const_cast<int32_t *>(a.comm_prev);
+    int64_t *ca = const_cast<int64_t *>(a.a);
+    int32_t *size = const_cast<int32_t *>(a.size);
+    if (blockIdx.x < nb) {
+        for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < nplain; t += (int64_t)nb * BLOCK) {
+            const int32_t i = list[t];
+            commit_one(i, a.comm_next[i], comm_prev, a.k, ca, size);
+        }
+        return;
+    }
+    const int64_t nw = (int64_t)(gridDim.x - nb) * (BLOCK / 64);
+    for (int64_t t = nplain + (int64_t)(blockIdx.x - nb) * (BLOCK / 64) + (threadIdx.x >> 6); t < count; t += nw) {
+        const int32_t dest = hub_decide<GT>(a, h, pos0 + t);
+        if ((threadIdx.x & 63) == 0) commit_one(list[t], dest, comm_prev, a.k, ca, size);
+    }
+}
+
+void commit_hubs(const SweepArgs &a, const HubArgs &h, const int32_t *list, int64_t pos0, int64_t count, bool wide,
+                 hipStream_t st)
+{
+    if (count <= 0) return;
+    // the class's hubs are its last positions
+    const int64_t nhub = (h.e > h.s) ? h.e - h.s : 0;
+    const int64_t nplain = count - nhub;
+    unsigned nb = grid_for(nplain > 0 ? nplain : 1, BLOCK * 4);
+    if (nb > 65536) nb = 65536;
+    unsigned nh = nhub ? grid_for(nhub, BLOCK / 64) : 0;
+    if (nh > 1024) nh = 1024;
+    if (wide) k_commit_hubs<i128><<<nb + nh, BLOCK, 0, st>>>(a, h, list, pos0, count, nplain, nb);
+    else k_commit_hubs<int64_t><<<nb + nh, BLOCK, 0, st>>>(a, h, list, pos0, count, nplain, nb);
 }
 
 void clear_stats(SweepStats *s, int count, hipStream_t st)
