@@ -58,7 +58,7 @@ def _per_dispatch(path, counter):
     for r in csv.DictReader(open(path)):
         if r.get("Counter_Name") != counter:
             continue
-        d = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        d = int(r.get("Dispatch_Id") or r.get("Correlation_Id"))
         name, val = r["Kernel_Name"], float(r["Counter_Value"])
         prev = out.get(d)
         out[d] = (name, val + (prev[1] if prev else 0.0))
@@ -70,10 +70,10 @@ def traffic(args):
     for counter, path in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
         d = _per_dispatch(path, counter)
         kern = [v for n, v in d.values() if args.kernel in n]
-        copy = [v for n, v in d.values() if args.copy in n]
-        if not kern or not copy:
-            raise SystemExit(f"{counter}: no dispatch of {args.kernel!r} or {args.copy!r}")
-        copy_kib = max(copy)  # the probe is the largest copy of the run
+        copy = [d[i][1] for i in sorted(d) if args.copy in d[i][0]]
+        if not kern or len(copy) < 3:
+            raise SystemExit(f"{counter}: no dispatch of {args.kernel!r} or of the probe {args.copy!r}")
+        copy_kib = sorted(copy[-3:])[1]  # the probe: the last three copies of the run (median)
         factor = copy_kib * 1024.0 / args.copy_bytes  # counter bytes per real byte moved one way
         res[counter] = {"kib_per_dispatch": sum(kern) / len(kern), "dispatches": len(kern),
                         "copy_kib": copy_kib, "factor": factor}
