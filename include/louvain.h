@@ -29,6 +29,11 @@
  *    null stream).  Calls that return host values synchronize that stream.
  *  - A handle is not thread-safe; distinct handles are independent.
  *  - Device memory is owned by the handle and released by louvain_destroy.
+ *  - Repeated launch sequences are captured once per phase as HIP graphs
+ *    and replayed: by default the sweep stage of the batched form.  The
+ *    environment variable LOUVAIN_HIP_GRAPHS, read when a handle is created,
+ *    selects 0 (no capture), 1 (default) or 2 (also the colour classes of an
+ *    iteration, which measured slightly slower than ordinary launches).
  */
 #ifndef LOUVAIN_H
 #define LOUVAIN_H

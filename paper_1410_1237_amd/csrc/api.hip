@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <cstdlib>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -214,6 +215,7 @@ struct louvain_graph_s {
     int64_t jp_chunk_cap = 0, jp_bm_cap = 0;
     int32_t num_colors = 0;
     bool colored = false;
+    bool singleton = false; // state is the singleton partition (no commit since init_state)
 
     // binning
     uint64_t *keys = nullptr, *keys_alt = nullptr;
@@ -229,6 +231,7 @@ struct louvain_graph_s {
     int32_t *pkey = nullptr, *boff = nullptr;
     uint64_t *pval = nullptr;
     int64_t *hpart = nullptr, *hself = nullptr;
+    int32_t *chunk_pos = nullptr, *bucket_pos = nullptr;
     int64_t pcap = 0, xcap = 0, qcap = 0;   // pairs, bucket boundaries, buckets allocated
     std::vector<lv::HubArgs> hub_groups;    // per group (e <= s when the group has no hub)
 
@@ -248,6 +251,19 @@ struct louvain_graph_s {
     // results
     std::vector<louvain_phase_stats> phases;
     std::vector<louvain_iter_stats> iters;
+
+    // launch sequences captured as HIP graphs and replayed while the bins and
+    // buffers they were captured on stay the same (epoch)
+    struct Stage {
+        hipGraphExec_t exec = nullptr;
+        uint64_t epoch = ~0ull;
+    };
+    hipStream_t gst = nullptr;           // private stream: graphs are captured on and launched from it
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    bool graphs_ok = true;               // cleared if a capture is refused (then stages run eagerly)
+    bool graph_colored = false;          // capture the colour classes too (measured slower on MI355X)
+    uint64_t epoch = 0;
+    Stage stage_colored, stage_batch;
 
     // profiling
     bool prof = false;
@@ -302,6 +318,21 @@ template <typename T> louvain_status alloc(G *g, T **p, int64_t count)
 void release_all(G *g)
 {
     if (g->st) (void)hipStreamSynchronize(g->st);
+    if (g->gst) (void)hipStreamSynchronize(g->gst);
+    for (G::Stage *sg : {&g->stage_colored, &g->stage_batch})
+        if (sg->exec) {
+            (void)hipGraphExecDestroy(sg->exec);
+            sg->exec = nullptr;
+        }
+    for (auto &ev : g->gev)
+        if (ev) {
+            (void)hipEventDestroy(ev);
+            ev = nullptr;
+        }
+    if (g->gst) {
+        (void)hipStreamDestroy(g->gst);
+        g->gst = nullptr;
+    }
     for (auto &b : g->owned) pool().put(b.first, b.second, g->dev);
     g->owned.clear();
     for (auto ev : g->event_pool) (void)hipEventDestroy(ev);
@@ -415,6 +446,8 @@ louvain_status init_state(G *g)
     lv::fill<int32_t>(g->size, 1, n, g->st);
     if (n) HIPCHK(g, hipMemcpyAsync(g->a, g->k, n * sizeof(int64_t), hipMemcpyDeviceToDevice, g->st));
     g->sigma_in = g->self;
+    g->singleton = true;
+    ++g->epoch;
     g->colored = false;
     g->num_colors = 0;
     g->bins_valid = false;
@@ -488,8 +521,11 @@ louvain_status build_bins(G *g, bool by_color)
     if (pairs > g->pcap) {
         release_buffer(g, g->pkey);
         release_buffer(g, g->pval);
+        release_buffer(g, g->chunk_pos);
         const int64_t cap = pairs + pairs / 4 + lv::HUB_CHUNK;
-        if ((s = alloc(g, &g->pkey, cap)) || (s = alloc(g, &g->pval, cap))) return s;
+        if ((s = alloc(g, &g->pkey, cap)) || (s = alloc(g, &g->pval, cap)) ||
+            (s = alloc(g, &g->chunk_pos, cap / lv::HUB_CHUNK + 1)))
+            return s;
         g->pcap = cap;
     }
     if (tot[2] > g->xcap) {
@@ -501,12 +537,16 @@ louvain_status build_bins(G *g, bool by_color)
     if (tot[1] > g->qcap) {
         release_buffer(g, g->hpart);
         release_buffer(g, g->hself);
+        release_buffer(g, g->bucket_pos);
         const int64_t cap = tot[1] + tot[1] / 4 + 64;
-        if ((s = alloc(g, &g->hpart, lv::HUB_REC * cap)) || (s = alloc(g, &g->hself, cap))) return s;
+        if ((s = alloc(g, &g->hpart, lv::HUB_REC * cap)) || (s = alloc(g, &g->hself, cap)) ||
+            (s = alloc(g, &g->bucket_pos, cap)))
+            return s;
         g->qcap = cap;
         lv::fill<int64_t>(g->hself, 0, cap, g->st); // the hub decisions leave it zero
     }
     if (!with_hubs.empty()) {
+        lv::hub_owners(g->cpre, g->bpre, n, g->chunk_pos, g->bucket_pos, g->st);
         const int64_t m = (int64_t)idx.size();
         // gather cpre and bpre at the range ends: device scratch in vals_alt (free here)
         int64_t *didx = g->vals_alt, *dout = g->vals_alt + m;
@@ -524,6 +564,8 @@ louvain_status build_bins(G *g, bool by_color)
             h.cpre = g->cpre;
             h.bpre = g->bpre;
             h.xpre = g->xpre;
+            h.chunk_pos = g->chunk_pos;
+            h.bucket_pos = g->bucket_pos;
             h.chunk0 = vals[2 * t];
             h.n_chunks = vals[2 * t + 1] - h.chunk0;
             h.bucket0 = vals[m + 2 * t];
@@ -538,6 +580,61 @@ louvain_status build_bins(G *g, bool by_color)
     g->bin_groups = groups;
     g->bins_colored = by_color;
     g->bins_valid = true;
+    ++g->epoch;
+    return LOUVAIN_OK;
+}
+
+// Runs the launches of f() as one stage.  Outside profiling, and once the
+// state is past the singleton partition, the first call of an epoch captures
+// them (on the private stream) into a HIP graph; every call then launches the
+// graph, ordered after the work already on the handle's stream and before
+// the work that follows.  f() must only enqueue kernels.
+template <class F> louvain_status run_stage(G *g, G::Stage &sg, F f)
+{
+    if (g->prof || !g->graphs_ok || g->singleton || (&sg == &g->stage_colored && !g->graph_colored)) {
+        f();
+        return LOUVAIN_OK;
+    }
+    if (!g->gst) {
+        if (hipStreamCreateWithFlags(&g->gst, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&g->gev[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&g->gev[1], hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            g->graphs_ok = false;
+            f();
+            return LOUVAIN_OK;
+        }
+    }
+    if (!sg.exec || sg.epoch != g->epoch) {
+        if (sg.exec) {
+            (void)hipGraphExecDestroy(sg.exec);
+            sg.exec = nullptr;
+        }
+        hipStream_t main = g->st;
+        hipGraph_t graph = nullptr;
+        g->st = g->gst;
+        hipError_t e = hipStreamBeginCapture(g->gst, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            f();
+            e = hipStreamEndCapture(g->gst, &graph);
+        }
+        g->st = main;
+        if (e == hipSuccess) e = hipGraphInstantiate(&sg.exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            sg.exec = nullptr;
+            g->graphs_ok = false;
+            f();
+            return LOUVAIN_OK;
+        }
+        sg.epoch = g->epoch;
+    }
+    HIPCHK(g, hipEventRecord(g->gev[0], g->st));
+    HIPCHK(g, hipStreamWaitEvent(g->gst, g->gev[0], 0));
+    HIPCHK(g, hipGraphLaunch(sg.exec, g->gst));
+    HIPCHK(g, hipEventRecord(g->gev[1], g->gst));
+    HIPCHK(g, hipStreamWaitEvent(g->st, g->gev[1], 0));
     return LOUVAIN_OK;
 }
 
@@ -554,6 +651,7 @@ lv::SweepArgs sweep_args(G *g, int singlet)
     a.k = g->k;
     a.two_m = g->two_m;
     a.singlet = singlet;
+    a.singleton = g->singleton ? 1 : 0;
     a.gid = g->b_gid;
     a.two_m_g = g->b_two_m;
     a.active_g = g->b_active;
@@ -651,6 +749,7 @@ louvain_status commit_all(G *g)
 {
     ProfScope ps(g, PR_COMMIT, 8.0 * (double)g->cur.n, 0);
     lv::commit(nullptr, g->cur.n, g->comm_prev, g->comm_next, g->k, g->a, g->size, g->st);
+    g->singleton = false;
     return LOUVAIN_OK;
 }
 
@@ -658,16 +757,20 @@ louvain_status commit_all(G *g)
 // state after the classes before it (Sec. 5.4 step 3)
 louvain_status colored_iteration(G *g, int singlet, SweepSum &sum, lv::SweepStats *host)
 {
-    lv::clear_stats(g->stats, lv::NBINS * lv::STAT_REP, g->st);
-    const lv::SweepArgs a = sweep_args(g, singlet);
-    const bool wide = wide_gains(g);
-    for (int c = 0; c < g->num_colors; ++c) {
-        sweep_group(g, c, singlet, false);
-        const int64_t s = g->bin_off[c * 16], e = g->bin_off[c * 16 + 16];
-        ProfScope ps(g, PR_COMMIT, 8.0 * (double)(e - s), 0);
-        lv::commit_hubs(a, g->hub_groups[c], g->bin_verts + s, s, e - s, wide, g->st);
-    }
-    louvain_status st = read_stats(g, sum, host);
+    louvain_status st = run_stage(g, g->stage_colored, [&]() {
+        lv::clear_stats(g->stats, lv::NBINS * lv::STAT_REP, g->st);
+        const lv::SweepArgs a = sweep_args(g, singlet);
+        const bool wide = wide_gains(g);
+        for (int c = 0; c < g->num_colors; ++c) {
+            sweep_group(g, c, singlet, false);
+            const int64_t s = g->bin_off[c * 16], e = g->bin_off[c * 16 + 16];
+            ProfScope ps(g, PR_COMMIT, 8.0 * (double)(e - s), 0);
+            lv::commit_hubs(a, g->hub_groups[c], g->bin_verts + s, s, e - s, wide, g->st);
+            g->singleton = false;
+        }
+    });
+    if (st) return st;
+    st = read_stats(g, sum, host);
     prof_collect(g, host, wbytes(g->cur));
     return st;
 }
@@ -964,6 +1067,14 @@ louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, 
     g->scratch.part_cap = part;
     if ((s = alloc(g, &g->scratch.scalar, 8))) return bail(s);
     if ((s = alloc(g, &g->scratch.rep, 8 * lv::RED_REP + 8))) return bail(s);
+    {
+        // LOUVAIN_HIP_GRAPHS: 0 no graph capture, 1 (default) the batched
+        // sweep stage, 2 also the colour classes of an iteration
+        const char *env = std::getenv("LOUVAIN_HIP_GRAPHS");
+        const int mode = env && env[0] >= '0' && env[0] <= '2' ? env[0] - '0' : 1;
+        g->graphs_ok = mode > 0;
+        g->graph_colored = mode > 1;
+    }
     g->recs.resize(PR_COUNT);
     for (int r = 0; r < PR_COUNT; ++r) g->recs[r].name = kNames[r];
 
@@ -1538,8 +1649,11 @@ louvain_status louvain_batch_run(louvain_batch_t b, const louvain_params *p, int
         }
         HIPCHK(g, hipMemcpyAsync(b->active_d, active.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, g->st));
         for (int sidx = 1;; ++sidx) {
-            lv::fill<int64_t>(b->gstats, 0, 8 * (int64_t)ng, g->st);
-            sweep_group(g, 0, p->singlet_rule);
+            if ((s = run_stage(g, g->stage_batch, [&]() {
+                     lv::fill<int64_t>(b->gstats, 0, 8 * (int64_t)ng, g->st);
+                     sweep_group(g, 0, p->singlet_rule);
+                 })))
+                return s;
             if (ng) HIPCHK(g, hipMemcpyAsync(gst.data(), b->gstats, 8 * ng * sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
             if ((s = sync(g))) return s;
             prof_collect(g, nullptr, 0);
@@ -1590,6 +1704,7 @@ louvain_status louvain_batch_run(louvain_batch_t b, const louvain_params *p, int
                 ProfScope ps(g, PR_COMMIT, 8.0 * (double)g->cur.n, 0);
                 lv::commit_graphs(g->cur.n, g->comm_prev, g->comm_next, g->k, g->a, g->size, b->gid, b->keep_d,
                                   g->st);
+                g->singleton = false;
             }
             if (any_keep) {
                 std::vector<i128> s2;

@@ -228,6 +228,7 @@ struct SweepArgs {
     const int64_t *k = nullptr;
     int64_t two_m = 0;
     int singlet = 1;
+    int singleton = 0;              // every community is its own vertex (comm_prev[j] == j)
     SweepStats *stats = nullptr;
     // batched graphs (gid == null for a single graph): per-vertex graph id,
     // per-graph 2m, per-graph "sweeping" flag and per-graph stats (8 int64
@@ -259,6 +260,8 @@ struct HubArgs {
     const int32_t *verts = nullptr; // sorted vertex list (positions are absolute)
     int64_t s = 0, e = 0;           // hub positions [s, e) of this launch group
     const int64_t *cpre = nullptr, *bpre = nullptr, *xpre = nullptr; // n + 1 each
+    const int32_t *chunk_pos = nullptr;  // per chunk: position of its hub
+    const int32_t *bucket_pos = nullptr; // per bucket: position of its hub
     int64_t chunk0 = 0, n_chunks = 0;   // cpre[s], cpre[e] - cpre[s]
     int64_t bucket0 = 0, n_buckets = 0; // bpre[s], bpre[e] - bpre[s]
     int32_t *pkey = nullptr;        // HUB_CHUNK pairs per chunk
@@ -308,6 +311,9 @@ void narrow_ids(const int64_t *vals, int32_t *out, int64_t n, hipStream_t st);
 // and bucket-boundary entries (n + 1 each; the totals land at index count)
 void hub_prefix(const Csr &g, const int32_t *verts, int64_t count, int64_t *cpre, int64_t *bpre, int64_t *xpre,
                 Scratch &s, hipStream_t st);
+// chunk_pos[c] / bucket_pos[q] = the position whose hub owns chunk c / bucket q
+void hub_owners(const int64_t *cpre, const int64_t *bpre, int64_t count, int32_t *chunk_pos, int32_t *bucket_pos,
+                hipStream_t st);
 void gather_i64(const int64_t *src, const int64_t *idx, int64_t n, int64_t *out, hipStream_t st);
 // community degree/size updates for movers in the list (or all vertices if verts == null)
 void commit(const int32_t *verts, int64_t count, int32_t *comm_prev, const int32_t *comm_next,

@@ -172,8 +172,96 @@ __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint64_t *keys, int6
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-template <bool HV>
-__global__ __launch_bounds__(BLOCK) void k_radix_scatter(const uint64_t *keys, const int64_t *vals, int64_t n,
+// Key-only passes, one tile per block: the tile's keys are ranked stably by digit (wave
+// ballots per round of BLOCK keys), placed in LDS in digit order, and then
+// written out so that consecutive threads write consecutive positions of a
+// digit's run (coalesced) instead of scattering every key.
+__global__ __launch_bounds__(BLOCK) void k_radix_scatter_keys(const uint64_t *keys, int64_t n, int shift,
+                                                             const int64_t *offs, int64_t nb, uint64_t *okeys)
+{
+    __shared__ uint64_t s_key[RADIX_TILE];
+    __shared__ int64_t base_off[256]; // global start of digit d for this block
+    __shared__ int32_t loc[257];      // local start of digit d in the tile
+    __shared__ int32_t run[256];
+    __shared__ int32_t wcnt[BLOCK / 64][256];
+    __shared__ int32_t wsum[BLOCK / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    base_off[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+    loc[tid] = 0;
+    run[tid] = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / 64; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RADIX_TILE;
+    const int64_t cnt = min((int64_t)RADIX_TILE, n - base);
+    // local digit counts
+    for (int r = 0; r < RADIX_ITEMS; ++r) {
+        const int64_t i = base + r * BLOCK + tid;
+        if (i < n) atomicAdd(&loc[(keys[i] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    {
+        // exclusive scan of loc[0..256) (one value per thread)
+        const int32_t v = loc[tid];
+        int32_t inc = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        if (lane == 63) wsum[wid] = inc;
+        __syncthreads();
+        int32_t pre = inc - v;
+        for (int w = 0; w < wid; ++w) pre += wsum[w];
+        __syncthreads();
+        loc[tid] = pre;
+        if (tid == 0) loc[256] = (int32_t)cnt;
+    }
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < RADIX_ITEMS; ++r) {
+        const int64_t i = base + r * BLOCK + tid;
+        const bool valid = i < n;
+        const uint64_t key = valid ? keys[i] : ~0ull;
+        const int d = (int)((key >> shift) & 255);
+        uint64_t peers = ~0ull;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int bit = (d >> b) & 1;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        peers &= __ballot(valid);
+        const int rank = __popcll(peers & lt_mask);
+        if (valid && rank == 0) wcnt[wid][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int32_t pos = loc[d] + run[d] + rank;
+            for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
+            s_key[pos] = key;
+        }
+        __syncthreads();
+        int32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w) {
+            add += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        run[tid] += add;
+        __syncthreads();
+    }
+    // write out: position j of the tile holds digit d = its key's digit
+    for (int32_t j = tid; j < cnt; j += BLOCK) {
+        const uint64_t key = s_key[j];
+        const int d = (int)((key >> shift) & 255);
+        const int64_t pos = base_off[d] + (j - loc[d]);
+        okeys[pos] = key;
+    }
+}
+
+// key-value passes: each key is written straight to its place (a staged
+// tile of keys and values would halve the occupancy)
+__global__ __launch_bounds__(BLOCK) void k_radix_scatter_direct(const uint64_t *keys, const int64_t *vals, int64_t n,
                                                          int shift, const int64_t *offs, int64_t nb,
                                                          uint64_t *okeys, int64_t *ovals)
 {
@@ -193,7 +281,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(const uint64_t *keys, c
         const bool valid = i < n;
         const uint64_t key = valid ? keys[i] : ~0ull;
         int64_t v = 0;
-        if (HV && valid) v = vals[i];
+        if (valid) v = vals[i];
         const int d = (int)((key >> shift) & 255);
         uint64_t peers = ~0ull;
 #pragma unroll
@@ -209,7 +297,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(const uint64_t *keys, c
         for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
         if (valid) {
             okeys[pos] = key;
-            if (HV) ovals[pos] = v;
+            ovals[pos] = v;
         }
         __syncthreads();
         int32_t add = 0;
@@ -245,10 +333,9 @@ void radix_sort(uint64_t *keys, uint64_t *keys_alt, int64_t *vals, int64_t *vals
         k_radix_hist<<<(unsigned)nb, BLOCK, 0, st>>>(src_k, n, shift, hist, nb);
         scan_impl(LoadI64{hist}, hist, 256 * nb, (int64_t *)nullptr, part, st);
         if (vals)
-            k_radix_scatter<true><<<(unsigned)nb, BLOCK, 0, st>>>(src_k, src_v, n, shift, hist, nb, dst_k, dst_v);
+            k_radix_scatter_direct<<<(unsigned)nb, BLOCK, 0, st>>>(src_k, src_v, n, shift, hist, nb, dst_k, dst_v);
         else
-            k_radix_scatter<false><<<(unsigned)nb, BLOCK, 0, st>>>(src_k, nullptr, n, shift, hist, nb, dst_k,
-                                                                   nullptr);
+            k_radix_scatter_keys<<<(unsigned)nb, BLOCK, 0, st>>>(src_k, n, shift, hist, nb, dst_k);
         uint64_t *tk = src_k; src_k = dst_k; dst_k = tk;
         int64_t *tv = src_v; src_v = dst_v; dst_v = tv;
     }

@@ -131,7 +131,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const BinRange &b
             wself += w;
             continue;
         }
-        const int32_t c = a.comm_prev[j];
+        const int32_t c = a.singleton ? j : a.comm_prev[j];
         uint32_t h = slot_hash(c, shift);
         for (;;) {
             int32_t cur = tkey[h];
@@ -243,16 +243,6 @@ constexpr int HUB_CAP2 = 3072;        // distinct keys one pass-2 round may hold
 constexpr int HUB_BLOCK2 = 512;
 constexpr int HUB_SEGS = 1024;        // chunk segments a pass-2 block stages at a time
 
-__device__ __forceinline__ int64_t last_leq(const int64_t *arr, int64_t lo, int64_t hi, int64_t x)
-{
-    // largest p in [lo, hi) with arr[p] <= x (arr non-decreasing, arr[lo] <= x)
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (arr[mid] <= x) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
 // bucket of community c among 2^lp (top bits of the Fibonacci hash)
 __device__ __forceinline__ int hub_bucket(int32_t c, int lp)
 {
@@ -319,7 +309,7 @@ __device__ __forceinline__ void hub_part_tile(const SweepArgs &a, const HubArgs 
     VT *tval = (VT *)(smem + HUB_T1 * sizeof(int32_t));
     int32_t *hist = (int32_t *)(smem + HUB_T1 * (sizeof(int32_t) + sizeof(VT)));
     const int64_t target = h.chunk0 + tile;
-    const int64_t p = last_leq(h.cpre, h.s, h.e, target);
+    const int64_t p = h.chunk_pos[target];
     const int32_t v = h.verts[p];
     if (!sweeping(a, v)) return; // uniform over the block
     const int64_t lc = target - h.cpre[p];
@@ -341,7 +331,7 @@ __device__ __forceinline__ void hub_part_tile(const SweepArgs &a, const HubArgs 
             h.self[h.bpre[p]] = w;
             continue;
         }
-        const int32_t c = a.comm_prev[j];
+        const int32_t c = a.singleton ? j : a.comm_prev[j];
         uint32_t q = slot_hash(c, 12);
         for (;;) {
             int32_t cur = tkey[q];
@@ -537,7 +527,7 @@ __global__ __launch_bounds__(HUB_BLOCK2) void k_hub_agg(SweepArgs a, HubArgs h)
     __shared__ Best<GT> sb[HUB_BLOCK2 / 64];
     __shared__ int64_t se[HUB_BLOCK2 / 64][2];
     const int64_t q = h.bucket0 + blockIdx.x;
-    const int64_t p = last_leq(h.bpre, h.s, h.e, q);
+    const int64_t p = h.bucket_pos[q];
     const int32_t v = h.verts[p];
     if (!sweeping(a, v)) return; // uniform over the block
     const int P = (int)(h.bpre[p + 1] - h.bpre[p]);
@@ -870,6 +860,24 @@ void hub_prefix(const Csr &g, const int32_t *verts, int64_t count, int64_t *cpre
     scan_i64(xpre, xpre, count, xpre + count, s, st);
 }
 
+
+__global__ __launch_bounds__(BLOCK) void k_hub_owners(const int64_t *cpre, const int64_t *bpre, int64_t count,
+                                                      int32_t *chunk_pos, int32_t *bucket_pos)
+{
+    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < count; p += (int64_t)gridDim.x * BLOCK) {
+        for (int64_t c = cpre[p]; c < cpre[p + 1]; ++c) chunk_pos[c] = (int32_t)p;
+        for (int64_t q = bpre[p]; q < bpre[p + 1]; ++q) bucket_pos[q] = (int32_t)p;
+    }
+}
+
+void hub_owners(const int64_t *cpre, const int64_t *bpre, int64_t count, int32_t *chunk_pos, int32_t *bucket_pos,
+                hipStream_t st)
+{
+    if (count <= 0) return;
+    unsigned gb = grid_for(count, BLOCK * 4);
+    if (gb > 65536) gb = 65536;
+    k_hub_owners<<<gb, BLOCK, 0, st>>>(cpre, bpre, count, chunk_pos, bucket_pos);
+}
 
 __global__ __launch_bounds__(BLOCK) void k_gather_i64(const int64_t *src, const int64_t *idx, int64_t n, int64_t *out)
 {

@@ -293,3 +293,17 @@ def test_hub_bucket_overflow(L, O, pi):
     print(f"[parity] overflow hubs n={g.n} nnz={g.nnz} params {PARAM_SETS[pi]}", flush=True)
     res = L.Graph.from_csr(g).run(L.params(**PARAM_SETS[pi]))
     compare_run(res, O.run(g, oracle.Params(**PARAM_SETS[pi])), "overflow hubs")
+
+
+@pytest.mark.parametrize("mode", ["0", "1", "2"])
+def test_graph_capture_modes(L, O, mode, monkeypatch):
+    """Colour-class iterations replayed from a captured HIP graph (mode 2),
+    the default (mode 1) and no capture (mode 0) all give the oracle's run;
+    each phase replays its graph once per iteration after the first, with the
+    library's own synchronisations in between."""
+    monkeypatch.setenv("LOUVAIN_HIP_GRAPHS", mode)
+    p = dict(vf=1, color=1, color_cutoff=1)
+    for g in (GG.rmat(13, 16, wmax=100, seed=6), hub_graph(seed=11, hub_deg=40000, extra=60000, n=50000)):
+        print(f"[parity] graphs={mode} {g.name} n={g.n}", flush=True)
+        res = L.Graph.from_csr(g).run(L.params(**p))
+        compare_run(res, O.run(g, oracle.Params(**p)), f"graphs={mode} {g.name}")
