@@ -484,13 +484,16 @@ void release_buffer(G *g, void *p)
 }
 
 // sorts the current graph's vertices by (group, degree bin); group = colour or none
-louvain_status build_bins(G *g, bool by_color)
+// by_color: one group per colour class; mask_inactive (batched form): the
+// vertices of graphs that stopped sweeping are left out of every bin
+louvain_status build_bins(G *g, bool by_color, bool mask_inactive = false)
 {
     const int64_t n = g->cur.n;
     const int groups = by_color ? g->num_colors : 1;
     const int64_t nkeys = 16 * (int64_t)groups;
     if (nkeys > g->bin_hist_cap) return fail(g, LOUVAIN_E_STATE, "bin key capacity exceeded");
-    lv::bin_keys(g->cur, by_color ? g->color : nullptr, g->keys, g->vals, g->st);
+    lv::bin_keys(g->cur, by_color ? g->color : nullptr, g->keys, g->vals, g->st, mask_inactive ? g->b_gid : nullptr,
+                 mask_inactive ? g->b_active : nullptr);
     lv::radix_sort(g->keys, g->keys_alt, g->vals, g->vals_alt, n, 4 + (by_color ? bits_for(groups) : 0), g->scratch,
                    g->st);
     lv::narrow_ids(g->vals, g->bin_verts, n, g->st);
@@ -1629,7 +1632,6 @@ louvain_status louvain_batch_run(louvain_batch_t b, const louvain_params *p, int
         for (auto &r : b->runs) any |= !r.finished;
         if (!any) break;
         if ((s = batch_nnz(b, nnz))) return s;
-        if ((s = build_bins(g, false))) return s;
         // phase start: every graph from singletons; its Q_0 is its previous phase's Q
         for (int32_t i = 0; i < ng; ++i) {
             B::Run &r = b->runs[i];
@@ -1648,6 +1650,16 @@ louvain_status louvain_batch_run(louvain_batch_t b, const louvain_params *p, int
             r.hit = 0;
         }
         HIPCHK(g, hipMemcpyAsync(b->active_d, active.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, g->st));
+        // the bins hold only the vertices of sweeping graphs; they are rebuilt
+        // whenever that set has halved
+        auto active_vertices = [&]() {
+            int64_t v = 0;
+            for (int32_t i = 0; i < ng; ++i)
+                if (active[i]) v += b->goff[i + 1] - b->goff[i];
+            return v;
+        };
+        if ((s = build_bins(g, false, true))) return s;
+        int64_t binned = active_vertices();
         for (int sidx = 1;; ++sidx) {
             if ((s = run_stage(g, g->stage_batch, [&]() {
                      lv::fill<int64_t>(b->gstats, 0, 8 * (int64_t)ng, g->st);
@@ -1719,6 +1731,11 @@ louvain_status louvain_batch_run(louvain_batch_t b, const louvain_params *p, int
             }
             if (!still) break;
             HIPCHK(g, hipMemcpyAsync(b->active_d, active.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, g->st));
+            const int64_t now = active_vertices();
+            if (2 * now < binned) {
+                if ((s = build_bins(g, false, true))) return s;
+                binned = now;
+            }
         }
         if ((s = sync(g))) return s;
         // rebuild every graph (a finished graph sits at singletons: an identity rebuild)

@@ -302,7 +302,10 @@ bool sweep_hub_agg(const SweepArgs &a, const HubArgs &h, bool wide, bool narrow,
 void commit_hubs(const SweepArgs &a, const HubArgs &h, const int32_t *list, int64_t pos0, int64_t count, bool wide,
                  hipStream_t st);
 // per-vertex degree bin keys for sorting: key = (group << 4) | bin, val = vertex
-void bin_keys(const Csr &g, const int32_t *group, uint64_t *keys, int64_t *vals, hipStream_t st);
+// (batched form: vertices of graphs with active[gid[v]] == 0 go to bin 0,
+// which is never swept)
+void bin_keys(const Csr &g, const int32_t *group, uint64_t *keys, int64_t *vals, hipStream_t st,
+              const int32_t *gid = nullptr, const int32_t *active = nullptr);
 // off[key] = first index of the sorted keys with key >= key, key in [0, nkeys]
 void key_offsets(const uint64_t *keys, int64_t n, int64_t nkeys, int64_t *off, hipStream_t st);
 // vertex ids from sorted bin values (int64 -> int32)

@@ -779,21 +779,23 @@ bool sweep_hub_agg(const SweepArgs &a, const HubArgs &h, bool wide, bool narrow,
 
 // ---- binning ----------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_bin_keys(const int64_t *off, int64_t n, const int32_t *group,
-                                                    uint64_t *keys, int64_t *vals)
+                                                    uint64_t *keys, int64_t *vals, const int32_t *gid,
+                                                    const int32_t *active)
 {
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
-        const int b = degree_bin(off[i + 1] - off[i]);
+        const int b = (gid && !active[gid[i]]) ? 0 : degree_bin(off[i + 1] - off[i]);
         keys[i] = ((uint64_t)(group ? group[i] : 0) << 4) | (uint64_t)b;
         vals[i] = i;
     }
 }
 
-void bin_keys(const Csr &g, const int32_t *group, uint64_t *keys, int64_t *vals, hipStream_t st)
+void bin_keys(const Csr &g, const int32_t *group, uint64_t *keys, int64_t *vals, hipStream_t st, const int32_t *gid,
+              const int32_t *active)
 {
     if (g.n == 0) return;
     unsigned gb = grid_for(g.n, BLOCK * 4);
     if (gb > 65536) gb = 65536;
-    k_bin_keys<<<gb, BLOCK, 0, st>>>(g.off, g.n, group, keys, vals);
+    k_bin_keys<<<gb, BLOCK, 0, st>>>(g.off, g.n, group, keys, vals, gid, active);
 }
 
 // off[key] = first index of sorted keys whose key is >= key, for key in [0, nkeys]
