@@ -261,6 +261,17 @@ louvain_status louvain_batch_init(int32_t num_graphs, const int64_t *graph_off, 
                                   const int32_t *cols, const int32_t *weights, uint32_t flags, void *hip_stream,
                                   louvain_batch_t *out);
 
+/* The same batch from separate host CSRs (graph i: n[i] vertices, nnz[i]
+ * entries, offsets[i], cols[i], weights[i] or NULL, all in the layout of
+ * louvain_init_csr with local vertex ids): the arrays are copied side by side
+ * to device memory and renumbered there, so the caller needs no union CSR.
+ * weights may be NULL (all unit) and any weights[i] may be NULL (unit).
+ * flags: LOUVAIN_VALIDATE only. */
+louvain_status louvain_batch_init_graphs(int32_t num_graphs, const int64_t *n, const int64_t *nnz,
+                                         const int64_t *const *offsets, const int32_t *const *cols,
+                                         const int32_t *const *weights, uint32_t flags, void *hip_stream,
+                                         louvain_batch_t *out);
+
 /* labels_out: graph_off[num_graphs] labels, local to each graph (may be NULL);
  * results: num_graphs records (may be NULL). */
 louvain_status louvain_batch_run(louvain_batch_t b, const louvain_params *params, int32_t *labels_out,
@@ -302,6 +313,7 @@ typedef struct {
     int32_t reserved;
     double t_submit, t_admit, t_done; /* seconds since the server started */
     int64_t batch_id, batch_graphs;   /* the batch that ran the job and its size */
+    double t_packed, t_ready;         /* its batch packed on the host / resident and checked on the device */
 } louvain_job_result;
 
 void louvain_server_config_default(louvain_server_config *cfg);

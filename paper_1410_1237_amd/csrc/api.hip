@@ -27,40 +27,52 @@ namespace {
 
 struct Pool {
     std::mutex mu;
-    std::map<std::pair<int, size_t>, std::vector<void *>> free_;
+    std::map<std::pair<int, size_t>, std::vector<void *>> free_; // (device, size class) -> blocks
     size_t cached = 0;
     static constexpr size_t CAP = (size_t)96 << 30;
 
+    // size classes: 8 per power of two (at most 12.5 % rounding), 256-byte
+    // minimum, so that buffers of nearby sizes are reused
+    static size_t size_class(size_t bytes)
+    {
+        if (bytes <= 256) return 256;
+        const int lg = 63 - __builtin_clzll((unsigned long long)(bytes - 1)); // bytes in (2^lg, 2^(lg+1)]
+        const size_t step = (size_t)1 << (lg - 3);                            // lg >= 8 here
+        return (bytes + step - 1) / step * step;
+    }
+
     hipError_t get(void **p, size_t bytes, int dev)
     {
+        const size_t cls = size_class(bytes);
         {
             std::lock_guard<std::mutex> lk(mu);
-            auto it = free_.find({dev, bytes});
+            auto it = free_.find({dev, cls});
             if (it != free_.end() && !it->second.empty()) {
                 *p = it->second.back();
                 it->second.pop_back();
-                cached -= bytes;
+                cached -= cls;
                 return hipSuccess;
             }
         }
-        hipError_t e = hipMalloc(p, bytes);
+        hipError_t e = hipMalloc(p, cls);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             trim(dev);
-            e = hipMalloc(p, bytes);
+            e = hipMalloc(p, cls);
         }
         return e;
     }
     void put(void *p, size_t bytes, int dev)
     {
         if (!p) return;
+        const size_t cls = size_class(bytes);
         std::lock_guard<std::mutex> lk(mu);
-        if (cached + bytes > CAP) {
+        if (cached + cls > CAP) {
             (void)hipFree(p);
             return;
         }
-        free_[{dev, bytes}].push_back(p);
-        cached += bytes;
+        free_[{dev, cls}].push_back(p);
+        cached += cls;
     }
     void trim(int dev)
     {
@@ -1474,7 +1486,7 @@ louvain_status batch_sums(B *b, const int64_t *x, bool with_self, std::vector<i1
                           std::vector<int64_t> *self)
 {
     G *g = b->g;
-    lv::graph_sums(g->cur, with_self, x, b->goff_d, b->ng, b->gsum, g->st);
+    lv::graph_sums(g->cur, with_self, x, b->gid, b->ng, b->gsum, g->st);
     std::vector<int64_t> h(4 * (size_t)b->ng);
     if (b->ng) HIPCHK(g, hipMemcpyAsync(h.data(), b->gsum, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
     louvain_status s = sync(g);
@@ -1569,6 +1581,84 @@ const char *louvain_batch_last_error(louvain_batch_t b)
 {
     if (!b) return g_init_error.c_str();
     return b->err.empty() ? b->g->err.c_str() : b->err.c_str();
+}
+
+louvain_status louvain_batch_init_graphs(int32_t num_graphs, const int64_t *n, const int64_t *nnz,
+                                         const int64_t *const *offsets, const int32_t *const *cols,
+                                         const int32_t *const *weights, uint32_t flags, void *hip_stream,
+                                         louvain_batch_t *out)
+{
+    g_init_error.clear();
+    if (!out) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (num_graphs < 0 || (num_graphs > 0 && (!n || !nnz || !offsets || !cols)))
+        return fail(nullptr, LOUVAIN_E_INVALID_ARG, "bad graph arrays");
+    if (flags & ~LOUVAIN_VALIDATE) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "host arrays only (VALIDATE allowed)");
+    std::vector<int64_t> goff(num_graphs + 1, 0), eoff(num_graphs + 1, 0);
+    bool weighted = false;
+    for (int32_t i = 0; i < num_graphs; ++i) {
+        if (n[i] < 0 || nnz[i] < 0 || !offsets[i] || (nnz[i] > 0 && !cols[i]))
+            return fail(nullptr, LOUVAIN_E_INVALID_ARG, "bad arrays of graph " + std::to_string(i));
+        if (offsets[i][0] != 0 || offsets[i][n[i]] != nnz[i])
+            return fail(nullptr, LOUVAIN_E_BAD_CSR, "offsets of graph " + std::to_string(i) + " do not span [0, nnz]");
+        goff[i + 1] = goff[i] + n[i];
+        eoff[i + 1] = eoff[i] + nnz[i];
+        weighted |= weights && weights[i];
+    }
+    const int64_t N = goff[num_graphs], E = eoff[num_graphs];
+    if (N >= ((int64_t)1 << 31) - 1) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "n must be below 2^31 - 1");
+    hipStream_t st = (hipStream_t)hip_stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(nullptr, LOUVAIN_E_HIP, "no device");
+    // staging buffers: the union CSR, then the graph and entry offsets
+    const size_t b_off = (N + 1) * sizeof(int64_t), b_col = (E > 0 ? E : 1) * sizeof(int32_t);
+    const size_t b_idx = 2 * (num_graphs + 1) * sizeof(int64_t);
+    void *p_off = nullptr, *p_col = nullptr, *p_w = nullptr, *p_idx = nullptr;
+    auto release = [&]() {
+        if (st) (void)hipStreamSynchronize(st);
+        else (void)hipDeviceSynchronize();
+        pool().put(p_off, b_off, dev);
+        pool().put(p_col, b_col, dev);
+        if (p_w) pool().put(p_w, b_col, dev);
+        pool().put(p_idx, b_idx, dev);
+    };
+    if (pool().get(&p_off, b_off, dev) != hipSuccess || pool().get(&p_col, b_col, dev) != hipSuccess ||
+        (weighted && pool().get(&p_w, b_col, dev) != hipSuccess) || pool().get(&p_idx, b_idx, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        release();
+        return fail(nullptr, LOUVAIN_E_OOM, "staging allocation failed");
+    }
+    int64_t *d_off = (int64_t *)p_off, *d_idx = (int64_t *)p_idx;
+    int32_t *d_col = (int32_t *)p_col, *d_w = (int32_t *)p_w;
+    bool ok = true;
+    for (int32_t i = 0; i < num_graphs && ok; ++i) {
+        if (n[i]) ok &= hipMemcpyAsync(d_off + goff[i], offsets[i], n[i] * sizeof(int64_t), hipMemcpyHostToDevice, st) == hipSuccess;
+        if (nnz[i]) {
+            ok &= hipMemcpyAsync(d_col + eoff[i], cols[i], nnz[i] * sizeof(int32_t), hipMemcpyHostToDevice, st) == hipSuccess;
+            if (weighted) {
+                if (weights[i])
+                    ok &= hipMemcpyAsync(d_w + eoff[i], weights[i], nnz[i] * sizeof(int32_t), hipMemcpyHostToDevice,
+                                         st) == hipSuccess;
+                else
+                    lv::fill<int32_t>(d_w + eoff[i], 1, nnz[i], st);
+            }
+        }
+    }
+    ok = ok && hipMemcpyAsync(d_idx, goff.data(), (num_graphs + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(d_idx + num_graphs + 1, eoff.data(), (num_graphs + 1) * sizeof(int64_t), hipMemcpyHostToDevice,
+                              st) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        release();
+        return fail(nullptr, LOUVAIN_E_HIP, "copy of the graphs failed");
+    }
+    lv::batch_fixup(d_off, N, d_col, E, d_idx, d_idx + num_graphs + 1, num_graphs, st);
+    // the union's last offset is E: graph i's offsets were copied without their final entry
+    lv::fill<int64_t>(d_off + N, E, 1, st);
+    const louvain_status s = louvain_batch_init(num_graphs, goff.data(), E, d_off, d_col, weighted ? d_w : nullptr,
+                                                flags | LOUVAIN_DEVICE_PTRS, hip_stream, out);
+    release();
+    return s;
 }
 
 louvain_status louvain_batch_run(louvain_batch_t b, const louvain_params *p, int32_t *labels_out,

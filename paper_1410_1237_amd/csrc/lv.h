@@ -328,15 +328,18 @@ void graph_ids(const int64_t *goff, int32_t ng, int64_t n, int32_t *gid, hipStre
 // flag := 6 when an entry joins two different graphs
 void cross_edges(const Csr &g, const int32_t *gid, int32_t *flag, hipStream_t st);
 // out[4g..4g+3]: sum x, sum x^2 (lo, hi), self-loop weight (if with_self)
-void graph_sums(const Csr &g, bool with_self, const int64_t *x, const int64_t *goff, int32_t ng, int64_t *out,
+void graph_sums(const Csr &g, bool with_self, const int64_t *x, const int32_t *gid, int32_t ng, int64_t *out,
                 hipStream_t st);
 void commit_graphs(int64_t n, int32_t *comm_prev, int32_t *comm_next, const int64_t *k, int64_t *a, int32_t *size,
                    const int32_t *gid, const int32_t *keep, hipStream_t st);
-void graph_internal(const Csr &g, const int32_t *comm, const int64_t *goff, int32_t ng, int64_t *out, hipStream_t st);
 void new_graph_offsets(const int64_t *goff, int32_t ng, int64_t n, const int32_t *new_id, int64_t total,
                        int64_t *new_goff, hipStream_t st);
 void local_labels(const int32_t *orig_map, const int32_t *gid0, int64_t n0, const int64_t *goff, int32_t *labels,
                   hipStream_t st);
+// per-graph arrays copied side by side -> union CSR (adds each graph's first
+// entry to its offsets and its first vertex to its columns)
+void batch_fixup(int64_t *off, int64_t n, int32_t *col, int64_t nnz, const int64_t *goff, const int64_t *eoff,
+                 int32_t ng, hipStream_t st);
 
 // ---- coloring (color.hip) ---------------------------------------------------
 

@@ -5,7 +5,8 @@
 // a batch from the queue head whenever a worker slot is free and the HBM
 // budget covers the batch's estimated footprint; each batch runs on its own
 // worker thread and HIP stream through the batched form, so batches admitted
-// at different times overlap on the device.  Memory is reserved at admission
+// at different times overlap on the device; a batch's jobs are copied to the
+// device as they are and packed there.  Memory is reserved at admission
 // and returned when the batch completes, which may admit the next jobs.
 // Every job's result is the one it gets alone (the batched form is exact per
 // graph).
@@ -39,7 +40,7 @@ struct Job {
     bool done = false;
     louvain_graph_result res{};
     std::vector<int32_t> labels;
-    double t_submit = 0, t_admit = 0, t_done = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0, t_packed = 0, t_ready = 0;
     int64_t batch_id = -1, batch_graphs = 0;
 };
 
@@ -93,32 +94,30 @@ void run_batch(S *s, std::vector<std::shared_ptr<Job>> batch, int64_t batch_id, 
     hipStream_t st = nullptr;
     (void)hipStreamCreate(&st); // default priority
     const int32_t ng = (int32_t)batch.size();
-    std::vector<int64_t> goff(ng + 1, 0);
-    int64_t nnz = 0;
+    std::vector<int64_t> goff(ng + 1, 0), ns(ng), nnzs(ng);
+    std::vector<const int64_t *> offs(ng);
+    std::vector<const int32_t *> cols(ng), ws(ng);
     bool weighted = false;
     for (int32_t i = 0; i < ng; ++i) {
-        goff[i + 1] = goff[i] + batch[i]->n;
-        nnz += batch[i]->nnz;
-        weighted |= batch[i]->weighted;
+        const Job &j = *batch[i];
+        goff[i + 1] = goff[i] + j.n;
+        ns[i] = j.n;
+        nnzs[i] = j.nnz;
+        offs[i] = j.off.data();
+        cols[i] = j.col.data();
+        ws[i] = j.weighted ? j.w.data() : nullptr;
+        weighted |= j.weighted;
     }
     const int64_t n = goff[ng];
-    std::vector<int64_t> off(n + 1, 0);
-    std::vector<int32_t> col(nnz), w(weighted ? nnz : 0);
-    int64_t e = 0;
-    for (int32_t i = 0; i < ng; ++i) {
-        const Job &j = *batch[i];
-        for (int64_t v = 0; v < j.n; ++v) off[goff[i] + v + 1] = e + j.off[v + 1];
-        for (int64_t x = 0; x < j.nnz; ++x) {
-            col[e + x] = (int32_t)(j.col[x] + goff[i]);
-            if (weighted) w[e + x] = j.weighted ? j.w[x] : 1;
-        }
-        e += j.nnz;
-    }
     std::vector<louvain_graph_result> res(ng);
     std::vector<int32_t> labels(n > 0 ? n : 1);
     louvain_batch_t b = nullptr;
-    louvain_status rc = louvain_batch_init(ng, goff.data(), nnz, off.data(), col.data(), weighted ? w.data() : nullptr,
-                                           LOUVAIN_VALIDATE, st, &b);
+    const double t_packed = s->now();
+    // each job's arrays go to the device as they are; the union is assembled there
+    louvain_status rc = louvain_batch_init_graphs(ng, ns.data(), nnzs.data(), offs.data(), cols.data(),
+                                                  weighted ? ws.data() : nullptr, LOUVAIN_VALIDATE, st, &b);
+    if (rc == LOUVAIN_OK) (void)hipStreamSynchronize(st);
+    const double t_ready = s->now();
     if (rc == LOUVAIN_OK) rc = louvain_batch_run(b, &s->params, labels.data(), 0, res.data());
     std::string msg = rc == LOUVAIN_OK ? "" : louvain_batch_last_error(b);
     louvain_batch_destroy(b);
@@ -134,6 +133,8 @@ void run_batch(S *s, std::vector<std::shared_ptr<Job>> batch, int64_t batch_id, 
                 j.labels.assign(labels.begin() + goff[i], labels.begin() + goff[i + 1]);
             }
             j.t_done = t;
+            j.t_packed = t_packed;
+            j.t_ready = t_ready;
             j.batch_id = batch_id;
             j.batch_graphs = ng;
             j.done = true;
@@ -311,6 +312,8 @@ louvain_status louvain_server_poll(louvain_server_t s, uint64_t ticket, int32_t 
         out->t_done = j.t_done;
         out->batch_id = j.batch_id;
         out->batch_graphs = j.batch_graphs;
+        out->t_packed = j.t_packed;
+        out->t_ready = j.t_ready;
     }
     if (labels_out && j.status == LOUVAIN_OK && !j.labels.empty())
         std::memcpy(labels_out, j.labels.data(), j.labels.size() * sizeof(int32_t));

@@ -85,7 +85,8 @@ class ServerConfig(ctypes.Structure):
 class JobResult(ctypes.Structure):
     _fields_ = [("result", GraphResult), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
-                ("batch_id", ctypes.c_int64), ("batch_graphs", ctypes.c_int64)]
+                ("batch_id", ctypes.c_int64), ("batch_graphs", ctypes.c_int64), ("t_packed", ctypes.c_double),
+                ("t_ready", ctypes.c_double)]
 
 
 _lib = None
@@ -94,7 +95,8 @@ EXPORTS = ["louvain_params_default", "louvain_init_csr", "louvain_vf", "louvain_
            "louvain_coarsen", "louvain_run", "louvain_destroy", "louvain_last_error", "louvain_get_info",
            "louvain_get_state", "louvain_get_graph", "louvain_get_colors", "louvain_get_map", "louvain_profile",
            "louvain_profile_get", "louvain_batch_init", "louvain_batch_run", "louvain_batch_graph_stats",
-           "louvain_batch_destroy", "louvain_batch_last_error", "louvain_server_config_default",
+           "louvain_batch_destroy", "louvain_batch_last_error", "louvain_batch_init_graphs",
+           "louvain_server_config_default",
            "louvain_server_create", "louvain_server_submit", "louvain_server_poll", "louvain_server_release",
            "louvain_server_wait_all", "louvain_server_last_error", "louvain_server_destroy"]
 
@@ -153,6 +155,8 @@ def lib():
     L.louvain_batch_graph_stats.restype = st
     L.louvain_batch_destroy.argtypes = [vp]
     L.louvain_batch_destroy.restype = None
+    L.louvain_batch_init_graphs.argtypes = [i32, vp, vp, vp, vp, vp, u32, vp, ctypes.POINTER(vp)]
+    L.louvain_batch_init_graphs.restype = st
     L.louvain_batch_last_error.argtypes = [vp]
     L.louvain_batch_last_error.restype = ctypes.c_char_p
     L.louvain_server_config_default.argtypes = [ctypes.POINTER(ServerConfig)]
@@ -486,6 +490,35 @@ class Batch:
                                     VALIDATE if validate else 0, stream)
 
     @classmethod
+    def from_graphs(cls, graphs, validate: bool = True, stream=None):
+        """Separate host CSRs, packed on the device (louvain_batch_init_graphs)."""
+        self = cls.__new__(cls)
+        self.graphs = list(graphs)
+        ng = len(self.graphs)
+        keep = []  # contiguous arrays alive until the call returns
+
+        def arr(x, dt):
+            a = np.ascontiguousarray(x, dtype=dt)
+            keep.append(a)
+            return a.ctypes.data
+        ns = np.array([g.n for g in self.graphs], dtype=np.int64)
+        nnz = np.array([g.nnz for g in self.graphs], dtype=np.int64)
+        P = ctypes.c_void_p * max(ng, 1)
+        offs = P(*[arr(g.offsets, np.int64) for g in self.graphs])
+        cols = P(*[arr(g.cols, np.int32) if g.nnz else None for g in self.graphs])
+        weighted = any(g.weights is not None for g in self.graphs)
+        ws = P(*[arr(g.weights, np.int32) if g.weights is not None else None for g in self.graphs]) if weighted else None
+        self.goff = np.zeros(ng + 1, dtype=np.int64)
+        self.goff[1:] = np.cumsum(ns)
+        h = ctypes.c_void_p()
+        st = lib().louvain_batch_init_graphs(ng, ns.ctypes.data, nnz.ctypes.data, offs, cols, ws,
+                                             VALIDATE if validate else 0, _stream_ptr(stream), ctypes.byref(h))
+        if st != OK:
+            raise LouvainError(st, lib().louvain_batch_last_error(None).decode())
+        self.h = h.value
+        return self
+
+    @classmethod
     def from_union(cls, graph_off, offsets, cols, weights=None, device=True, stream=None):
         """Device tensors (torch) of a union CSR already in HBM."""
         self = cls.__new__(cls)
@@ -566,6 +599,8 @@ class JobInfo:
     t_done: float
     batch_id: int
     batch_graphs: int
+    t_packed: float = 0.0
+    t_ready: float = 0.0
 
     @property
     def latency(self) -> float:
@@ -630,7 +665,8 @@ class Server:
         return JobInfo(ticket=ticket, status=r.status, labels=None if out is None else out[:n],
                        K=g.num_communities, N=g.q_num.value(), D=g.q_den.value(), q=g.q, n_vf=g.n_vf,
                        phases=g.phases, iterations=g.iterations, t_submit=r.t_submit, t_admit=r.t_admit,
-                       t_done=r.t_done, batch_id=r.batch_id, batch_graphs=r.batch_graphs)
+                       t_done=r.t_done, batch_id=r.batch_id, batch_graphs=r.batch_graphs, t_packed=r.t_packed,
+                       t_ready=r.t_ready)
 
     def release(self, ticket: int):
         _ = lib().louvain_server_release(self.h, ticket)

@@ -85,3 +85,19 @@ def test_batch_rejects(L):
     with pytest.raises(L.LouvainError):
         b.run(L.params(color=1))
     b.close()
+
+
+def test_batch_from_separate_graphs(L, O):
+    """louvain_batch_init_graphs (per-graph host arrays packed on the device)
+    gives the same runs as the union path and the oracle, with empty graphs,
+    unweighted graphs among weighted ones and hubs."""
+    gs = mixed_graphs()
+    b1 = L.Batch.from_graphs(gs)
+    r1 = b1.run(L.params())
+    b1.close()
+    b2 = L.Batch(gs)
+    r2 = b2.run(L.params())
+    b2.close()
+    for g, x, y in zip(gs, r1, r2):
+        assert np.array_equal(x.labels, y.labels) and (x.N, x.D, x.K) == (y.N, y.D, y.K), g.name
+        compare_run(x, O.run(g, oracle.Params()), g.name)

@@ -86,3 +86,22 @@ def test_library_has_no_undefined_internal_symbols():
     from paper_1410_1237_amd import louvain as L
     out = subprocess.run(["nm", "-C", "--undefined-only", L.LIB_PATH], capture_output=True, text=True).stdout
     assert "lv::" not in out, out
+
+
+def test_batch_init_graphs_host_rejection():
+    # rejected on the host before any device call
+    import ctypes
+    import numpy as np
+    from paper_1410_1237_amd import louvain as L
+    off = np.array([1, 2], dtype=np.int64)  # must start at 0
+    col = np.array([0], dtype=np.int32)
+    n = np.array([1], dtype=np.int64)
+    nnz = np.array([1], dtype=np.int64)
+    P = ctypes.c_void_p * 1
+    h = ctypes.c_void_p()
+    st = L.lib().louvain_batch_init_graphs(1, n.ctypes.data, nnz.ctypes.data, P(off.ctypes.data), P(col.ctypes.data),
+                                           None, 0, None, ctypes.byref(h))
+    assert st == L.E_BAD_CSR
+    st = L.lib().louvain_batch_init_graphs(1, n.ctypes.data, nnz.ctypes.data, P(off.ctypes.data), P(col.ctypes.data),
+                                           None, L.DEVICE_PTRS, None, ctypes.byref(h))
+    assert st == L.E_INVALID_ARG
