@@ -194,11 +194,17 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter_keys(const uint64_t *ke
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RADIX_TILE;
     const int64_t cnt = min((int64_t)RADIX_TILE, n - base);
-    // local digit counts
+    // the tile's keys, all loads issued before any is used
+    uint64_t kr[RADIX_ITEMS];
+#pragma unroll
     for (int r = 0; r < RADIX_ITEMS; ++r) {
         const int64_t i = base + r * BLOCK + tid;
-        if (i < n) atomicAdd(&loc[(keys[i] >> shift) & 255], 1);
+        kr[r] = i < n ? keys[i] : ~0ull;
     }
+    // local digit counts
+#pragma unroll
+    for (int r = 0; r < RADIX_ITEMS; ++r)
+        if (base + r * BLOCK + tid < n) atomicAdd(&loc[(kr[r] >> shift) & 255], 1);
     __syncthreads();
     {
         // exclusive scan of loc[0..256) (one value per thread)
@@ -219,10 +225,11 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter_keys(const uint64_t *ke
     }
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
     for (int r = 0; r < RADIX_ITEMS; ++r) {
         const int64_t i = base + r * BLOCK + tid;
         const bool valid = i < n;
-        const uint64_t key = valid ? keys[i] : ~0ull;
+        const uint64_t key = kr[r];
         const int d = (int)((key >> shift) & 255);
         uint64_t peers = ~0ull;
 #pragma unroll
@@ -259,30 +266,63 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter_keys(const uint64_t *ke
     }
 }
 
-// key-value passes: each key is written straight to its place (a staged
-// tile of keys and values would halve the occupancy)
-__global__ __launch_bounds__(BLOCK) void k_radix_scatter_direct(const uint64_t *keys, const int64_t *vals, int64_t n,
-                                                         int shift, const int64_t *offs, int64_t nb,
-                                                         uint64_t *okeys, int64_t *ovals)
+// Key-value passes: the same ranking; keys, then values, go through one LDS
+// staging buffer in digit order (local positions kept in registers) so both
+// are written out in runs.
+__global__ __launch_bounds__(BLOCK) void k_radix_scatter_kv(const uint64_t *keys, const int64_t *vals, int64_t n,
+                                                          int shift, const int64_t *offs, int64_t nb,
+                                                          uint64_t *okeys, int64_t *ovals)
 {
+    __shared__ uint64_t s_buf[RADIX_TILE];
+    __shared__ uint8_t s_dig[RADIX_TILE];
     __shared__ int64_t base_off[256];
+    __shared__ int32_t loc[257];
     __shared__ int32_t run[256];
     __shared__ int32_t wcnt[BLOCK / 64][256];
+    __shared__ int32_t wsum[BLOCK / 64];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     base_off[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+    loc[tid] = 0;
     run[tid] = 0;
 #pragma unroll
     for (int w = 0; w < BLOCK / 64; ++w) wcnt[w][tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RADIX_TILE;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t cnt = min((int64_t)RADIX_TILE, n - base);
+    uint64_t kr[RADIX_ITEMS];
+    int64_t vr[RADIX_ITEMS];
+#pragma unroll
     for (int r = 0; r < RADIX_ITEMS; ++r) {
         const int64_t i = base + r * BLOCK + tid;
-        const bool valid = i < n;
-        const uint64_t key = valid ? keys[i] : ~0ull;
-        int64_t v = 0;
-        if (valid) v = vals[i];
-        const int d = (int)((key >> shift) & 255);
+        kr[r] = i < n ? keys[i] : ~0ull;
+        vr[r] = i < n ? vals[i] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < RADIX_ITEMS; ++r)
+        if (base + r * BLOCK + tid < n) atomicAdd(&loc[(kr[r] >> shift) & 255], 1);
+    __syncthreads();
+    {
+        const int32_t v = loc[tid];
+        int32_t inc = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        if (lane == 63) wsum[wid] = inc;
+        __syncthreads();
+        int32_t pre = inc - v;
+        for (int w = 0; w < wid; ++w) pre += wsum[w];
+        __syncthreads();
+        loc[tid] = pre;
+    }
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int32_t pr[RADIX_ITEMS];
+#pragma unroll
+    for (int r = 0; r < RADIX_ITEMS; ++r) {
+        const bool valid = base + r * BLOCK + tid < n;
+        const int d = (int)((kr[r] >> shift) & 255);
         uint64_t peers = ~0ull;
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -290,15 +330,13 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter_direct(const uint64_t *
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
+        peers &= __ballot(valid);
         const int rank = __popcll(peers & lt_mask);
-        if (rank == 0) wcnt[wid][d] = __popcll(peers);
+        if (valid && rank == 0) wcnt[wid][d] = __popcll(peers);
         __syncthreads();
-        int64_t pos = base_off[d] + run[d] + rank;
+        int32_t pos = loc[d] + run[d] + rank;
         for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
-        if (valid) {
-            okeys[pos] = key;
-            ovals[pos] = v;
-        }
+        pr[r] = valid ? pos : -1;
         __syncthreads();
         int32_t add = 0;
 #pragma unroll
@@ -308,6 +346,28 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter_direct(const uint64_t *
         }
         run[tid] += add;
         __syncthreads();
+    }
+    // keys
+#pragma unroll
+    for (int r = 0; r < RADIX_ITEMS; ++r)
+        if (pr[r] >= 0) {
+            s_buf[pr[r]] = kr[r];
+            s_dig[pr[r]] = (uint8_t)((kr[r] >> shift) & 255);
+        }
+    __syncthreads();
+    for (int32_t j = tid; j < cnt; j += BLOCK) {
+        const int d = s_dig[j];
+        okeys[base_off[d] + (j - loc[d])] = s_buf[j];
+    }
+    __syncthreads();
+    // values
+#pragma unroll
+    for (int r = 0; r < RADIX_ITEMS; ++r)
+        if (pr[r] >= 0) s_buf[pr[r]] = (uint64_t)vr[r];
+    __syncthreads();
+    for (int32_t j = tid; j < cnt; j += BLOCK) {
+        const int d = s_dig[j];
+        ovals[base_off[d] + (j - loc[d])] = (int64_t)s_buf[j];
     }
 }
 
@@ -333,7 +393,7 @@ void radix_sort(uint64_t *keys, uint64_t *keys_alt, int64_t *vals, int64_t *vals
         k_radix_hist<<<(unsigned)nb, BLOCK, 0, st>>>(src_k, n, shift, hist, nb);
         scan_impl(LoadI64{hist}, hist, 256 * nb, (int64_t *)nullptr, part, st);
         if (vals)
-            k_radix_scatter_direct<<<(unsigned)nb, BLOCK, 0, st>>>(src_k, src_v, n, shift, hist, nb, dst_k, dst_v);
+            k_radix_scatter_kv<<<(unsigned)nb, BLOCK, 0, st>>>(src_k, src_v, n, shift, hist, nb, dst_k, dst_v);
         else
             k_radix_scatter_keys<<<(unsigned)nb, BLOCK, 0, st>>>(src_k, n, shift, hist, nb, dst_k);
         uint64_t *tk = src_k; src_k = dst_k; dst_k = tk;
