@@ -34,6 +34,11 @@
  *    environment variable LOUVAIN_HIP_GRAPHS, read when a handle is created,
  *    selects 0 (no capture), 1 (default) or 2 (also the colour classes of an
  *    iteration, which measured slightly slower than ordinary launches).
+ *  - Lanes per vertex of the degree bins are autotuned: at the start of a
+ *    phase, a bin of a kind and size not seen before in the process is swept
+ *    once per candidate (without committing) and the fastest is kept for the
+ *    process; LOUVAIN_AUTOTUNE=0 keeps the defaults and LOUVAIN_LANES=l1,l2,..
+ *    fixes them for bins 1, 2, ...  Results do not depend on the choice.
  */
 #ifndef LOUVAIN_H
 #define LOUVAIN_H

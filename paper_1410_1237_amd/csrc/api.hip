@@ -13,6 +13,7 @@
 #include <map>
 #include <cstdlib>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -228,6 +229,8 @@ struct louvain_graph_s {
     int32_t num_colors = 0;
     bool colored = false;
     bool singleton = false; // state is the singleton partition (no commit since init_state)
+    int lanes[9] = {0, 4, 8, 16, 32, 64, 64, 256, 256}; // lanes per vertex of bins 1..8 (tuned)
+    bool tune = true;       // LOUVAIN_AUTOTUNE=0 keeps the default lanes
 
     // binning
     uint64_t *keys = nullptr, *keys_alt = nullptr;
@@ -496,6 +499,8 @@ void release_buffer(G *g, void *p)
 }
 
 // sorts the current graph's vertices by (group, degree bin); group = colour or none
+louvain_status tune_lanes(G *g);
+
 // by_color: one group per colour class; mask_inactive (batched form): the
 // vertices of graphs that stopped sweeping are left out of every bin
 louvain_status build_bins(G *g, bool by_color, bool mask_inactive = false)
@@ -596,6 +601,9 @@ louvain_status build_bins(G *g, bool by_color, bool mask_inactive = false)
     g->bins_colored = by_color;
     g->bins_valid = true;
     ++g->epoch;
+    // lanes per vertex, chosen at the start of a phase (singleton state) from
+    // the process-wide choices, timing the ones not made yet
+    if (g->tune && g->singleton && !g->prof) return tune_lanes(g);
     return LOUVAIN_OK;
 }
 
@@ -688,6 +696,7 @@ void sweep_group(G *g, int group, int singlet, bool decide_hubs = true)
         f.bins[b].verts = g->bin_verts + s;
         f.bins[b].count = e - s;
         f.bins[b].stats = g->stats + b * lv::STAT_REP;
+        f.lanes[b] = g->lanes[b];
         (b <= 5 ? cnt_small : cnt_large) += (double)(e - s);
     }
     const lv::HubArgs &h = g->hub_groups[group];
@@ -708,6 +717,90 @@ void sweep_group(G *g, int group, int singlet, bool decide_hubs = true)
         ProfScope ps(g, PR_HUB_AGG, nhub, 0, 0x600);
         lv::sweep_hub_agg(a, h, wide, narrow, decide_hubs, g->st);
     }
+}
+
+// ---- autotuning of the lanes per vertex ---------------------------------------
+// Process-wide choices by (device, weight kind, bin, log2 of the bin's
+// vertices): the first handle that sees a bin of that kind and size times
+// every choice of kLaneChoices on it and keeps the fastest.
+struct LaneCache {
+    std::mutex mu;
+    std::map<std::tuple<int, int, int, int>, int> lanes;
+};
+LaneCache &lane_cache()
+{
+    static LaneCache *c = new LaneCache(); // lives until process end
+    return *c;
+}
+
+int lg_bucket(int64_t x)
+{
+    int b = 0;
+    while (((int64_t)1 << (b + 1)) <= x) ++b;
+    return b;
+}
+
+// Chooses g->lanes for the bins of group 0.  A trial is one sweep launch of
+// that bin alone: it writes comm_next of those vertices and statistics, and
+// nothing else (no commit), so the state is unchanged; the statistics are
+// cleared before every real sweep.
+louvain_status tune_lanes(G *g)
+{
+    constexpr int64_t MIN_VERTICES = 16384; // smaller bins keep the default
+    const lv::SweepArgs a = sweep_args(g, 1);
+    const bool wide = wide_gains(g);
+    const bool narrow = g->kmax <= (int64_t)UINT32_MAX;
+    const lv::HubArgs none;
+    for (int b = 1; b <= 6; ++b) {
+        const int64_t s = g->bin_off[b], e = g->bin_off[b + 1];
+        if (e - s < MIN_VERTICES || lv::kLaneChoices[b][1] == 0) continue;
+        const auto key = std::make_tuple(g->dev, (int)g->cur.wk, b, lg_bucket(e - s));
+        {
+            std::lock_guard<std::mutex> lk(lane_cache().mu);
+            auto it = lane_cache().lanes.find(key);
+            if (it != lane_cache().lanes.end()) {
+                g->lanes[b] = it->second;
+                continue;
+            }
+        }
+        int best = g->lanes[b];
+        float best_ms = 1e30f;
+        for (int c = 0; c < 4 && lv::kLaneChoices[b][c]; ++c) {
+            lv::FusedBins f;
+            f.bins[b].verts = g->bin_verts + s;
+            f.bins[b].count = e - s;
+            f.bins[b].stats = g->stats + b * lv::STAT_REP;
+            f.lanes[b] = lv::kLaneChoices[b][c];
+            float ms_min = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) { // the first is a warm-up
+                hipEvent_t e0 = take_event(g), e1 = take_event(g);
+                HIPCHK(g, hipEventRecord(e0, g->st));
+                if (b <= 5) lv::sweep_small(a, f, wide, g->st);
+                else lv::sweep_large(a, f, none, wide, narrow, g->st);
+                HIPCHK(g, hipEventRecord(e1, g->st));
+                HIPCHK(g, hipEventSynchronize(e1));
+                float ms = 0;
+                HIPCHK(g, hipEventElapsedTime(&ms, e0, e1));
+                if (rep) ms_min = std::min(ms_min, ms);
+                g->event_pool.push_back(e0);
+                g->event_pool.push_back(e1);
+            }
+            if (std::getenv("LOUVAIN_TUNE_LOG"))
+                std::fprintf(stderr, "louvain tune:   bin %d lanes %d: %.3f ms\n", b, lv::kLaneChoices[b][c], ms_min);
+            if (ms_min < best_ms) {
+                best_ms = ms_min;
+                best = lv::kLaneChoices[b][c];
+            }
+        }
+        g->lanes[b] = best;
+        if (std::getenv("LOUVAIN_TUNE_LOG"))
+            std::fprintf(stderr, "louvain tune: level %d bin %d (%lld vertices, weight kind %d): %d lanes, %.3f ms\n",
+                         g->level, b, (long long)(e - s), (int)g->cur.wk, best, best_ms);
+        std::lock_guard<std::mutex> lk(lane_cache().mu);
+        lane_cache().lanes[key] = best;
+    }
+    lv::clear_stats(g->stats, lv::NBINS * lv::STAT_REP, g->st);
+    return sync(g);
 }
 
 // sweep statistics summed over bins
@@ -1089,6 +1182,21 @@ louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, 
         const int mode = env && env[0] >= '0' && env[0] <= '2' ? env[0] - '0' : 1;
         g->graphs_ok = mode > 0;
         g->graph_colored = mode > 1;
+        const char *tune = std::getenv("LOUVAIN_AUTOTUNE");
+        g->tune = !(tune && tune[0] == '0');
+        // LOUVAIN_LANES=l1,l2,...: fixed lanes per vertex for bins 1, 2, ...
+        // (each one of the bin's choices; no tuning)
+        if (const char *ln = std::getenv("LOUVAIN_LANES")) {
+            int b = 1;
+            for (const char *q = ln; *q && b <= 8; ++b) {
+                const int v = std::atoi(q);
+                for (int c = 0; c < 4 && lv::kLaneChoices[b][c]; ++c)
+                    if (lv::kLaneChoices[b][c] == v) g->lanes[b] = v;
+                while (*q && *q != ',') ++q;
+                if (*q == ',') ++q;
+            }
+            g->tune = false;
+        }
     }
     g->recs.resize(PR_COUNT);
     for (int r = 0; r < PR_COUNT; ++r) g->recs[r].name = kNames[r];

@@ -284,8 +284,14 @@ struct BinRange {
 };
 struct FusedBins {
     BinRange bins[9];         // index = bin (1..8 used)
+    int lanes[9] = {0, 4, 8, 16, 32, 64, 64, 256, 256}; // lanes per vertex (4..64 or 256)
     int64_t hub_block0 = 0;   // first hub pass-1 block of the launch
 };
+// log2 of the LDS table slots per vertex of bins 0..8 (twice the longest row)
+constexpr int kBinShift[9] = {0, 3, 4, 5, 6, 7, 9, 11, 12};
+// lanes-per-vertex choices the tuner may take for bins 1..8 (0 ends a list)
+constexpr int kLaneChoices[9][4] = {{0}, {4, 8, 0}, {8, 4, 16, 0}, {16, 8, 32, 0}, {32, 16, 64, 0},
+                                    {64, 32, 0},     {64, 256, 0}, {256, 0},     {256, 0}};
 
 // Fused sweep launches (wide = 128-bit gains, narrow = hub sums fit 32
 // bits); each returns false when it had nothing to launch.  small: bins 1..5;

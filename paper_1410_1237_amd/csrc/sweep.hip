@@ -375,6 +375,31 @@ __device__ __forceinline__ void hub_part_tile(const SweepArgs &a, const HubArgs 
     for (int b = threadIdx.x; b <= P; b += BLOCK) bo[b] = hist[b];
 }
 
+// one tile of bin b with the bin's lanes per vertex (a launch-time choice
+// among kLaneChoices[b]); every (bin, lanes) pair is its own instance, so the
+// table size stays a compile-time constant.  LO..HI: the bins the launch has.
+template <int WK, typename GT, int LO, int HI>
+__device__ __forceinline__ void bin_tile(const SweepArgs &a, const FusedBins &f, int b, int64_t tile,
+                                         unsigned char *smem, unsigned long long *bstat)
+{
+    const BinRange &br = f.bins[b];
+    const int l = f.lanes[b];
+#define LV_TILE(B, L, SH)                                                                                              \
+    if ((B) >= LO && (B) <= HI && b == (B) && l == (L)) {                                                             \
+        sweep_tile<L, WK, GT>(a, br, tile, SH, smem, bstat);                                                           \
+        return;                                                                                                        \
+    }
+    LV_TILE(1, 4, 3) LV_TILE(1, 8, 3)
+    LV_TILE(2, 8, 4) LV_TILE(2, 4, 4) LV_TILE(2, 16, 4)
+    LV_TILE(3, 16, 5) LV_TILE(3, 8, 5) LV_TILE(3, 32, 5)
+    LV_TILE(4, 32, 6) LV_TILE(4, 16, 6) LV_TILE(4, 64, 6)
+    LV_TILE(5, 64, 7) LV_TILE(5, 32, 7)
+    LV_TILE(6, 64, 9) LV_TILE(6, 256, 9)
+    LV_TILE(7, 256, 11)
+    LV_TILE(8, 256, 12)
+#undef LV_TILE
+}
+
 // Fused launches: blocks are assigned to bins by block ranges.
 //  small: bins 1..5 (4..64 lanes per vertex, 512 LDS slots per block)
 //  large: bins 6..8 (64 or 256 lanes per vertex, up to 4096 slots) and hub pass 1
@@ -386,14 +411,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_small(SweepArgs a, FusedBins f)
     const int64_t blk = blockIdx.x;
     int b = 1;
     while (b < 5 && blk >= f.bins[b + 1].block0) ++b;
-    const int64_t tile = blk - f.bins[b].block0;
-    switch (b) {
-    case 1: sweep_tile<4, WK, GT>(a, f.bins[1], tile, 3, smem, bstat); break;
-    case 2: sweep_tile<8, WK, GT>(a, f.bins[2], tile, 4, smem, bstat); break;
-    case 3: sweep_tile<16, WK, GT>(a, f.bins[3], tile, 5, smem, bstat); break;
-    case 4: sweep_tile<32, WK, GT>(a, f.bins[4], tile, 6, smem, bstat); break;
-    default: sweep_tile<64, WK, GT>(a, f.bins[5], tile, 7, smem, bstat); break;
-    }
+    bin_tile<WK, GT, 1, 5>(a, f, b, blk - f.bins[b].block0, smem, bstat);
 }
 
 template <int WK, typename GT, typename VT>
@@ -408,12 +426,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_large(SweepArgs a, FusedBins f,
     }
     int b = 6;
     while (b < 8 && blk >= f.bins[b + 1].block0) ++b;
-    const int64_t tile = blk - f.bins[b].block0;
-    switch (b) {
-    case 6: sweep_tile<64, WK, GT>(a, f.bins[6], tile, 9, smem, bstat); break;
-    case 7: sweep_tile<256, WK, GT>(a, f.bins[7], tile, 11, smem, bstat); break;
-    default: sweep_tile<256, WK, GT>(a, f.bins[8], tile, 12, smem, bstat); break;
-    }
+    bin_tile<WK, GT, 6, 8>(a, f, b, blk - f.bins[b].block0, smem, bstat);
 }
 
 template <int WK, typename GT, typename VT>
@@ -428,17 +441,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_all(SweepArgs a, FusedBins f, H
     }
     int b = 1;
     while (b < 8 && blk >= f.bins[b + 1].block0) ++b;
-    const int64_t tile = blk - f.bins[b].block0;
-    switch (b) {
-    case 1: sweep_tile<4, WK, GT>(a, f.bins[1], tile, 3, smem, bstat); break;
-    case 2: sweep_tile<8, WK, GT>(a, f.bins[2], tile, 4, smem, bstat); break;
-    case 3: sweep_tile<16, WK, GT>(a, f.bins[3], tile, 5, smem, bstat); break;
-    case 4: sweep_tile<32, WK, GT>(a, f.bins[4], tile, 6, smem, bstat); break;
-    case 5: sweep_tile<64, WK, GT>(a, f.bins[5], tile, 7, smem, bstat); break;
-    case 6: sweep_tile<64, WK, GT>(a, f.bins[6], tile, 9, smem, bstat); break;
-    case 7: sweep_tile<256, WK, GT>(a, f.bins[7], tile, 11, smem, bstat); break;
-    default: sweep_tile<256, WK, GT>(a, f.bins[8], tile, 12, smem, bstat); break;
-    }
+    bin_tile<WK, GT, 1, 8>(a, f, b, blk - f.bins[b].block0, smem, bstat);
 }
 
 // decision of hub p from its bucket records and self-loop slot, by one
@@ -669,28 +672,43 @@ __global__ __launch_bounds__(HUB_BLOCK2) void k_hub_agg(SweepArgs a, HubArgs h)
 }
 
 // ---- host launchers --------------------------------------------------------
+// LDS of bins 1..5 of a launch: vertices per block x table slots x slot bytes
+static size_t small_lds(const FusedBins &f, int wk)
+{
+    size_t m = 0;
+    for (int b = 1; b <= 5; ++b) {
+        const size_t v = (size_t)(BLOCK / f.lanes[b]) << kBinShift[b];
+        if (v > m) m = v;
+    }
+    return m * (wk == W_UNIT ? 8 : 12);
+}
+
 template <typename GT> static void small_t(const SweepArgs &a, const FusedBins &f, int64_t blocks, hipStream_t st)
 {
+    const size_t lds = small_lds(f, a.g.wk);
     switch (a.g.wk) {
-    case W_UNIT: k_sweep_small<W_UNIT, GT><<<(unsigned)blocks, BLOCK, 512 * 8, st>>>(a, f); break;
-    case W_I32: k_sweep_small<W_I32, GT><<<(unsigned)blocks, BLOCK, 512 * 12, st>>>(a, f); break;
-    default: k_sweep_small<W_I64, GT><<<(unsigned)blocks, BLOCK, 512 * 12, st>>>(a, f); break;
+    case W_UNIT: k_sweep_small<W_UNIT, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f); break;
+    case W_I32: k_sweep_small<W_I32, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f); break;
+    default: k_sweep_small<W_I64, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f); break;
     }
 }
 
 // dynamic LDS of a fused launch with bins up to 8 and hub pass 1
-template <int WK, typename VT> static size_t fused_lds()
+template <int WK, typename VT> static size_t fused_lds(const FusedBins &f)
 {
-    const size_t bin8 = (size_t)4096 * (WK == W_UNIT ? 8 : 12);
-    const size_t part = hub_part_lds<VT>();
-    return bin8 > part ? bin8 : part;
+    size_t m = hub_part_lds<VT>();
+    for (int b = 1; b <= 8; ++b) {
+        const size_t v = ((size_t)(BLOCK / f.lanes[b]) << kBinShift[b]) * (WK == W_UNIT ? 8 : 12);
+        if (v > m) m = v;
+    }
+    return m;
 }
 
 template <bool ALL, int WK, typename GT, typename VT>
 static void fused_launch(const SweepArgs &a, const FusedBins &f, const HubArgs &h, int64_t blocks, hipStream_t st)
 {
-    if (ALL) k_sweep_all<WK, GT, VT><<<(unsigned)blocks, BLOCK, fused_lds<WK, VT>(), st>>>(a, f, h);
-    else k_sweep_large<WK, GT, VT><<<(unsigned)blocks, BLOCK, fused_lds<WK, VT>(), st>>>(a, f, h);
+    if (ALL) k_sweep_all<WK, GT, VT><<<(unsigned)blocks, BLOCK, fused_lds<WK, VT>(f), st>>>(a, f, h);
+    else k_sweep_large<WK, GT, VT><<<(unsigned)blocks, BLOCK, fused_lds<WK, VT>(f), st>>>(a, f, h);
 }
 
 template <bool ALL, typename GT, typename VT>
@@ -716,14 +734,13 @@ static void fused(const SweepArgs &a, const FusedBins &f, const HubArgs &h, int6
     }
 }
 
-static const int kLanes[9] = {0, 4, 8, 16, 32, 64, 64, 256, 256};
 
 bool sweep_small(const SweepArgs &a, FusedBins f, bool wide, hipStream_t st)
 {
     int64_t blocks = 0;
     for (int b = 1; b <= 5; ++b) {
         f.bins[b].block0 = blocks;
-        blocks += (f.bins[b].count + BLOCK / kLanes[b] - 1) / (BLOCK / kLanes[b]);
+        blocks += (f.bins[b].count + BLOCK / f.lanes[b] - 1) / (BLOCK / f.lanes[b]);
     }
     if (blocks == 0) return false;
     if (wide) small_t<i128>(a, f, blocks, st);
@@ -736,7 +753,7 @@ bool sweep_large(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, b
     int64_t blocks = 0;
     for (int b = 6; b <= 8; ++b) {
         f.bins[b].block0 = blocks;
-        blocks += (f.bins[b].count + BLOCK / kLanes[b] - 1) / (BLOCK / kLanes[b]);
+        blocks += (f.bins[b].count + BLOCK / f.lanes[b] - 1) / (BLOCK / f.lanes[b]);
     }
     f.hub_block0 = blocks;
     if (h.e > h.s) blocks += h.n_chunks;
@@ -750,7 +767,7 @@ bool sweep_all(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, boo
     int64_t blocks = 0;
     for (int b = 1; b <= 8; ++b) {
         f.bins[b].block0 = blocks;
-        blocks += (f.bins[b].count + BLOCK / kLanes[b] - 1) / (BLOCK / kLanes[b]);
+        blocks += (f.bins[b].count + BLOCK / f.lanes[b] - 1) / (BLOCK / f.lanes[b]);
     }
     f.hub_block0 = blocks;
     if (h.e > h.s) blocks += h.n_chunks;

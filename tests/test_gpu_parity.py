@@ -307,3 +307,28 @@ def test_graph_capture_modes(L, O, mode, monkeypatch):
         print(f"[parity] graphs={mode} {g.name} n={g.n}", flush=True)
         res = L.Graph.from_csr(g).run(L.params(**p))
         compare_run(res, O.run(g, oracle.Params(**p)), f"graphs={mode} {g.name}")
+
+
+def test_autotune_does_not_change_results(L, O, monkeypatch):
+    """Lanes per vertex chosen by the tuner (a graph with bins above the
+    tuning size) versus the defaults: identical runs, equal to the oracle."""
+    g = GG.rmat(17, 16, seed=21)
+    print(f"[parity] autotune {g.name} n={g.n} nnz={g.nnz}", flush=True)
+    ref = O.run(g, oracle.Params())
+    for mode in ("1", "0"):
+        monkeypatch.setenv("LOUVAIN_AUTOTUNE", mode)
+        res = L.Graph.from_csr(g).run(L.params())
+        compare_run(res, ref, f"autotune={mode}")
+
+
+@pytest.mark.parametrize("lanes", ["8,16,32,64,64,256", "4,4,8,16,32,64", "8,8,16,32,64,64"])
+def test_fixed_lanes_equal_oracle(L, O, lanes, monkeypatch):
+    """Every lanes-per-vertex choice the tuner may take gives the oracle's
+    run (graphs with rows in bins 1..6, weighted, with self-loops)."""
+    monkeypatch.setenv("LOUVAIN_LANES", lanes)
+    for g in (GG.rmat(13, 16, wmax=100, seed=6), GG.chung_lu(20000, 2.1, 2000.0, 3.0e5, 150000, wmax=100, seed=4)):
+        print(f"[parity] lanes={lanes} {g.name}", flush=True)
+        res = L.Graph.from_csr(g).run(L.params(vf=1, color=1, color_cutoff=1))
+        compare_run(res, O.run(g, oracle.Params(vf=1, color=1, color_cutoff=1)), f"lanes={lanes}")
+        res = L.Graph.from_csr(g).run(L.params())
+        compare_run(res, O.run(g, oracle.Params()), f"lanes={lanes} plain")
