@@ -333,7 +333,8 @@ louvain_status louvain_server_poll(louvain_server_t s, uint64_t ticket, int32_t 
                                    int32_t *done);
 /* forgets a finished job */
 louvain_status louvain_server_release(louvain_server_t s, uint64_t ticket);
-/* blocks until every submitted job finished */
+/* blocks until every submitted job finished; LOUVAIN_E_HIP if a device error
+ * occurred (an invalid job only fails itself: its batch is retried job by job) */
 louvain_status louvain_server_wait_all(louvain_server_t s);
 const char *louvain_server_last_error(louvain_server_t s);
 /* waits for the submitted jobs, then stops the loop */

@@ -88,18 +88,19 @@ namespace {
 typedef louvain_server_s S;
 typedef louvain_server_s::Worker Worker;
 
-void run_batch(S *s, std::vector<std::shared_ptr<Job>> batch, int64_t batch_id, uint64_t bytes)
+// Runs jobs [first, last) of `batch` as one batched run on stream st and
+// stores each job's outcome in its Job (results under the server's lock).
+// Returns the status of the batch initialisation (an invalid job fails it).
+louvain_status run_group(S *s, std::vector<std::shared_ptr<Job>> &batch, size_t first, size_t last, hipStream_t st,
+                         double t_packed)
 {
-    (void)hipSetDevice(s->dev);
-    hipStream_t st = nullptr;
-    (void)hipStreamCreate(&st); // default priority
-    const int32_t ng = (int32_t)batch.size();
+    const int32_t ng = (int32_t)(last - first);
     std::vector<int64_t> goff(ng + 1, 0), ns(ng), nnzs(ng);
     std::vector<const int64_t *> offs(ng);
     std::vector<const int32_t *> cols(ng), ws(ng);
     bool weighted = false;
     for (int32_t i = 0; i < ng; ++i) {
-        const Job &j = *batch[i];
+        const Job &j = *batch[first + i];
         goff[i + 1] = goff[i] + j.n;
         ns[i] = j.n;
         nnzs[i] = j.nnz;
@@ -112,31 +113,50 @@ void run_batch(S *s, std::vector<std::shared_ptr<Job>> batch, int64_t batch_id, 
     std::vector<louvain_graph_result> res(ng);
     std::vector<int32_t> labels(n > 0 ? n : 1);
     louvain_batch_t b = nullptr;
-    const double t_packed = s->now();
     // each job's arrays go to the device as they are; the union is assembled there
-    louvain_status rc = louvain_batch_init_graphs(ng, ns.data(), nnzs.data(), offs.data(), cols.data(),
-                                                  weighted ? ws.data() : nullptr, LOUVAIN_VALIDATE, st, &b);
+    const louvain_status init = louvain_batch_init_graphs(ng, ns.data(), nnzs.data(), offs.data(), cols.data(),
+                                                          weighted ? ws.data() : nullptr, LOUVAIN_VALIDATE, st, &b);
+    louvain_status rc = init;
     if (rc == LOUVAIN_OK) (void)hipStreamSynchronize(st);
     const double t_ready = s->now();
     if (rc == LOUVAIN_OK) rc = louvain_batch_run(b, &s->params, labels.data(), 0, res.data());
-    std::string msg = rc == LOUVAIN_OK ? "" : louvain_batch_last_error(b);
+    const std::string msg = rc == LOUVAIN_OK ? "" : louvain_batch_last_error(b);
     louvain_batch_destroy(b);
+    if (init != LOUVAIN_OK && ng > 1 && (init == LOUVAIN_E_BAD_CSR || init == LOUVAIN_E_OVERFLOW))
+        return init; // the caller retries the jobs one by one
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (int32_t i = 0; i < ng; ++i) {
+        Job &j = *batch[first + i];
+        j.status = rc;
+        if (rc == LOUVAIN_OK) {
+            j.res = res[i];
+            j.labels.assign(labels.begin() + goff[i], labels.begin() + goff[i + 1]);
+        }
+        j.t_packed = t_packed;
+        j.t_ready = t_ready;
+    }
+    if (rc == LOUVAIN_E_HIP) s->err = msg; // device errors are the server's; invalid jobs only their own
+    return init;
+}
+
+void run_batch(S *s, std::vector<std::shared_ptr<Job>> batch, int64_t batch_id, uint64_t bytes)
+{
+    (void)hipSetDevice(s->dev);
+    hipStream_t st = nullptr;
+    (void)hipStreamCreate(&st); // default priority
+    const double t_packed = s->now();
+    const louvain_status init = run_group(s, batch, 0, batch.size(), st, t_packed);
+    if (batch.size() > 1 && (init == LOUVAIN_E_BAD_CSR || init == LOUVAIN_E_OVERFLOW))
+        for (size_t i = 0; i < batch.size(); ++i) run_group(s, batch, i, i + 1, st, t_packed); // isolate the bad job
     (void)hipStreamDestroy(st);
     {
         std::lock_guard<std::mutex> lk(s->mu);
         const double t = s->now();
-        for (int32_t i = 0; i < ng; ++i) {
-            Job &j = *batch[i];
-            j.status = rc;
-            if (rc == LOUVAIN_OK) {
-                j.res = res[i];
-                j.labels.assign(labels.begin() + goff[i], labels.begin() + goff[i + 1]);
-            }
+        for (auto &jp : batch) {
+            Job &j = *jp;
             j.t_done = t;
-            j.t_packed = t_packed;
-            j.t_ready = t_ready;
             j.batch_id = batch_id;
-            j.batch_graphs = ng;
+            j.batch_graphs = (int64_t)batch.size();
             j.done = true;
             j.off.clear();
             j.off.shrink_to_fit();
@@ -146,7 +166,6 @@ void run_batch(S *s, std::vector<std::shared_ptr<Job>> batch, int64_t batch_id, 
             j.w.shrink_to_fit();
             s->pending -= 1;
         }
-        if (rc != LOUVAIN_OK) s->err = msg;
         s->reserved -= bytes;
         s->inflight -= 1;
     }

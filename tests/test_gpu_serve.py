@@ -121,3 +121,22 @@ def test_served_rejects(L):
     with pytest.raises(L.LouvainError):
         s.poll(t)
     s.close()
+
+
+def test_served_invalid_job_fails_alone(L, O):
+    """A job that passes the submit checks but not the device validation
+    (an asymmetric CSR) fails with LOUVAIN_E_BAD_CSR; the jobs batched with it
+    still get their own results."""
+    good = [GG.batch_sbm(i) for i in range(140, 146)]
+    bad = SG.from_edges(4, [(0, 1), (1, 2), (2, 3)])
+    bad.cols = bad.cols.copy()
+    bad.cols[0] = 2  # row 0 now points to 2, but row 2 has no entry back to 0
+    p = L.params()
+    s = L.Server(p, max_inflight_batches=1, max_batch_graphs=8)
+    tickets = [s.submit(g) for g in good[:3]] + [s.submit(bad)] + [s.submit(g) for g in good[3:]]
+    s.wait_all()
+    infos = [s.poll(t) for t in tickets]
+    assert infos[3].status == L.E_BAD_CSR
+    for g, info in zip(good, infos[:3] + infos[4:]):
+        check_job(L, O, g, info, solo(L, g, p), g.name)
+    s.close()
