@@ -399,14 +399,21 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_degrees(const int64_t *off, co
     }
 }
 
-// coarse row offsets: off[c] = first run whose row is >= c
-__global__ __launch_bounds__(BLOCK) void k_row_offsets(const uint64_t *keys, const int64_t *rstart, int64_t nruns,
-                                                       int bits, int64_t n_new, int64_t *off_out)
+// runs per coarse row, counted from the first and the last run of each row
+// (at most two uncontended additions per row; rows with no run stay 0); an
+// exclusive scan then gives the row offsets. Work per thread is one run,
+// whatever the lengths of the rows or of the gaps between non-empty rows.
+__global__ __launch_bounds__(BLOCK) void k_row_counts(const uint64_t *keys, const int64_t *rstart, int64_t nruns,
+                                                      int bits, int64_t *cnt)
 {
-    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r <= nruns; r += (int64_t)gridDim.x * BLOCK) {
-        const int64_t prev = (r == 0) ? -1 : (int64_t)(keys[rstart[r - 1]] >> bits);
-        const int64_t cur = (r == nruns) ? n_new : (int64_t)(keys[rstart[r]] >> bits);
-        for (int64_t c = prev + 1; c <= cur; ++c) off_out[c] = r;
+    for (int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x; r < nruns; r += (int64_t)gridDim.x * BLOCK) {
+        const uint64_t row = keys[rstart[r]] >> bits;
+        const bool head = r == 0 || (keys[rstart[r - 1]] >> bits) != row;
+        const bool tail = r == nruns - 1 || (keys[rstart[r + 1]] >> bits) != row;
+        unsigned long long *c = (unsigned long long *)&cnt[row];
+        if (head && tail) *c = 1;
+        else if (head) atomicAdd(c, (unsigned long long)(-r));
+        else if (tail) atomicAdd(c, (unsigned long long)(r + 1));
     }
 }
 
@@ -471,9 +478,9 @@ void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_ori
     if (gw > 65536) gw = 65536;
     rep_clear(s.rep, st);
     k_run_weights<<<gw, BLOCK, 0, st>>>(b.keys, bits, rstart, nruns, pref, w_out, s.rep);
-    unsigned go = grid_for(nruns + 1, BLOCK * 4);
-    if (go > 65536) go = 65536;
-    k_row_offsets<<<go, BLOCK, 0, st>>>(b.keys, rstart, nruns, bits, nn, off_out);
+    fill<int64_t>(off_out, 0, nn, st);
+    k_row_counts<<<gw, BLOCK, 0, st>>>(b.keys, rstart, nruns, bits, off_out);
+    scan_i64(off_out, off_out, nn, off_out + nn, s, st); // in place; the total is nruns
     *nnz_new = nruns;
     // weighted degrees, 2m (the total weight: unchanged by coarsening), the
     // largest degree and the self-loop total of the coarse graph

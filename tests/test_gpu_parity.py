@@ -332,3 +332,34 @@ def test_fixed_lanes_equal_oracle(L, O, lanes, monkeypatch):
         compare_run(res, O.run(g, oracle.Params(vf=1, color=1, color_cutoff=1)), f"lanes={lanes}")
         res = L.Graph.from_csr(g).run(L.params())
         compare_run(res, O.run(g, oracle.Params()), f"lanes={lanes} plain")
+
+
+def spread_graph(base, starts, n):
+    """base with gap isolated ids inserted before its vertex `at`, for each
+    (at, gap) in starts, and isolated ids up to n after it: long runs of empty
+    rows before, between and after the connected vertices, in the input and
+    in every coarse graph."""
+    newid = np.arange(base.n, dtype=np.int64)
+    for at, gap in starts:
+        newid[at:] += gap
+    assert newid[-1] < n
+    deg = np.diff(base.offsets)
+    d = np.zeros(n, dtype=np.int64)
+    d[newid] = deg
+    off = np.zeros(n + 1, dtype=np.int64)
+    off[1:] = np.cumsum(d)
+    g = SG.CSR(n, off, newid[base.cols].astype(np.int32), None if base.weights is None else base.weights.copy())
+    g.name = f"spread({base.name}, n={n})"
+    return g
+
+
+def test_long_empty_row_gaps(L, O):
+    """Coarse row offsets over long stretches of empty rows (isolated
+    vertices before, between and after the connected ones)."""
+    base = GG.rmat(12, 8, wmax=30, seed=13)
+    g = spread_graph(base, [(0, 70000), (1000, 100000), (3000, 5)], base.n + 70000 + 100000 + 5 + 150000)
+    _steps(L, O, g, colored=False, vf=True, phases=3, iters=4)
+    for d in (dict(), dict(vf=1, color=1, color_cutoff=1000)):
+        with L.Graph.from_csr(g) as gs:
+            res = gs.run(L.params(**d))
+        compare_run(res, O.run(g, oracle_params(d)), f"{g.name} {d}")
