@@ -244,7 +244,7 @@ def bench_served(args):
     torch.cuda.init()
 
     def run(rate):
-        s = L.Server(p)
+        s = L.Server(p, solo_min_vertices=args.solo_min_vertices, max_inflight_batches=args.max_inflight)
         rng = np.random.default_rng(6)
         gaps = rng.exponential(1.0 / rate, size=len(jobs)) if rate else np.zeros(len(jobs))
         t0 = time.perf_counter()
@@ -255,7 +255,7 @@ def bench_served(args):
             wait = due - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(wait)
-            tickets.append(s.submit(g))
+            tickets.append(s.submit(g, borrow=True))  # the job arrays outlive the server
         s.wait_all()
         infos = [s.poll(tk, labels=False) for tk in tickets]
         s.close()
@@ -286,7 +286,11 @@ def bench_served(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": f"served_job x{len(jobs)}", "jobs": len(jobs), "n_total": tot_n, "nnz_total": tot_e,
                    "arrivals": "Poisson", "rate_per_s": round(rate, 2), "capacity_per_s": round(capacity, 2),
-                   "hbm_budget_bytes": 200 << 30, "max_inflight_batches": 4, "heuristics": "plain"},
+                   "hbm_budget_bytes": 200 << 30, "heuristics": "plain",
+                   "max_inflight_batches": L.louvain_server_config_default().max_inflight_batches
+                   if args.max_inflight is None else args.max_inflight,
+                   "solo_min_vertices": L.louvain_server_config_default().solo_min_vertices
+                   if args.solo_min_vertices is None else args.solo_min_vertices, "submission": "borrowed"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
                        "p99": round(float(np.percentile(lat, 99)) * 1e3, 2),
                        "max": round(float(lat.max()) * 1e3, 2)},
@@ -319,6 +323,10 @@ def main():
                     help="single graph (default); batched: many SBMs in one batched run; served: request loop")
     ap.add_argument("--graphs", type=int, default=4096, help="batched form: graphs in the batch")
     ap.add_argument("--jobs", type=int, default=128, help="served form: jobs")
+    ap.add_argument("--max-inflight", type=int, default=None,
+                    help="served form: concurrent batches (default: the library's)")
+    ap.add_argument("--solo-min-vertices", type=int, default=None,
+                    help="served form: jobs this large run alone (default: the library's)")
     ap.add_argument("--solo-sample", type=int, default=256, help="batched form: graphs timed one at a time")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (a plain copy kernel of "

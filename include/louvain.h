@@ -293,15 +293,17 @@ const char *louvain_batch_last_error(louvain_batch_t b);
 /* ---- served form --------------------------------------------------------- */
 
 /*
- * A request loop with continuous batching: jobs (host CSRs, copied at submit)
- * queue FIFO; a scheduler thread admits jobs from the queue head into a new
- * batch whenever fewer than max_inflight_batches batches run and the HBM
- * budget covers the batch's estimated device footprint; each batch runs the
- * batched form on its own worker thread and HIP stream, so batches admitted
- * at different times overlap on the device, and memory returned by a
- * finished batch admits the next jobs.  Each job's result equals the graph
- * run alone.  A job larger than the whole budget fails with LOUVAIN_E_OOM.
- * Uses the device current at louvain_server_create.
+ * A request loop with continuous batching: jobs (host CSRs, copied at submit,
+ * or borrowed until they finish) queue FIFO; a scheduler thread admits jobs
+ * from the queue head into a new batch whenever fewer than
+ * max_inflight_batches batches run and the HBM budget covers the batch's
+ * estimated device footprint; each batch runs the batched form on its own
+ * worker thread and HIP stream, so batches admitted at different times
+ * overlap on the device, and memory returned by a finished batch admits the
+ * next jobs.  A job of at least solo_min_vertices vertices is a batch of its
+ * own and runs through louvain_init_csr + louvain_run.  Each job's result
+ * equals the graph run alone.  A job larger than the whole budget fails with
+ * LOUVAIN_E_OOM.  Uses the device current at louvain_server_create.
  */
 typedef struct louvain_server_s *louvain_server_t;
 
@@ -310,6 +312,7 @@ typedef struct {
     int32_t max_inflight_batches;  /* concurrent batches / streams (default 4) */
     int32_t max_batch_graphs;      /* jobs per batch (default 4096) */
     int64_t max_batch_vertices;    /* vertices per batch, 0 = no limit */
+    int64_t solo_min_vertices;     /* jobs this large run alone (default 100,000; 0 = never) */
 } louvain_server_config;
 
 typedef struct {
@@ -325,8 +328,18 @@ void louvain_server_config_default(louvain_server_config *cfg);
 /* cfg may be NULL (defaults); params->color must be 0 */
 louvain_status louvain_server_create(const louvain_server_config *cfg, const louvain_params *params,
                                      louvain_server_t *out);
+/* host CSR in the layout of louvain_init_csr (weights NULL = unit), copied
+ * before the call returns; offsets and column range are checked here
+ * (LOUVAIN_E_BAD_CSR), order, weights and symmetry on the device when the job
+ * runs (then the job's status is LOUVAIN_E_BAD_CSR) */
 louvain_status louvain_server_submit(louvain_server_t s, int64_t n, int64_t nnz, const int64_t *offsets,
                                      const int32_t *cols, const int32_t *weights, uint64_t *ticket);
+/* the same without the copy: the server reads the caller's arrays when the
+ * job runs, so they must stay allocated and unchanged until poll reports the
+ * job done (wait_all and destroy also wait for it); only offsets[0] and
+ * offsets[n] are checked here, everything else on the device */
+louvain_status louvain_server_submit_borrowed(louvain_server_t s, int64_t n, int64_t nnz, const int64_t *offsets,
+                                              const int32_t *cols, const int32_t *weights, uint64_t *ticket);
 /* *done = 1 once the job finished; then labels_out (n host entries, may be
  * NULL) and *out (may be NULL) are filled */
 louvain_status louvain_server_poll(louvain_server_t s, uint64_t ticket, int32_t *labels_out, louvain_job_result *out,

@@ -1,15 +1,18 @@
 // Served form: a request loop that admits community-detection jobs into
 // batches while other batches are on the device.
 //
-// Jobs are queued FIFO with a copy of their CSR.  A scheduler thread forms
-// a batch from the queue head whenever a worker slot is free and the HBM
-// budget covers the batch's estimated footprint; each batch runs on its own
-// worker thread and HIP stream through the batched form, so batches admitted
-// at different times overlap on the device; a batch's jobs are copied to the
-// device as they are and packed there.  Memory is reserved at admission
-// and returned when the batch completes, which may admit the next jobs.
-// Every job's result is the one it gets alone (the batched form is exact per
-// graph).
+// Jobs are queued FIFO with a copy of their CSR (or, submitted as borrowed,
+// with the caller's arrays).  A scheduler thread forms a batch from the
+// queue head whenever a worker slot is free and the HBM budget covers the
+// batch's estimated footprint; each batch runs on its own worker thread and
+// HIP stream through the batched form, so batches admitted at different
+// times overlap on the device; a batch's jobs are copied to the device as
+// they are and packed there.  A job of at least solo_min_vertices vertices
+// is a batch of its own and runs through the single-graph path, which keeps
+// a large graph's sweeps at full width (batching pays off for the small,
+// latency-bound graphs).  Memory is reserved at admission and returned when
+// the batch completes, which may admit the next jobs.  Every job's result is
+// the one it gets alone (the batched form is exact per graph).
 #include "louvain.h"
 
 #include <hip/hip_runtime.h>
@@ -31,9 +34,11 @@ namespace {
 struct Job {
     uint64_t ticket = 0;
     int64_t n = 0, nnz = 0;
-    std::vector<int64_t> off;
+    std::vector<int64_t> off; // the copy of a copied job (empty when borrowed)
     std::vector<int32_t> col, w;
-    bool weighted = false;
+    const int64_t *p_off = nullptr; // the arrays the job reads: its copy or the caller's
+    const int32_t *p_col = nullptr, *p_w = nullptr;
+    bool solo = false; // runs alone through the single-graph path
     uint64_t bytes = 0;
     // outcome
     int32_t status = -1; // -1 pending, else louvain_status
@@ -104,10 +109,10 @@ louvain_status run_group(S *s, std::vector<std::shared_ptr<Job>> &batch, size_t 
         goff[i + 1] = goff[i] + j.n;
         ns[i] = j.n;
         nnzs[i] = j.nnz;
-        offs[i] = j.off.data();
-        cols[i] = j.col.data();
-        ws[i] = j.weighted ? j.w.data() : nullptr;
-        weighted |= j.weighted;
+        offs[i] = j.p_off;
+        cols[i] = j.p_col;
+        ws[i] = j.p_w;
+        weighted |= j.p_w != nullptr;
     }
     const int64_t n = goff[ng];
     std::vector<louvain_graph_result> res(ng);
@@ -139,15 +144,52 @@ louvain_status run_group(S *s, std::vector<std::shared_ptr<Job>> &batch, size_t 
     return init;
 }
 
+// Runs one job through louvain_init_csr + louvain_run on stream st.
+void run_solo(S *s, Job &j, hipStream_t st, double t_packed)
+{
+    std::vector<int32_t> labels(j.n > 0 ? j.n : 1);
+    louvain_graph_t g = nullptr;
+    louvain_result r{};
+    louvain_status rc = louvain_init_csr(j.n, j.nnz, j.p_off, j.p_col, j.p_w, LOUVAIN_VALIDATE, st, &g);
+    const double t_ready = s->now();
+    if (rc == LOUVAIN_OK) rc = louvain_run(g, &s->params, labels.data(), 0, &r);
+    const std::string msg = rc == LOUVAIN_OK ? "" : louvain_last_error(g);
+    louvain_destroy(g);
+    std::lock_guard<std::mutex> lk(s->mu);
+    j.status = rc;
+    if (rc == LOUVAIN_OK) {
+        louvain_graph_result &o = j.res;
+        o.n = j.n;
+        o.nnz = j.nnz;
+        o.num_communities = r.num_communities;
+        o.phases = r.phases;
+        o.iterations = r.iterations;
+        o.q_num = r.q_num;
+        o.q_den = r.q_den;
+        o.q0_num = r.q0_num;
+        o.q = r.q;
+        o.n_vf = r.n_vf;
+        j.labels = std::move(labels);
+        j.labels.resize(j.n);
+    }
+    j.t_packed = t_packed;
+    j.t_ready = t_ready;
+    if (rc == LOUVAIN_E_HIP) s->err = msg;
+}
+
 void run_batch(S *s, std::vector<std::shared_ptr<Job>> batch, int64_t batch_id, uint64_t bytes)
 {
     (void)hipSetDevice(s->dev);
     hipStream_t st = nullptr;
     (void)hipStreamCreate(&st); // default priority
     const double t_packed = s->now();
-    const louvain_status init = run_group(s, batch, 0, batch.size(), st, t_packed);
-    if (batch.size() > 1 && (init == LOUVAIN_E_BAD_CSR || init == LOUVAIN_E_OVERFLOW))
-        for (size_t i = 0; i < batch.size(); ++i) run_group(s, batch, i, i + 1, st, t_packed); // isolate the bad job
+    if (batch.size() == 1 && batch[0]->solo) {
+        run_solo(s, *batch[0], st, t_packed);
+    } else {
+        const louvain_status init = run_group(s, batch, 0, batch.size(), st, t_packed);
+        if (batch.size() > 1 && (init == LOUVAIN_E_BAD_CSR || init == LOUVAIN_E_OVERFLOW))
+            for (size_t i = 0; i < batch.size(); ++i) run_group(s, batch, i, i + 1, st, t_packed); // isolate the bad job
+    }
     (void)hipStreamDestroy(st);
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -164,6 +206,8 @@ void run_batch(S *s, std::vector<std::shared_ptr<Job>> batch, int64_t batch_id, 
             j.col.shrink_to_fit();
             j.w.clear();
             j.w.shrink_to_fit();
+            j.p_off = nullptr; // a borrowed job's arrays are the caller's again
+            j.p_col = j.p_w = nullptr;
             s->pending -= 1;
         }
         s->reserved -= bytes;
@@ -213,6 +257,8 @@ void schedule(S *s)
                 s->cv.notify_all();
                 continue;
             }
+            const bool solo = j->solo;
+            if (solo && !batch.empty()) break; // a large job is the next batch, alone
             if (s->reserved + bytes + j->bytes > s->cfg.hbm_budget_bytes) break;
             if (!batch.empty() && s->cfg.max_batch_vertices > 0 && verts + j->n > s->cfg.max_batch_vertices) break;
             bytes += j->bytes;
@@ -220,6 +266,7 @@ void schedule(S *s)
             j->t_admit = s->now();
             batch.push_back(j);
             s->queue.pop_front();
+            if (solo) break;
         }
         if (batch.empty()) {
             // the head needs memory still held by running batches: wait for one to finish
@@ -256,6 +303,7 @@ void louvain_server_config_default(louvain_server_config *c)
     c->max_inflight_batches = 4;
     c->max_batch_graphs = 4096;
     c->max_batch_vertices = 0;
+    c->solo_min_vertices = 100000;
 }
 
 louvain_status louvain_server_create(const louvain_server_config *cfg, const louvain_params *params,
@@ -267,7 +315,8 @@ louvain_status louvain_server_create(const louvain_server_config *cfg, const lou
     S *s = new S();
     if (cfg) s->cfg = *cfg;
     else louvain_server_config_default(&s->cfg);
-    if (s->cfg.max_inflight_batches < 1 || s->cfg.max_batch_graphs < 1 || s->cfg.hbm_budget_bytes == 0) {
+    if (s->cfg.max_inflight_batches < 1 || s->cfg.max_batch_graphs < 1 || s->cfg.hbm_budget_bytes == 0 ||
+        s->cfg.max_batch_vertices < 0 || s->cfg.solo_min_vertices < 0) {
         delete s;
         return LOUVAIN_E_INVALID_ARG;
     }
@@ -282,22 +331,36 @@ louvain_status louvain_server_create(const louvain_server_config *cfg, const lou
     return LOUVAIN_OK;
 }
 
-louvain_status louvain_server_submit(louvain_server_t s, int64_t n, int64_t nnz, const int64_t *offsets,
-                                     const int32_t *cols, const int32_t *weights, uint64_t *ticket)
+} // extern "C"
+
+namespace {
+
+louvain_status submit(S *s, int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                      const int32_t *weights, bool borrow, uint64_t *ticket)
 {
     if (!s || !ticket || n < 0 || nnz < 0 || !offsets || (nnz > 0 && !cols)) return LOUVAIN_E_INVALID_ARG;
+    if (n >= ((int64_t)1 << 31) - 1) return LOUVAIN_E_INVALID_ARG;
     if (offsets[0] != 0 || offsets[n] != nnz) return LOUVAIN_E_BAD_CSR;
-    for (int64_t x = 0; x < nnz; ++x)
-        if (cols[x] < 0 || cols[x] >= n) return LOUVAIN_E_BAD_CSR;
     auto j = std::make_shared<Job>();
     j->n = n;
     j->nnz = nnz;
-    j->off.assign(offsets, offsets + n + 1);
-    j->col.assign(cols, cols + nnz);
-    if (weights) {
-        j->w.assign(weights, weights + nnz);
-        j->weighted = true;
+    if (borrow) {
+        // read in place when the job runs; its device validation covers the
+        // checks a copied job gets here
+        j->p_off = offsets;
+        j->p_col = cols;
+        j->p_w = weights;
+    } else {
+        for (int64_t x = 0; x < nnz; ++x)
+            if (cols[x] < 0 || cols[x] >= n) return LOUVAIN_E_BAD_CSR;
+        j->off.assign(offsets, offsets + n + 1);
+        j->col.assign(cols, cols + nnz);
+        if (weights) j->w.assign(weights, weights + nnz);
+        j->p_off = j->off.data();
+        j->p_col = j->col.data();
+        j->p_w = weights ? j->w.data() : nullptr;
     }
+    j->solo = s->cfg.solo_min_vertices > 0 && n >= s->cfg.solo_min_vertices;
     j->bytes = job_bytes(n, nnz);
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -310,6 +373,22 @@ louvain_status louvain_server_submit(louvain_server_t s, int64_t n, int64_t nnz,
     }
     s->cv.notify_all();
     return LOUVAIN_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+louvain_status louvain_server_submit(louvain_server_t s, int64_t n, int64_t nnz, const int64_t *offsets,
+                                     const int32_t *cols, const int32_t *weights, uint64_t *ticket)
+{
+    return submit(s, n, nnz, offsets, cols, weights, false, ticket);
+}
+
+louvain_status louvain_server_submit_borrowed(louvain_server_t s, int64_t n, int64_t nnz, const int64_t *offsets,
+                                              const int32_t *cols, const int32_t *weights, uint64_t *ticket)
+{
+    return submit(s, n, nnz, offsets, cols, weights, true, ticket);
 }
 
 louvain_status louvain_server_poll(louvain_server_t s, uint64_t ticket, int32_t *labels_out, louvain_job_result *out,

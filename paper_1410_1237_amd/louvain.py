@@ -79,7 +79,8 @@ class GraphResult(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_inflight_batches", ctypes.c_int32),
-                ("max_batch_graphs", ctypes.c_int32), ("max_batch_vertices", ctypes.c_int64)]
+                ("max_batch_graphs", ctypes.c_int32), ("max_batch_vertices", ctypes.c_int64),
+                ("solo_min_vertices", ctypes.c_int64)]
 
 
 class JobResult(ctypes.Structure):
@@ -97,7 +98,8 @@ EXPORTS = ["louvain_params_default", "louvain_init_csr", "louvain_vf", "louvain_
            "louvain_profile_get", "louvain_batch_init", "louvain_batch_run", "louvain_batch_graph_stats",
            "louvain_batch_destroy", "louvain_batch_last_error", "louvain_batch_init_graphs",
            "louvain_server_config_default",
-           "louvain_server_create", "louvain_server_submit", "louvain_server_poll", "louvain_server_release",
+           "louvain_server_create", "louvain_server_submit", "louvain_server_submit_borrowed",
+           "louvain_server_poll", "louvain_server_release",
            "louvain_server_wait_all", "louvain_server_last_error", "louvain_server_destroy"]
 
 
@@ -165,6 +167,8 @@ def lib():
     L.louvain_server_create.restype = st
     L.louvain_server_submit.argtypes = [vp, i64, i64, vp, vp, vp, ctypes.POINTER(u64)]
     L.louvain_server_submit.restype = st
+    L.louvain_server_submit_borrowed.argtypes = [vp, i64, i64, vp, vp, vp, ctypes.POINTER(u64)]
+    L.louvain_server_submit_borrowed.restype = st
     L.louvain_server_poll.argtypes = [vp, u64, vp, ctypes.POINTER(JobResult), ctypes.POINTER(i32)]
     L.louvain_server_poll.restype = st
     L.louvain_server_release.argtypes = [vp, u64]
@@ -619,7 +623,7 @@ class Server:
 
     def __init__(self, p: Optional[Params] = None, hbm_budget_bytes: Optional[int] = None,
                  max_inflight_batches: Optional[int] = None, max_batch_graphs: Optional[int] = None,
-                 max_batch_vertices: Optional[int] = None, **kw):
+                 max_batch_vertices: Optional[int] = None, solo_min_vertices: Optional[int] = None, **kw):
         cfg = louvain_server_config_default()
         if hbm_budget_bytes is not None:
             cfg.hbm_budget_bytes = int(hbm_budget_bytes)
@@ -629,6 +633,8 @@ class Server:
             cfg.max_batch_graphs = int(max_batch_graphs)
         if max_batch_vertices is not None:
             cfg.max_batch_vertices = int(max_batch_vertices)
+        if solo_min_vertices is not None:
+            cfg.solo_min_vertices = int(solo_min_vertices)
         self.p = p or params(**kw)
         h = ctypes.c_void_p()
         st = lib().louvain_server_create(ctypes.byref(cfg), ctypes.byref(self.p), ctypes.byref(h))
@@ -636,18 +642,23 @@ class Server:
             raise LouvainError(st, "louvain_server_create rejected its arguments")
         self.h = h.value
         self.sizes = {}
+        self.held = {}  # ticket -> arrays of a borrowed job, kept alive until it is done
 
-    def submit(self, g) -> int:
+    def submit(self, g, borrow: bool = False) -> int:
+        """Queues a job; borrow=True skips the copy: the arrays are kept
+        referenced here until the job is done."""
         off = np.ascontiguousarray(g.offsets, dtype=np.int64)
         col = np.ascontiguousarray(g.cols, dtype=np.int32)
         w = None if g.weights is None else np.ascontiguousarray(g.weights, dtype=np.int32)
         t = ctypes.c_uint64()
-        st = lib().louvain_server_submit(self.h, int(g.n), int(col.size), off.ctypes.data,
-                                         col.ctypes.data if col.size else None,
-                                         None if w is None else w.ctypes.data, ctypes.byref(t))
+        fn = lib().louvain_server_submit_borrowed if borrow else lib().louvain_server_submit
+        st = fn(self.h, int(g.n), int(col.size), off.ctypes.data, col.ctypes.data if col.size else None,
+                None if w is None else w.ctypes.data, ctypes.byref(t))
         if st != OK:
             raise LouvainError(st, "louvain_server_submit rejected the graph")
         self.sizes[t.value] = int(g.n)
+        if borrow:
+            self.held[t.value] = (off, col, w)
         return t.value
 
     def poll(self, ticket: int, labels: bool = True) -> Optional[JobInfo]:
@@ -661,6 +672,7 @@ class Server:
             raise LouvainError(st, "unknown ticket")
         if not done.value:
             return None
+        self.held.pop(ticket, None)
         g = r.result
         return JobInfo(ticket=ticket, status=r.status, labels=None if out is None else out[:n],
                        K=g.num_communities, N=g.q_num.value(), D=g.q_den.value(), q=g.q, n_vf=g.n_vf,
@@ -674,6 +686,7 @@ class Server:
 
     def wait_all(self):
         st = lib().louvain_server_wait_all(self.h)
+        self.held.clear()
         if st != OK:
             raise LouvainError(st, lib().louvain_server_last_error(self.h).decode())
 
@@ -681,6 +694,7 @@ class Server:
         if getattr(self, "h", None):
             lib().louvain_server_destroy(self.h)
             self.h = None
+            self.held.clear()
 
     def __del__(self):
         try:

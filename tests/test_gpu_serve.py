@@ -79,6 +79,24 @@ def test_served_mix_equals_alone(L, O, inflight, per_batch):
     s.close()
 
 
+def test_served_solo_and_borrowed(L, O):
+    """Jobs above the size threshold run alone through the single-graph path,
+    the rest in batches; borrowed submissions (no copy) give the same results."""
+    gs = job_mix()
+    p = L.params()
+    refs = [solo(L, g, p) for g in gs]
+    s = L.Server(p, max_inflight_batches=3, max_batch_graphs=16, solo_min_vertices=20000)
+    tickets = [s.submit(g, borrow=(i % 2 == 0)) for i, g in enumerate(gs)]
+    s.wait_all()
+    infos = [s.poll(t) for t in tickets]
+    for g, info, ref in zip(gs, infos, refs):
+        check_job(L, O, g, info, ref, g.name)
+        if g.n >= 20000:
+            assert info.batch_graphs == 1, g.name
+    assert any(i.batch_graphs > 1 for i in infos)
+    s.close()
+
+
 def job_bytes(g):
     # the server's estimate of a job's device footprint
     big = max(g.n, g.nnz) + 1
@@ -131,12 +149,17 @@ def test_served_invalid_job_fails_alone(L, O):
     bad = SG.from_edges(4, [(0, 1), (1, 2), (2, 3)])
     bad.cols = bad.cols.copy()
     bad.cols[0] = 2  # row 0 now points to 2, but row 2 has no entry back to 0
+    # borrowed: not range-checked at submission, the device validation rejects it
+    far = SG.from_edges(4, [(0, 1), (1, 2), (2, 3)])
+    far.cols = far.cols.copy()
+    far.cols[0] = 9
     p = L.params()
     s = L.Server(p, max_inflight_batches=1, max_batch_graphs=8)
-    tickets = [s.submit(g) for g in good[:3]] + [s.submit(bad)] + [s.submit(g) for g in good[3:]]
+    tickets = [s.submit(g) for g in good[:3]] + [s.submit(bad), s.submit(far, borrow=True)] + \
+        [s.submit(g, borrow=True) for g in good[3:]]
     s.wait_all()
     infos = [s.poll(t) for t in tickets]
-    assert infos[3].status == L.E_BAD_CSR
-    for g, info in zip(good, infos[:3] + infos[4:]):
+    assert infos[3].status == L.E_BAD_CSR and infos[4].status == L.E_BAD_CSR
+    for g, info in zip(good, infos[:3] + infos[5:]):
         check_job(L, O, g, info, solo(L, g, p), g.name)
     s.close()

@@ -70,12 +70,15 @@ def test_server_config_and_host_rejection():
     from paper_1410_1237_amd import louvain as L
     c = L.louvain_server_config_default()
     assert c.hbm_budget_bytes == 200 << 30 and c.max_inflight_batches == 4
-    assert c.max_batch_graphs == 4096 and c.max_batch_vertices == 0
+    assert c.max_batch_graphs == 4096 and c.max_batch_vertices == 0 and c.solo_min_vertices == 100000
     with pytest.raises(L.LouvainError) as e:  # colored mode is not served
         L.Server(L.params(color=1))
     assert e.value.status == L.E_INVALID_ARG
     with pytest.raises(L.LouvainError) as e:
         L.Server(L.params(), max_inflight_batches=0)
+    assert e.value.status == L.E_INVALID_ARG
+    with pytest.raises(L.LouvainError) as e:
+        L.Server(L.params(), solo_min_vertices=-1)
     assert e.value.status == L.E_INVALID_ARG
 
 
