@@ -68,6 +68,10 @@ __global__ __launch_bounds__(BLOCK) void k_jp_count(Csr g, uint64_t seed, int32_
                 acc = 0;
                 ++row;
                 next = tile_off(t, g.off, s_off, row + 1);
+                if (e >= next) { // empty rows: search instead of stepping through them
+                    row = tile_row(t, g.off, s_off, e);
+                    next = tile_off(t, g.off, s_off, row + 1);
+                }
                 prow = jp_priority(seed, row);
             }
             const int32_t u = g.col[e];

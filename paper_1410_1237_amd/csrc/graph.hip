@@ -122,6 +122,10 @@ __global__ __launch_bounds__(BLOCK) void k_degrees(Csr g, int64_t *k, int64_t *r
                 acc = 0;
                 ++row;
                 next = tile_off(t, g.off, s_off, row + 1);
+                if (e >= next) { // empty rows: search instead of stepping through them
+                    row = tile_row(t, g.off, s_off, e);
+                    next = tile_off(t, g.off, s_off, row + 1);
+                }
             }
             const int64_t w = WLoad<WK>::at(g.w, e);
             acc += w;

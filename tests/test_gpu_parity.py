@@ -354,11 +354,13 @@ def spread_graph(base, starts, n):
 
 
 def test_long_empty_row_gaps(L, O):
-    """Coarse row offsets over long stretches of empty rows (isolated
-    vertices before, between and after the connected ones)."""
+    """Degrees, colouring counts and coarse row offsets over long stretches
+    of empty rows (isolated vertices before, between and after the connected
+    ones)."""
     base = GG.rmat(12, 8, wmax=30, seed=13)
     g = spread_graph(base, [(0, 70000), (1000, 100000), (3000, 5)], base.n + 70000 + 100000 + 5 + 150000)
     _steps(L, O, g, colored=False, vf=True, phases=3, iters=4)
+    _steps(L, O, g, colored=True, vf=False, phases=2, iters=3)
     for d in (dict(), dict(vf=1, color=1, color_cutoff=1000)):
         with L.Graph.from_csr(g) as gs:
             res = gs.run(L.params(**d))
