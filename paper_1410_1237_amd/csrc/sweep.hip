@@ -92,6 +92,72 @@ __device__ __forceinline__ void flush_graph_stats(const SweepArgs &a, int grp, b
     }
 }
 
+// adds w to community c's slot of an open-addressed LDS table of 2^shift
+// slots (linear probing; -1 marks a free slot)
+template <typename VT>
+__device__ __forceinline__ void table_add(int32_t *tkey, VT *tval, int shift, int32_t c, VT w)
+{
+    const uint32_t mask = (1u << shift) - 1;
+    uint32_t h = slot_hash(c, shift);
+    for (;;) {
+        int32_t cur = tkey[h];
+        if (cur == c) {
+            atomicAdd(&tval[h], w);
+            return;
+        }
+        if (cur == -1) {
+            cur = atomicCAS(&tkey[h], -1, c);
+            if (cur == -1 || cur == c) {
+                atomicAdd(&tval[h], w);
+                return;
+            }
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// Entries a lane loads (columns, weights, then the neighbours' communities)
+// before it inserts any of them: the community gathers are random reads, and
+// issuing several before the first is used keeps more of them in flight.
+constexpr int GATHER_K = 4;
+
+// Gathers the entries [beg, end) of vertex i, taken by a lane at stride
+// `stride` from `first`, into the table; returns the self-loop weight seen.
+template <int WK, typename VT>
+__device__ __forceinline__ int64_t gather_row(const SweepArgs &a, int32_t i, int64_t first, int64_t end, int stride,
+                                              int32_t *tkey, VT *tval, int shift)
+{
+    int64_t wself = 0;
+    for (int64_t e0 = first; e0 < end; e0 += (int64_t)GATHER_K * stride) {
+        int32_t c[GATHER_K];
+        int64_t w[GATHER_K];
+#pragma unroll
+        for (int k = 0; k < GATHER_K; ++k) {
+            const int64_t e = e0 + (int64_t)k * stride;
+            c[k] = -1;
+            w[k] = 0;
+            if (e < end) {
+                const int32_t j = a.g.col[e];
+                const int64_t x = WLoad<WK>::at(a.g.w, e);
+                if (j == i) wself += x;
+                else {
+                    c[k] = j;
+                    w[k] = x;
+                }
+            }
+        }
+        if (!a.singleton) {
+#pragma unroll
+            for (int k = 0; k < GATHER_K; ++k)
+                if (c[k] >= 0) c[k] = a.comm_prev[c[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < GATHER_K; ++k)
+            if (c[k] >= 0) table_add<VT>(tkey, tval, shift, c[k], (VT)w[k]);
+    }
+    return wself;
+}
+
 // One block-tile of a degree bin: VPB = BLOCK / LPV vertices, LPV lanes each,
 // hash tables of 2^shift slots per vertex in LDS.
 template <int LPV, int WK, typename GT>
@@ -124,48 +190,36 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const BinRange &b
         end = a.g.off[i + 1];
         A = a.comm_prev[i];
     }
-    for (int64_t e = beg + lane; e < end; e += LPV) {
-        const int32_t j = a.g.col[e];
-        const int64_t w = WLoad<WK>::at(a.g.w, e);
-        if (j == i) {
-            wself += w;
-            continue;
-        }
-        const int32_t c = a.singleton ? j : a.comm_prev[j];
-        uint32_t h = slot_hash(c, shift);
-        for (;;) {
-            int32_t cur = tkey[h];
-            if (cur == c) {
-                atomicAdd(&tval[h], (VT)w);
-                break;
-            }
-            if (cur == -1) {
-                cur = atomicCAS(&tkey[h], -1, c);
-                if (cur == -1 || cur == c) {
-                    atomicAdd(&tval[h], (VT)w);
-                    break;
-                }
-            }
-            h = (h + 1) & (uint32_t)(S - 1);
-        }
-    }
+    if (valid) wself = gather_row<WK, VT>(a, i, beg + lane, end, LPV, tkey, tval, shift);
     __syncthreads();
 
-    // gains over the distinct communities (Eq. 4 scaled by 2m^2), best by (G, -c)
+    // gains over the distinct communities (Eq. 4 scaled by 2m^2), best by
+    // (G, -c); the community degrees of GATHER_K slots are read together
     const int64_t ki = valid ? a.k[i] : 0;
     Best<GT> best{0, -1, 0};
     int64_t eA = 0, distinct = 0;
-    for (int64_t s = lane; s < S; s += LPV) {
-        const int32_t c = tkey[s];
-        if (c < 0) continue;
-        const int64_t e = (int64_t)tval[s];
-        ++distinct;
-        if (c == A) {
-            eA = e;
-            continue;
+    for (int64_t s0 = lane; s0 < S; s0 += (int64_t)GATHER_K * LPV) {
+        int32_t c[GATHER_K];
+        int64_t ac[GATHER_K];
+#pragma unroll
+        for (int k = 0; k < GATHER_K; ++k) {
+            const int64_t s = s0 + (int64_t)k * LPV;
+            c[k] = s < S ? tkey[s] : -1;
         }
-        Best<GT> cand{(GT)two_m * (GT)e - (GT)ki * (GT)a.a[c], c, e};
-        if (better(cand, best)) best = cand;
+#pragma unroll
+        for (int k = 0; k < GATHER_K; ++k) ac[k] = (c[k] >= 0 && c[k] != A) ? a.a[c[k]] : 0;
+#pragma unroll
+        for (int k = 0; k < GATHER_K; ++k) {
+            if (c[k] < 0) continue;
+            const int64_t e = (int64_t)tval[s0 + (int64_t)k * LPV];
+            ++distinct;
+            if (c[k] == A) {
+                eA = e;
+                continue;
+            }
+            Best<GT> cand{(GT)two_m * (GT)e - (GT)ki * (GT)ac[k], c[k], e};
+            if (better(cand, best)) best = cand;
+        }
     }
 
     // reduce over the LPV lanes of the vertex
@@ -324,30 +378,11 @@ __device__ __forceinline__ void hub_part_tile(const SweepArgs &a, const HubArgs 
     }
     for (int b = threadIdx.x; b <= P; b += BLOCK) hist[b] = 0;
     __syncthreads();
-    for (int64_t e = beg + threadIdx.x; e < end; e += BLOCK) {
-        const int32_t j = a.g.col[e];
-        const int64_t w = WLoad<WK>::at(a.g.w, e);
-        if (j == v) { // the only chunk holding the self-loop leaves it for the decision
-            h.self[h.bpre[p]] = w;
-            continue;
-        }
-        const int32_t c = a.singleton ? j : a.comm_prev[j];
-        uint32_t q = slot_hash(c, 12);
-        for (;;) {
-            int32_t cur = tkey[q];
-            if (cur == c) {
-                atomicAdd(&tval[q], (VT)w);
-                break;
-            }
-            if (cur == -1) {
-                cur = atomicCAS(&tkey[q], -1, c);
-                if (cur == -1 || cur == c) {
-                    atomicAdd(&tval[q], (VT)w);
-                    break;
-                }
-            }
-            q = (q + 1) & (HUB_T1 - 1);
-        }
+    {
+        // the only chunk holding the self-loop leaves it for the decision
+        const int64_t wself = gather_row<WK, VT>(a, v, beg + threadIdx.x, end, BLOCK, tkey, tval, 12);
+        static_assert(HUB_T1 == 1 << 12, "pass-1 table of 2^12 slots");
+        if (wself) h.self[h.bpre[p]] = wself;
     }
     __syncthreads();
     // rank of every distinct community inside its bucket, then bucket starts
@@ -617,17 +652,26 @@ __global__ __launch_bounds__(HUB_BLOCK2) void k_hub_agg(SweepArgs a, HubArgs h)
             __syncthreads();
             const bool ov = s_over != 0;
             if (!ov) {
-                for (int s = tid; s < HUB_T2; s += HUB_BLOCK2) {
-                    const int32_t c = tkey[s];
-                    if (c < 0) continue;
-                    const int64_t e = (int64_t)tval[s];
-                    ++distinct;
-                    if (c == A) {
-                        eA += e;
-                        continue;
+                static_assert(HUB_T2 % (GATHER_K * HUB_BLOCK2) == 0, "whole slot groups");
+                for (int s0 = tid; s0 < HUB_T2; s0 += GATHER_K * HUB_BLOCK2) {
+                    int32_t c[GATHER_K];
+                    int64_t ac[GATHER_K];
+#pragma unroll
+                    for (int k = 0; k < GATHER_K; ++k) c[k] = tkey[s0 + k * HUB_BLOCK2];
+#pragma unroll
+                    for (int k = 0; k < GATHER_K; ++k) ac[k] = (c[k] >= 0 && c[k] != A) ? a.a[c[k]] : 0;
+#pragma unroll
+                    for (int k = 0; k < GATHER_K; ++k) {
+                        if (c[k] < 0) continue;
+                        const int64_t e = (int64_t)tval[s0 + k * HUB_BLOCK2];
+                        ++distinct;
+                        if (c[k] == A) {
+                            eA += e;
+                            continue;
+                        }
+                        Best<GT> cand{(GT)two_m * (GT)e - (GT)kv * (GT)ac[k], c[k], e};
+                        if (better(cand, best)) best = cand;
                     }
-                    Best<GT> cand{(GT)two_m * (GT)e - (GT)kv * (GT)a.a[c], c, e};
-                    if (better(cand, best)) best = cand;
                 }
             }
             __syncthreads(); // table and flag are read by all before the next round clears them

@@ -365,3 +365,18 @@ def test_long_empty_row_gaps(L, O):
         with L.Graph.from_csr(g) as gs:
             res = gs.run(L.params(**d))
         compare_run(res, O.run(g, oracle_params(d)), f"{g.name} {d}")
+
+
+def test_gain_bound_cases(L, O):
+    """The best community need not be one of the largest edge weight: vertex 0
+    (self-loop 10) has weight 3 to the heavy star centre 1 and weight 1 to the
+    light vertex 2, and G(2) > G(1) in the first sweep; the graph is also
+    repeated with its ids reversed (the singlet rule then lets 0 move)."""
+    edges = [(0, 0), (0, 1), (0, 2), (2, 8)] + [(1, v) for v in range(3, 8)]
+    w = [10, 3, 1, 1] + [2] * 5
+    g = SG.from_edges(9, edges, w, name="gain_bound")
+    r = SG.from_edges(9, [(8 - u, 8 - v) if u >= v else (8 - v, 8 - u) for u, v in edges], w, name="gain_bound_rev")
+    for x in (g, r):
+        _steps(L, O, x, colored=False, vf=False, phases=2, iters=3)
+        for d in (dict(), dict(singlet_rule=0)):
+            compare_run(L.Graph.from_csr(x).run(L.params(**d)), O.run(x, oracle_params(d)), f"{x.name} {d}")
