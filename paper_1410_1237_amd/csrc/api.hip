@@ -884,15 +884,20 @@ louvain_status colored_iteration(G *g, int singlet, SweepSum &sum, lv::SweepStat
 }
 
 // rebuild the community graph of the current partition (Sec. 5.4 step 4)
-louvain_status coarsen_current(G *g, const int32_t *comm, int64_t &n_new)
+// vf: comm is a vertex-following map (the rebuild compacts rows, no sort)
+louvain_status coarsen_current(G *g, const int32_t *comm, int64_t &n_new, bool vf = false)
 {
     const int dst = g->cur_buf == 0 ? 1 : 0;
     lv::CoarsenBufs b{g->flag, g->new_id, g->keys, g->keys_alt, g->vals, g->vals_alt, g->run};
     int64_t nnz_new = 0;
     {
         ProfScope ps(g, PR_COARSEN, 0, (double)g->cur.nnz);
-        lv::coarsen(g->cur, comm, g->orig_map, g->n0, b, g->off_b[dst], g->col_b[dst], g->w_b[dst], g->k, g->dscal,
-                    &n_new, &nnz_new, g->scratch, g->st);
+        if (vf)
+            lv::coarsen_vf(g->cur, comm, g->k, g->orig_map, g->n0, b, g->off_b[dst], g->col_b[dst], g->w_b[dst], g->k,
+                           g->dscal, &n_new, &nnz_new, g->scratch, g->st);
+        else
+            lv::coarsen(g->cur, comm, g->orig_map, g->n0, b, g->off_b[dst], g->col_b[dst], g->w_b[dst], g->k,
+                        g->dscal, &n_new, &nnz_new, g->scratch, g->st);
     }
     g->cur.n = n_new;
     g->cur.nnz = nnz_new;
@@ -1276,7 +1281,7 @@ louvain_status louvain_vf(louvain_graph_t g, int64_t *n_new_out)
     if (g->level != 0) return fail(g, LOUVAIN_E_STATE, "vertex following applies to the input graph only");
     lv::vf_map(g->cur, g->comm_prev, g->st);
     int64_t n_new = 0;
-    if ((s = coarsen_current(g, g->comm_prev, n_new))) return s;
+    if ((s = coarsen_current(g, g->comm_prev, n_new, true))) return s;
     if (n_new_out) *n_new_out = n_new;
     return LOUVAIN_OK;
 }
@@ -1360,7 +1365,7 @@ louvain_status louvain_run(louvain_graph_t g, const louvain_params *p, int32_t *
             const auto t0 = std::chrono::steady_clock::now();
             int64_t nv = 0;
             lv::vf_map(g->cur, g->comm_prev, g->st);
-            if ((s = coarsen_current(g, g->comm_prev, nv))) return s;
+            if ((s = coarsen_current(g, g->comm_prev, nv, true))) return s;
             ms_vf = ms_since(t0);
         }
         res.n_vf = g->cur.n;
@@ -1814,7 +1819,7 @@ louvain_status louvain_batch_run(louvain_batch_t b, const louvain_params *p, int
         const int64_t n0 = g->cur.n;
         int64_t nv = 0;
         lv::vf_map(g->cur, g->comm_prev, g->st);
-        if ((s = coarsen_current(g, g->comm_prev, nv))) return s;
+        if ((s = coarsen_current(g, g->comm_prev, nv, true))) return s;
         if ((s = batch_after_coarsen(b, n0, nv))) return s;
     }
     if ((s = batch_sums(b, g->k, true, sq, nullptr, &self))) return s;

@@ -501,6 +501,190 @@ void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_ori
     rep_fold(s.rep, 1, stats + 2, st);
 }
 
+// ---- rebuild after vertex following -------------------------------------------
+// Under a vertex-following map each community is one kept vertex u (a fixed
+// point of the map) with the vertices whose only entry leads to u, so the
+// coarse row of u is u's row without the entries into its own community,
+// columns renumbered (the renumbering is monotone on the kept vertices, so
+// the row stays sorted), plus the self-loop that collects everything inside
+// the community: w_uu once and every edge to an absorbed vertex twice (both
+// of its directions lie inside).  Entry tags in A: >= 0 the coarse column,
+// else one of the following.
+constexpr int32_t VF_INSIDE = -1; // entry to a vertex the row's vertex absorbs
+constexpr int32_t VF_DROP = -2;   // entry of an absorbed vertex's row
+constexpr int32_t VF_SELF = -3;   // the row's own self-loop
+
+template <int WK>
+__global__ __launch_bounds__(BLOCK) void k_vf_entries(Csr g, const int32_t *map, const int32_t *cmap, int32_t *A,
+                                                      int64_t *wself)
+{
+    __shared__ int64_t s_off[ROWCAP + 1];
+    __shared__ int64_t s_meta[2];
+    const int64_t e0 = (int64_t)blockIdx.x * ETILE;
+    const int64_t e1 = min(e0 + ETILE, g.nnz) - 1;
+    TileRows t = tile_rows(g.off, g.n, e0, e1, s_off, s_meta);
+    for (int r = 0; r < EITEMS; ++r) {
+        const int64_t e = e0 + r * BLOCK + threadIdx.x;
+        if (e > e1) break;
+        const int64_t u = tile_row(t, g.off, s_off, e);
+        if (map[u] != u) {
+            A[e] = VF_DROP;
+            continue;
+        }
+        const int32_t v = g.col[e];
+        if (v == u) {
+            A[e] = VF_SELF;
+            wself[u] = WLoad<WK>::at(g.w, e);
+            continue;
+        }
+        const int32_t cv = cmap[v];
+        A[e] = cv == cmap[u] ? VF_INSIDE : cv;
+    }
+}
+
+// entries of each coarse row (turned into offsets by a scan) and the
+// community degree k_u + the weight of u's edges to the vertices it absorbs
+// (their degrees); run / pin: exclusive prefix counts of the kept entries and
+// prefix sums of the inside entries' weights, nnz + 1 entries each
+__global__ __launch_bounds__(BLOCK) void k_vf_rows(const int64_t *off, int64_t n, const int32_t *map,
+                                                   const int32_t *cmap, const int64_t *run, const int64_t *pin,
+                                                   const int64_t *wself, const int64_t *k_in, int64_t *cnt_out,
+                                                   int64_t *kt)
+{
+    for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < n; u += (int64_t)gridDim.x * BLOCK) {
+        if (map[u] != u) continue;
+        const int64_t b = off[u], e = off[u + 1];
+        const int64_t inside = pin[e] - pin[b];
+        const int64_t self = wself[u] + 2 * inside;
+        cnt_out[cmap[u]] = run[e] - run[b] + (self > 0 ? 1 : 0);
+        kt[u] = k_in[u] + inside;
+    }
+}
+
+// the kept entries into the coarse rows (after the self-loop's slot where the
+// row passes its own vertex)
+template <int WK>
+__global__ __launch_bounds__(BLOCK) void k_vf_write(Csr g, const int32_t *cmap, const int32_t *A, const int64_t *run,
+                                                    const int64_t *pin, const int64_t *wself, const int64_t *off_out,
+                                                    int32_t *col_out, int64_t *w_out)
+{
+    __shared__ int64_t s_off[ROWCAP + 1];
+    __shared__ int64_t s_meta[2];
+    const int64_t e0 = (int64_t)blockIdx.x * ETILE;
+    const int64_t e1 = min(e0 + ETILE, g.nnz) - 1;
+    TileRows t = tile_rows(g.off, g.n, e0, e1, s_off, s_meta);
+    for (int r = 0; r < EITEMS; ++r) {
+        const int64_t e = e0 + r * BLOCK + threadIdx.x;
+        if (e > e1) break;
+        const int32_t a = A[e];
+        if (a < 0) continue;
+        const int64_t u = tile_row(t, g.off, s_off, e);
+        const int64_t b = tile_off(t, g.off, s_off, u), en = tile_off(t, g.off, s_off, u + 1);
+        const int64_t self = wself[u] + 2 * (pin[en] - pin[b]);
+        const int64_t pos = off_out[cmap[u]] + (run[e] - run[b]) + ((self > 0 && g.col[e] > u) ? 1 : 0);
+        col_out[pos] = a;
+        w_out[pos] = WLoad<WK>::at(g.w, e);
+    }
+}
+
+// coarse degrees, and each community's self-loop at its sorted place; 2m and
+// the self-loop total into the replicated counters 0 and 2
+__global__ __launch_bounds__(BLOCK) void k_vf_self(const int64_t *off, const int32_t *col, int64_t n,
+                                                   const int32_t *map, const int32_t *cmap, const int64_t *run,
+                                                   const int64_t *pin, const int64_t *wself, const int64_t *kt,
+                                                   const int64_t *off_out, int32_t *col_out, int64_t *w_out,
+                                                   int64_t *k_out, int64_t *rep)
+{
+    __shared__ int64_t s_red[BLOCK / 64];
+    int64_t two = 0, selft = 0;
+    for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < n; u += (int64_t)gridDim.x * BLOCK) {
+        if (map[u] != u) continue;
+        const int32_t cu = cmap[u];
+        const int64_t b = off[u], e = off[u + 1];
+        const int64_t self = wself[u] + 2 * (pin[e] - pin[b]);
+        k_out[cu] = kt[u];
+        two += kt[u];
+        if (self > 0) {
+            int64_t lo = b, hi = e; // first entry of the row with a column above u
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (col[mid] <= u) lo = mid + 1;
+                else hi = mid;
+            }
+            const int64_t pos = off_out[cu] + run[lo] - run[b];
+            col_out[pos] = cu;
+            w_out[pos] = self;
+            selft += self;
+        }
+    }
+    two = block_total(two, s_red);
+    selft = block_total(selft, s_red);
+    if (threadIdx.x == 0) {
+        rep_add(rep, 0, two);
+        rep_add(rep, 2, selft);
+    }
+}
+
+void coarsen_vf(const Csr &g, const int32_t *map, const int64_t *k_in, int32_t *orig_map, int64_t n_orig,
+                CoarsenBufs &b, int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *k_out, int64_t *stats,
+                int64_t *n_new, int64_t *nnz_new, Scratch &s, hipStream_t st)
+{
+    fill<int64_t>(stats, 0, 3, st);
+    const int64_t n = g.n, nnz = g.nnz;
+    // renumber the kept vertices (every community's label) in ascending id
+    fill<int32_t>(b.flag, 0, n + 1, st);
+    unsigned gv = grid_for(n, BLOCK * 4);
+    if (gv > 65536) gv = 65536;
+    if (n > 0) k_mark<<<gv, BLOCK, 0, st>>>(map, n, b.flag);
+    scan_i32_to_i32(b.flag, b.new_id, n, s.scalar, s, st);
+    int64_t nn = 0;
+    hipMemcpyAsync(&nn, s.scalar, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    unsigned gx = grid_for(n_orig, BLOCK * 4);
+    if (gx > 65536) gx = 65536;
+    if (n_orig > 0) k_compose<<<gx, BLOCK, 0, st>>>(orig_map, n_orig, map, b.new_id);
+    *n_new = nn;
+    if (nnz == 0) {
+        fill<int64_t>(off_out, 0, nn + 1, st);
+        fill<int64_t>(k_out, 0, nn, st);
+        *nnz_new = 0;
+        return;
+    }
+    int32_t *cmap = b.flag; // free after the renumbering scan
+    k_cmap<<<gv, BLOCK, 0, st>>>(map, b.new_id, n, cmap);
+    int32_t *A = (int32_t *)b.keys;
+    int64_t *run = b.vals_alt, *pin = b.vals, *wself = b.run, *kt = (int64_t *)b.keys_alt;
+    fill<int64_t>(wself, 0, n, st);
+    const unsigned ge = grid_for(nnz, ETILE);
+    switch (g.wk) {
+    case W_UNIT: k_vf_entries<W_UNIT><<<ge, BLOCK, 0, st>>>(g, map, cmap, A, wself); break;
+    case W_I32: k_vf_entries<W_I32><<<ge, BLOCK, 0, st>>>(g, map, cmap, A, wself); break;
+    default: k_vf_entries<W_I64><<<ge, BLOCK, 0, st>>>(g, map, cmap, A, wself); break;
+    }
+    scan_nonneg(A, run, nnz, run + nnz, s, st);
+    scan_tagged_weights(A, VF_INSIDE, g.w, g.wk, pin, nnz, pin + nnz, s, st);
+    k_vf_rows<<<gv, BLOCK, 0, st>>>(g.off, n, map, cmap, run, pin, wself, k_in, off_out, kt);
+    scan_i64(off_out, off_out, nn, off_out + nn, s, st); // in place; the total is nnz'
+    int64_t tot = 0;
+    hipMemcpyAsync(&tot, off_out + nn, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    switch (g.wk) {
+    case W_UNIT: k_vf_write<W_UNIT><<<ge, BLOCK, 0, st>>>(g, cmap, A, run, pin, wself, off_out, col_out, w_out); break;
+    case W_I32: k_vf_write<W_I32><<<ge, BLOCK, 0, st>>>(g, cmap, A, run, pin, wself, off_out, col_out, w_out); break;
+    default: k_vf_write<W_I64><<<ge, BLOCK, 0, st>>>(g, cmap, A, run, pin, wself, off_out, col_out, w_out); break;
+    }
+    rep_clear(s.rep, st);
+    k_vf_self<<<gv, BLOCK, 0, st>>>(g.off, g.col, n, map, cmap, run, pin, wself, kt, off_out, col_out, w_out, k_out,
+                                    s.rep);
+    rep_fold(s.rep, 3, stats, st); // 2m, 0 (the maximum below), self-loop total
+    if (nn > 0) {
+        unsigned gm = grid_for(nn, BLOCK * 16);
+        if (gm > 4096) gm = 4096;
+        k_max<<<gm, BLOCK, 0, st>>>(k_out, nn, stats + 1);
+    }
+    hipStreamSynchronize(st);
+    *nnz_new = tot;
+}
+
 template <int WK>
 __global__ __launch_bounds__(BLOCK) void k_w64(const void *w, int64_t nnz, int64_t *out)
 {

@@ -139,6 +139,11 @@ void scan_i32_to_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *total,
 void scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, Scratch &s, hipStream_t st);
 // head flags of sorted keys (key[e] != key[e-1]) scanned into run ids: out[e] = #heads before e
 void scan_heads(const uint64_t *keys, int64_t *out, int64_t n, int64_t *total, Scratch &s, hipStream_t st);
+// out[i] = number of j < i with a[j] >= 0
+void scan_nonneg(const int32_t *a, int64_t *out, int64_t n, int64_t *total, Scratch &s, hipStream_t st);
+// out[i] = sum of the weights w[j] (kind wk) of the j < i with a[j] == tag
+void scan_tagged_weights(const int32_t *a, int32_t tag, const void *w, int wk, int64_t *out, int64_t n,
+                         int64_t *total, Scratch &s, hipStream_t st);
 int64_t scan_partials_needed(int64_t n);
 
 // stable LSD radix sort of (key, value) by the low `bits` bits of key; the
@@ -176,6 +181,13 @@ struct CoarsenBufs {
 // builds the community graph of g under comm into (off_out, col_out, w_out)
 // with its weighted degrees k_out and stats = {2m, max degree, self-loop
 // total}; returns n' and nnz' (synchronizes); composes orig_map (n_orig entries)
+// the same rebuild for a vertex-following map (every community is one kept
+// vertex and vertices whose only entry leads to it), by compaction of the
+// kept rows instead of a sort; k_in: degrees of g (read before k_out is
+// written, so k_out may alias it)
+void coarsen_vf(const Csr &g, const int32_t *map, const int64_t *k_in, int32_t *orig_map, int64_t n_orig,
+                CoarsenBufs &b, int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *k_out, int64_t *stats,
+                int64_t *n_new, int64_t *nnz_new, Scratch &s, hipStream_t st);
 void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_orig, CoarsenBufs &b,
              int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *k_out, int64_t *stats, int64_t *n_new,
              int64_t *nnz_new, Scratch &s, hipStream_t st);

@@ -62,6 +62,16 @@ struct LoadI64 {
     const int64_t *p;
     __device__ int64_t operator()(int64_t i) const { return p[i]; }
 };
+struct NonNeg { // 1 where a[i] >= 0
+    const int32_t *a;
+    __device__ int64_t operator()(int64_t i) const { return a[i] >= 0 ? 1 : 0; }
+};
+template <int WK> struct TaggedWeight { // the weight of entry i where a[i] == tag, else 0
+    const int32_t *a;
+    const void *w;
+    int32_t tag;
+    __device__ int64_t operator()(int64_t i) const { return a[i] == tag ? WLoad<WK>::at(w, i) : 0; }
+};
 struct Heads {
     const uint64_t *k;
     __device__ int64_t operator()(int64_t i) const { return (i == 0 || k[i] != k[i - 1]) ? 1 : 0; }
@@ -153,6 +163,21 @@ void scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, Scratc
 void scan_heads(const uint64_t *keys, int64_t *out, int64_t n, int64_t *total, Scratch &s, hipStream_t st)
 {
     scan_impl(Heads{keys}, out, n, total, s.part, st);
+}
+
+void scan_nonneg(const int32_t *a, int64_t *out, int64_t n, int64_t *total, Scratch &s, hipStream_t st)
+{
+    scan_impl(NonNeg{a}, out, n, total, s.part, st);
+}
+
+void scan_tagged_weights(const int32_t *a, int32_t tag, const void *w, int wk, int64_t *out, int64_t n,
+                         int64_t *total, Scratch &s, hipStream_t st)
+{
+    switch (wk) {
+    case W_UNIT: scan_impl(TaggedWeight<W_UNIT>{a, w, tag}, out, n, total, s.part, st); break;
+    case W_I32: scan_impl(TaggedWeight<W_I32>{a, w, tag}, out, n, total, s.part, st); break;
+    default: scan_impl(TaggedWeight<W_I64>{a, w, tag}, out, n, total, s.part, st); break;
+    }
 }
 
 // ---- radix sort -------------------------------------------------------------
