@@ -1,7 +1,8 @@
 // Device-wide primitives for wave64 / gfx950: exclusive prefix sums
 // (reduce-then-scan, recursive over tile partials) and a stable LSD radix
 // sort of 64-bit keys with optional 64-bit payloads (8-bit digits, per-block
-// histograms, in-block stable ranking by wave ballots).
+// histograms, in-block stable ranking by wave ballots and wave-private
+// digit counters).
 #include "lv.h"
 
 namespace lv {
@@ -197,44 +198,56 @@ __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint64_t *keys, int6
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-// Key-only passes, one tile per block: the tile's keys are ranked stably by digit (wave
-// ballots per round of BLOCK keys), placed in LDS in digit order, and then
-// written out so that consecutive threads write consecutive positions of a
-// digit's run (coalesced) instead of scattering every key.
-__global__ __launch_bounds__(BLOCK) void k_radix_scatter_keys(const uint64_t *keys, int64_t n, int shift,
-                                                             const int64_t *offs, int64_t nb, uint64_t *okeys)
+// Stable rank of a tile's keys by the digit at `shift`.  Wave w holds the
+// tile's keys [w * 64 * RADIX_ITEMS, (w + 1) * 64 * RADIX_ITEMS) in rounds of 64
+// consecutive keys, so tile order is (wave, round, lane): each wave ranks its
+// own keys with private digit counters (ballots find the lanes of a round
+// that share a digit; the first of them updates the counter), then the
+// counters are turned into per-wave offsets and digit starts with two block
+// barriers in all.  Returns each key's tile position in pr (-1 past n) and
+// the tile start of every digit in loc[0..256).
+__device__ __forceinline__ void rank_tile(const uint64_t (&kr)[RADIX_ITEMS], int shift, int64_t base, int64_t n,
+                                          int32_t (&pr)[RADIX_ITEMS], int32_t *loc, int32_t (*wcnt)[256],
+                                          int32_t *wsum)
 {
-    __shared__ uint64_t s_key[RADIX_TILE];
-    __shared__ int64_t base_off[256]; // global start of digit d for this block
-    __shared__ int32_t loc[257];      // local start of digit d in the tile
-    __shared__ int32_t run[256];
-    __shared__ int32_t wcnt[BLOCK / 64][256];
-    __shared__ int32_t wsum[BLOCK / 64];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    base_off[tid] = offs[(int64_t)tid * nb + blockIdx.x];
-    loc[tid] = 0;
-    run[tid] = 0;
 #pragma unroll
     for (int w = 0; w < BLOCK / 64; ++w) wcnt[w][tid] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * RADIX_TILE;
-    const int64_t cnt = min((int64_t)RADIX_TILE, n - base);
-    // the tile's keys, all loads issued before any is used
-    uint64_t kr[RADIX_ITEMS];
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int32_t wr[RADIX_ITEMS];
 #pragma unroll
     for (int r = 0; r < RADIX_ITEMS; ++r) {
-        const int64_t i = base + r * BLOCK + tid;
-        kr[r] = i < n ? keys[i] : ~0ull;
-    }
-    // local digit counts
+        const bool valid = base + (int64_t)wid * 64 * RADIX_ITEMS + r * 64 + lane < n;
+        const int d = (int)((kr[r] >> shift) & 255);
+        uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int r = 0; r < RADIX_ITEMS; ++r)
-        if (base + r * BLOCK + tid < n) atomicAdd(&loc[(kr[r] >> shift) & 255], 1);
+        for (int b = 0; b < 8; ++b) {
+            const int bit = (d >> b) & 1;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const int rank = __popcll(peers & lt_mask);
+        int32_t before = 0;
+        if (valid && rank == 0) {
+            before = wcnt[wid][d];
+            wcnt[wid][d] = before + __popcll(peers);
+        }
+        const int leader = valid ? __ffsll((unsigned long long)peers) - 1 : lane;
+        before = __shfl(before, leader, 64);
+        wr[r] = valid ? before + rank : -1;
+    }
     __syncthreads();
     {
-        // exclusive scan of loc[0..256) (one value per thread)
-        const int32_t v = loc[tid];
-        int32_t inc = v;
+        // digit tid: exclusive prefix over the waves, then over the digits
+        int32_t tot = 0;
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w) {
+            const int32_t c = wcnt[w][tid];
+            wcnt[w][tid] = tot;
+            tot += c;
+        }
+        int32_t inc = tot;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const int32_t y = __shfl_up(inc, o, 64);
@@ -242,57 +255,56 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter_keys(const uint64_t *ke
         }
         if (lane == 63) wsum[wid] = inc;
         __syncthreads();
-        int32_t pre = inc - v;
+        int32_t pre = inc - tot;
         for (int w = 0; w < wid; ++w) pre += wsum[w];
-        __syncthreads();
         loc[tid] = pre;
-        if (tid == 0) loc[256] = (int32_t)cnt;
     }
     __syncthreads();
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int r = 0; r < RADIX_ITEMS; ++r) {
-        const int64_t i = base + r * BLOCK + tid;
-        const bool valid = i < n;
-        const uint64_t key = kr[r];
-        const int d = (int)((key >> shift) & 255);
-        uint64_t peers = ~0ull;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const int bit = (d >> b) & 1;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        peers &= __ballot(valid);
-        const int rank = __popcll(peers & lt_mask);
-        if (valid && rank == 0) wcnt[wid][d] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            int32_t pos = loc[d] + run[d] + rank;
-            for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
-            s_key[pos] = key;
-        }
-        __syncthreads();
-        int32_t add = 0;
-#pragma unroll
-        for (int w = 0; w < BLOCK / 64; ++w) {
-            add += wcnt[w][tid];
-            wcnt[w][tid] = 0;
-        }
-        run[tid] += add;
-        __syncthreads();
+        const int d = (int)((kr[r] >> shift) & 255);
+        pr[r] = wr[r] >= 0 ? loc[d] + wcnt[wid][d] + wr[r] : -1;
     }
+}
+
+// Key-only passes, one tile per block: the tile's keys are ranked (rank_tile),
+// placed in LDS in digit order, and written out so that consecutive threads
+// write consecutive positions of a digit's run instead of scattering every key.
+__global__ __launch_bounds__(BLOCK) void k_radix_scatter_keys(const uint64_t *keys, int64_t n, int shift,
+                                                             const int64_t *offs, int64_t nb, uint64_t *okeys)
+{
+    __shared__ uint64_t s_key[RADIX_TILE];
+    __shared__ int64_t base_off[256]; // global start of digit d for this block
+    __shared__ int32_t loc[256];      // local start of digit d in the tile
+    __shared__ int32_t wcnt[BLOCK / 64][256];
+    __shared__ int32_t wsum[BLOCK / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    base_off[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * RADIX_TILE;
+    const int64_t cnt = min((int64_t)RADIX_TILE, n - base);
+    // the wave's keys, all loads issued before any is used
+    uint64_t kr[RADIX_ITEMS];
+#pragma unroll
+    for (int r = 0; r < RADIX_ITEMS; ++r) {
+        const int64_t i = base + (int64_t)wid * 64 * RADIX_ITEMS + r * 64 + lane;
+        kr[r] = i < n ? keys[i] : ~0ull;
+    }
+    int32_t pr[RADIX_ITEMS];
+    rank_tile(kr, shift, base, n, pr, loc, wcnt, wsum);
+#pragma unroll
+    for (int r = 0; r < RADIX_ITEMS; ++r)
+        if (pr[r] >= 0) s_key[pr[r]] = kr[r];
+    __syncthreads();
     // write out: position j of the tile holds digit d = its key's digit
     for (int32_t j = tid; j < cnt; j += BLOCK) {
         const uint64_t key = s_key[j];
         const int d = (int)((key >> shift) & 255);
-        const int64_t pos = base_off[d] + (j - loc[d]);
-        okeys[pos] = key;
+        okeys[base_off[d] + (j - loc[d])] = key;
     }
 }
 
 // Key-value passes: the same ranking; keys, then values, go through one LDS
-// staging buffer in digit order (local positions kept in registers) so both
+// staging buffer in digit order (tile positions kept in registers) so both
 // are written out in runs.
 __global__ __launch_bounds__(BLOCK) void k_radix_scatter_kv(const uint64_t *keys, const int64_t *vals, int64_t n,
                                                           int shift, const int64_t *offs, int64_t nb,
@@ -301,77 +313,23 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter_kv(const uint64_t *keys
     __shared__ uint64_t s_buf[RADIX_TILE];
     __shared__ uint8_t s_dig[RADIX_TILE];
     __shared__ int64_t base_off[256];
-    __shared__ int32_t loc[257];
-    __shared__ int32_t run[256];
+    __shared__ int32_t loc[256];
     __shared__ int32_t wcnt[BLOCK / 64][256];
     __shared__ int32_t wsum[BLOCK / 64];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     base_off[tid] = offs[(int64_t)tid * nb + blockIdx.x];
-    loc[tid] = 0;
-    run[tid] = 0;
-#pragma unroll
-    for (int w = 0; w < BLOCK / 64; ++w) wcnt[w][tid] = 0;
-    __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RADIX_TILE;
     const int64_t cnt = min((int64_t)RADIX_TILE, n - base);
     uint64_t kr[RADIX_ITEMS];
     int64_t vr[RADIX_ITEMS];
 #pragma unroll
     for (int r = 0; r < RADIX_ITEMS; ++r) {
-        const int64_t i = base + r * BLOCK + tid;
+        const int64_t i = base + (int64_t)wid * 64 * RADIX_ITEMS + r * 64 + lane;
         kr[r] = i < n ? keys[i] : ~0ull;
         vr[r] = i < n ? vals[i] : 0;
     }
-#pragma unroll
-    for (int r = 0; r < RADIX_ITEMS; ++r)
-        if (base + r * BLOCK + tid < n) atomicAdd(&loc[(kr[r] >> shift) & 255], 1);
-    __syncthreads();
-    {
-        const int32_t v = loc[tid];
-        int32_t inc = v;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int32_t y = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += y;
-        }
-        if (lane == 63) wsum[wid] = inc;
-        __syncthreads();
-        int32_t pre = inc - v;
-        for (int w = 0; w < wid; ++w) pre += wsum[w];
-        __syncthreads();
-        loc[tid] = pre;
-    }
-    __syncthreads();
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int32_t pr[RADIX_ITEMS];
-#pragma unroll
-    for (int r = 0; r < RADIX_ITEMS; ++r) {
-        const bool valid = base + r * BLOCK + tid < n;
-        const int d = (int)((kr[r] >> shift) & 255);
-        uint64_t peers = ~0ull;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const int bit = (d >> b) & 1;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        peers &= __ballot(valid);
-        const int rank = __popcll(peers & lt_mask);
-        if (valid && rank == 0) wcnt[wid][d] = __popcll(peers);
-        __syncthreads();
-        int32_t pos = loc[d] + run[d] + rank;
-        for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
-        pr[r] = valid ? pos : -1;
-        __syncthreads();
-        int32_t add = 0;
-#pragma unroll
-        for (int w = 0; w < BLOCK / 64; ++w) {
-            add += wcnt[w][tid];
-            wcnt[w][tid] = 0;
-        }
-        run[tid] += add;
-        __syncthreads();
-    }
+    rank_tile(kr, shift, base, n, pr, loc, wcnt, wsum);
     // keys
 #pragma unroll
     for (int r = 0; r < RADIX_ITEMS; ++r)
