@@ -257,10 +257,13 @@ struct SweepArgs {
 // the community's hash bucket (a hub has P = 2^k buckets, about one per
 // HUB_BUCKET entries, at most HUB_PMAX), with the P + 1 bucket boundaries in
 // boff.  Pass 2: one workgroup per (hub, bucket) sums the bucket's segments of
-// every chunk, evaluates the gains and leaves the bucket's best; the last
-// bucket of a hub decides.  Per-position prefixes over the sorted vertex
+// every chunk, evaluates the gains and leaves the bucket's best; one
+// wavefront per hub then decides from its buckets' records.  Chunks are half
+// the bucket size: on R-MAT the short chunk launches of the colour classes
+// finish sooner, and the bucket tables stay as full as before.  Per-position
+// prefixes over the sorted vertex
 // list: cpre (chunks), bpre (buckets), xpre (boundary entries).
-constexpr int HUB_CHUNK = 2048;
+constexpr int HUB_CHUNK = 1024;
 constexpr int64_t HUB_BUCKET = 2048;
 constexpr int HUB_PMAX = 1024;
 __host__ __device__ inline int hub_buckets(int64_t d)

@@ -4,8 +4,9 @@
 // Every vertex of a launch reads only the state of the previous iteration
 // (or colour class): comm_prev, a (community degrees) and size.  A group of
 // LPV lanes gathers the vertex's row, sums the edge weight per neighbouring
-// community e_{i->c} in an open-addressed hash table (LDS for rows up to
-// 2048 entries, a per-vertex HBM table for hubs), then evaluates the exact
+// community e_{i->c} in an open-addressed LDS hash table (rows up to 2048
+// entries; longer rows in chunks whose tables are merged per hash bucket by
+// a second pass), then evaluates the exact
 // integer gain G(c) = 2m*e_{i->c} - k_i*a_c for every distinct community and
 // reduces the lexicographic maximum of (G, -c) with wave shuffles.  The
 // vertex moves iff G(c*) > G_stay = 2m*e_{i->A\{i}} - k_i*(a_A - k_i) and the
@@ -291,7 +292,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const BinRange &b
 // Pass 1 (partition) and pass 2 (aggregate) keep every per-community sum in
 // LDS; HBM only carries the chunks' distinct pairs between the passes, so no
 // HBM location is updated by more than one workgroup.
-constexpr int HUB_T1 = 2 * HUB_CHUNK; // pass-1 table slots (2^12)
+constexpr int HUB_T1 = 2 * HUB_CHUNK; // pass-1 table slots (2^11)
 constexpr int HUB_T2 = 4096;          // pass-2 table slots (2^12)
 constexpr int HUB_CAP2 = 3072;        // distinct keys one pass-2 round may hold
 constexpr int HUB_BLOCK2 = 512;
@@ -380,8 +381,8 @@ __device__ __forceinline__ void hub_part_tile(const SweepArgs &a, const HubArgs 
     __syncthreads();
     {
         // the only chunk holding the self-loop leaves it for the decision
-        const int64_t wself = gather_row<WK, VT>(a, v, beg + threadIdx.x, end, BLOCK, tkey, tval, 12);
-        static_assert(HUB_T1 == 1 << 12, "pass-1 table of 2^12 slots");
+        const int64_t wself = gather_row<WK, VT>(a, v, beg + threadIdx.x, end, BLOCK, tkey, tval, 11);
+        static_assert(HUB_T1 == 1 << 11, "pass-1 table of 2^11 slots");
         if (wself) h.self[h.bpre[p]] = wself;
     }
     __syncthreads();
