@@ -190,13 +190,26 @@ __global__ __launch_bounds__(BLOCK) void k_jp_round(Csr g, uint64_t seed, JpList
             const int32_t v = in.light[f];
             const int64_t b = g.off[v], e = g.off[v + 1];
             const uint64_t pv = jp_priority(seed, v);
-            const int32_t c = jp_wave_mex(g, seed, v, pv, b, e, color, 0);
-            if (lane == 0) color[v] = c;
+            // one pass over the row: colours below 64 of the higher-priority
+            // neighbours, decrements of the lower-priority ones (their pushes
+            // are for the next round, which is the first to read v's colour)
+            unsigned long long used = 0;
             for (int64_t x = b + lane; x < e; x += 64) {
                 const int32_t u = g.col[x];
-                const bool ready = u != v && jp_priority(seed, u) < pv && atomicSub(&cnt[u], 1) == 1;
+                bool ready = false;
+                if (u != v) {
+                    if (jp_priority(seed, u) > pv) {
+                        const int32_t cu = color[u];
+                        if (cu >= 0 && cu < 64) used |= 1ull << cu;
+                    } else {
+                        ready = atomicSub(&cnt[u], 1) == 1;
+                    }
+                }
                 jp_push(g, ready, u, out, next);
             }
+            used = wave_or(used);
+            const int32_t c = used != ~0ull ? __ffsll(~used) - 1 : jp_wave_mex(g, seed, v, pv, b, e, color, 64);
+            if (lane == 0) color[v] = c;
         }
         return;
     }
