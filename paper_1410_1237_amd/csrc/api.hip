@@ -246,7 +246,8 @@ struct louvain_graph_s {
     int32_t *pkey = nullptr, *boff = nullptr;
     uint64_t *pval = nullptr;
     int64_t *hpart = nullptr, *hself = nullptr;
-    int32_t *chunk_pos = nullptr, *bucket_pos = nullptr;
+    lv::HubChunk *chunk_rec = nullptr;
+    lv::HubBucket *bucket_rec = nullptr;
     int64_t pcap = 0, xcap = 0, qcap = 0;   // pairs, bucket boundaries, buckets allocated
     std::vector<lv::HubArgs> hub_groups;    // per group (e <= s when the group has no hub)
 
@@ -541,10 +542,10 @@ louvain_status build_bins(G *g, bool by_color, bool mask_inactive = false)
     if (pairs > g->pcap) {
         release_buffer(g, g->pkey);
         release_buffer(g, g->pval);
-        release_buffer(g, g->chunk_pos);
+        release_buffer(g, g->chunk_rec);
         const int64_t cap = pairs + pairs / 4 + lv::HUB_CHUNK;
         if ((s = alloc(g, &g->pkey, cap)) || (s = alloc(g, &g->pval, cap)) ||
-            (s = alloc(g, &g->chunk_pos, cap / lv::HUB_CHUNK + 1)))
+            (s = alloc(g, &g->chunk_rec, cap / lv::HUB_CHUNK + 1)))
             return s;
         g->pcap = cap;
     }
@@ -557,16 +558,16 @@ louvain_status build_bins(G *g, bool by_color, bool mask_inactive = false)
     if (tot[1] > g->qcap) {
         release_buffer(g, g->hpart);
         release_buffer(g, g->hself);
-        release_buffer(g, g->bucket_pos);
+        release_buffer(g, g->bucket_rec);
         const int64_t cap = tot[1] + tot[1] / 4 + 64;
         if ((s = alloc(g, &g->hpart, lv::HUB_REC * cap)) || (s = alloc(g, &g->hself, cap)) ||
-            (s = alloc(g, &g->bucket_pos, cap)))
+            (s = alloc(g, &g->bucket_rec, cap)))
             return s;
         g->qcap = cap;
         lv::fill<int64_t>(g->hself, 0, cap, g->st); // the hub decisions leave it zero
     }
     if (!with_hubs.empty()) {
-        lv::hub_owners(g->cpre, g->bpre, n, g->chunk_pos, g->bucket_pos, g->st);
+        lv::hub_owners(g->bin_verts, g->cur.off, g->cpre, g->bpre, g->xpre, n, g->chunk_rec, g->bucket_rec, g->st);
         const int64_t m = (int64_t)idx.size();
         // gather cpre and bpre at the range ends: device scratch in vals_alt (free here)
         int64_t *didx = g->vals_alt, *dout = g->vals_alt + m;
@@ -584,8 +585,8 @@ louvain_status build_bins(G *g, bool by_color, bool mask_inactive = false)
             h.cpre = g->cpre;
             h.bpre = g->bpre;
             h.xpre = g->xpre;
-            h.chunk_pos = g->chunk_pos;
-            h.bucket_pos = g->bucket_pos;
+            h.chunks = g->chunk_rec;
+            h.buckets = g->bucket_rec;
             h.chunk0 = vals[2 * t];
             h.n_chunks = vals[2 * t + 1] - h.chunk0;
             h.bucket0 = vals[m + 2 * t];

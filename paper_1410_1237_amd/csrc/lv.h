@@ -271,12 +271,29 @@ __host__ __device__ inline int hub_buckets(int64_t d)
     const int64_t p = pow2_ceil((d + HUB_BUCKET - 1) / HUB_BUCKET);
     return (int)(p < HUB_PMAX ? p : HUB_PMAX);
 }
+// What a hub's pass-1 block (one chunk) and pass-2 block (one bucket) need,
+// gathered once per binning so that a block starts from one record instead
+// of a chain of dependent lookups (owner position, vertex, prefixes, offsets).
+struct HubChunk {
+    int32_t v, P;      // the hub and its bucket count
+    int64_t beg, end;  // the chunk's entries
+    int64_t bo;        // its P + 1 bucket boundaries in boff
+    int64_t self_slot; // the hub's first bucket (self-loop slot)
+    int64_t pad;
+};
+struct HubBucket {
+    int32_t v, P, b, pad; // the hub, its bucket count, this bucket
+    int64_t c0, nch;      // the hub's chunks
+    int64_t xo;           // the hub's boundaries in boff
+    int64_t pad2;
+};
+
 struct HubArgs {
     const int32_t *verts = nullptr; // sorted vertex list (positions are absolute)
     int64_t s = 0, e = 0;           // hub positions [s, e) of this launch group
     const int64_t *cpre = nullptr, *bpre = nullptr, *xpre = nullptr; // n + 1 each
-    const int32_t *chunk_pos = nullptr;  // per chunk: position of its hub
-    const int32_t *bucket_pos = nullptr; // per bucket: position of its hub
+    const struct HubChunk *chunks = nullptr;   // per chunk: what its pass-1 block reads
+    const struct HubBucket *buckets = nullptr; // per bucket: what its pass-2 block reads
     int64_t chunk0 = 0, n_chunks = 0;   // cpre[s], cpre[e] - cpre[s]
     int64_t bucket0 = 0, n_buckets = 0; // bpre[s], bpre[e] - bpre[s]
     int32_t *pkey = nullptr;        // HUB_CHUNK pairs per chunk
@@ -335,8 +352,10 @@ void narrow_ids(const int64_t *vals, int32_t *out, int64_t n, hipStream_t st);
 // and bucket-boundary entries (n + 1 each; the totals land at index count)
 void hub_prefix(const Csr &g, const int32_t *verts, int64_t count, int64_t *cpre, int64_t *bpre, int64_t *xpre,
                 Scratch &s, hipStream_t st);
-// chunk_pos[c] / bucket_pos[q] = the position whose hub owns chunk c / bucket q
-void hub_owners(const int64_t *cpre, const int64_t *bpre, int64_t count, int32_t *chunk_pos, int32_t *bucket_pos,
+// the chunk and bucket records of the hubs among positions [0, count) of the
+// sorted vertex list verts
+void hub_owners(const int32_t *verts, const int64_t *off, const int64_t *cpre, const int64_t *bpre,
+                const int64_t *xpre, int64_t count, HubChunk *chunks, HubBucket *buckets,
                 hipStream_t st);
 void gather_i64(const int64_t *src, const int64_t *idx, int64_t n, int64_t *out, hipStream_t st);
 // community degree/size updates for movers in the list (or all vertices if verts == null)

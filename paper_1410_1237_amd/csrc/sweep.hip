@@ -364,14 +364,11 @@ __device__ __forceinline__ void hub_part_tile(const SweepArgs &a, const HubArgs 
     VT *tval = (VT *)(smem + HUB_T1 * sizeof(int32_t));
     int32_t *hist = (int32_t *)(smem + HUB_T1 * (sizeof(int32_t) + sizeof(VT)));
     const int64_t target = h.chunk0 + tile;
-    const int64_t p = h.chunk_pos[target];
-    const int32_t v = h.verts[p];
+    const HubChunk ck = h.chunks[target];
+    const int32_t v = ck.v;
     if (!sweeping(a, v)) return; // uniform over the block
-    const int64_t lc = target - h.cpre[p];
-    const int64_t rb = a.g.off[v], re = a.g.off[v + 1];
-    const int64_t beg = rb + lc * HUB_CHUNK;
-    const int64_t end = min(re, beg + HUB_CHUNK);
-    const int P = (int)(h.bpre[p + 1] - h.bpre[p]);
+    const int64_t beg = ck.beg, end = ck.end;
+    const int P = ck.P;
     const int lp = __ffs(P) - 1;
     for (int s = threadIdx.x; s < HUB_T1; s += BLOCK) {
         tkey[s] = -1;
@@ -383,7 +380,7 @@ __device__ __forceinline__ void hub_part_tile(const SweepArgs &a, const HubArgs 
         // the only chunk holding the self-loop leaves it for the decision
         const int64_t wself = gather_row<WK, VT>(a, v, beg + threadIdx.x, end, BLOCK, tkey, tval, 11);
         static_assert(HUB_T1 == 1 << 11, "pass-1 table of 2^11 slots");
-        if (wself) h.self[h.bpre[p]] = wself;
+        if (wself) h.self[ck.self_slot] = wself;
     }
     __syncthreads();
     // rank of every distinct community inside its bucket, then bucket starts
@@ -407,7 +404,7 @@ __device__ __forceinline__ void hub_part_tile(const SweepArgs &a, const HubArgs 
         h.pkey[at] = c;
         pval[at] = tval[s];
     }
-    int32_t *bo = h.boff + h.xpre[p] + lc * (P + 1);
+    int32_t *bo = h.boff + ck.bo;
     for (int b = threadIdx.x; b <= P; b += BLOCK) bo[b] = hist[b];
 }
 
@@ -566,13 +563,13 @@ __global__ __launch_bounds__(HUB_BLOCK2) void k_hub_agg(SweepArgs a, HubArgs h)
     __shared__ Best<GT> sb[HUB_BLOCK2 / 64];
     __shared__ int64_t se[HUB_BLOCK2 / 64][2];
     const int64_t q = h.bucket0 + blockIdx.x;
-    const int64_t p = h.bucket_pos[q];
-    const int32_t v = h.verts[p];
+    const HubBucket bk = h.buckets[q];
+    const int32_t v = bk.v;
     if (!sweeping(a, v)) return; // uniform over the block
-    const int P = (int)(h.bpre[p + 1] - h.bpre[p]);
-    const int b = (int)(q - h.bpre[p]);
-    const int64_t c0 = h.cpre[p], nch = h.cpre[p + 1] - c0;
-    const int32_t *bo = h.boff + h.xpre[p];
+    const int P = bk.P;
+    const int b = bk.b;
+    const int64_t c0 = bk.c0, nch = bk.nch;
+    const int32_t *bo = h.boff + bk.xo;
     const VT *pval = (const VT *)h.pval;
     const int32_t A = a.comm_prev[v];
     const int64_t two_m = two_m_of(a, v), kv = a.k[v];
@@ -925,22 +922,50 @@ void hub_prefix(const Csr &g, const int32_t *verts, int64_t count, int64_t *cpre
 }
 
 
-__global__ __launch_bounds__(BLOCK) void k_hub_owners(const int64_t *cpre, const int64_t *bpre, int64_t count,
-                                                      int32_t *chunk_pos, int32_t *bucket_pos)
+__global__ __launch_bounds__(BLOCK) void k_hub_owners(const int32_t *verts, const int64_t *off, const int64_t *cpre,
+                                                      const int64_t *bpre, const int64_t *xpre, int64_t count,
+                                                      HubChunk *chunks, HubBucket *buckets)
 {
     for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < count; p += (int64_t)gridDim.x * BLOCK) {
-        for (int64_t c = cpre[p]; c < cpre[p + 1]; ++c) chunk_pos[c] = (int32_t)p;
-        for (int64_t q = bpre[p]; q < bpre[p + 1]; ++q) bucket_pos[q] = (int32_t)p;
+        const int64_t c0 = cpre[p], c1 = cpre[p + 1];
+        if (c1 == c0) continue; // not a hub
+        const int32_t v = verts[p];
+        const int64_t rb = off[v], re = off[v + 1];
+        const int64_t q0 = bpre[p], q1 = bpre[p + 1];
+        const int32_t P = (int32_t)(q1 - q0);
+        for (int64_t c = c0; c < c1; ++c) {
+            HubChunk k;
+            k.v = v;
+            k.P = P;
+            k.beg = rb + (c - c0) * HUB_CHUNK;
+            k.end = min(re, k.beg + HUB_CHUNK);
+            k.bo = xpre[p] + (c - c0) * (P + 1);
+            k.self_slot = q0;
+            k.pad = 0;
+            chunks[c] = k;
+        }
+        for (int64_t q = q0; q < q1; ++q) {
+            HubBucket k;
+            k.v = v;
+            k.P = P;
+            k.b = (int32_t)(q - q0);
+            k.pad = 0;
+            k.c0 = c0;
+            k.nch = c1 - c0;
+            k.xo = xpre[p];
+            k.pad2 = 0;
+            buckets[q] = k;
+        }
     }
 }
 
-void hub_owners(const int64_t *cpre, const int64_t *bpre, int64_t count, int32_t *chunk_pos, int32_t *bucket_pos,
-                hipStream_t st)
+void hub_owners(const int32_t *verts, const int64_t *off, const int64_t *cpre, const int64_t *bpre,
+                const int64_t *xpre, int64_t count, HubChunk *chunks, HubBucket *buckets, hipStream_t st)
 {
     if (count <= 0) return;
     unsigned gb = grid_for(count, BLOCK * 4);
     if (gb > 65536) gb = 65536;
-    k_hub_owners<<<gb, BLOCK, 0, st>>>(cpre, bpre, count, chunk_pos, bucket_pos);
+    k_hub_owners<<<gb, BLOCK, 0, st>>>(verts, off, cpre, bpre, xpre, count, chunks, buckets);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_gather_i64(const int64_t *src, const int64_t *idx, int64_t n, int64_t *out)
