@@ -29,7 +29,7 @@ def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
-            raise RuntimeError(f"graph generator library not built: {_LIB} (run __graft_entry__.build())")
+            raise RuntimeError(f"graph generator library not built: {_LIB} (run python -m paper_1410_1237_amd.build)")
         lib = ctypes.CDLL(_LIB)
         vp, i64, i32, u64, u32, dbl = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                        ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double)
