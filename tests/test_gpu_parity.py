@@ -380,3 +380,44 @@ def test_gain_bound_cases(L, O):
         _steps(L, O, x, colored=False, vf=False, phases=2, iters=3)
         for d in (dict(), dict(singlet_rule=0)):
             compare_run(L.Graph.from_csr(x).run(L.params(**d)), O.run(x, oracle_params(d)), f"{x.name} {d}")
+
+
+def heavy_graph(seed, n, extra, hub_deg, name):
+    """Weights uniform in [2^30, 2^31 - 1]: 2m * k_max is far above 2^62, so
+    gains take the 128-bit path and the LDS sums the 64-bit one (vertex 0 is
+    a hub of hub_deg neighbours when hub_deg > 0)."""
+    rng = np.random.default_rng(seed)
+    edges = set()
+    if hub_deg:
+        for v in rng.choice(np.arange(1, n), size=hub_deg, replace=False):
+            edges.add((0, int(v)))
+    while len(edges) < hub_deg + extra:
+        u, v = (int(x) for x in rng.integers(0, n, 2))
+        if u != v:
+            edges.add((min(u, v), max(u, v)))
+    edges = sorted(edges)
+    w = rng.integers(1 << 30, (1 << 31) - 1, size=len(edges))
+    return SG.from_edges(n, edges, w, name=name)
+
+
+def test_wide_gains(L, O):
+    """The 128-bit gain path (2m * k_max >= 2^62) of every kernel that
+    evaluates gains: the binned sweep, both hub passes, the hub decision of
+    the plain and the coloured commit, and the batched form."""
+    gs = [heavy_graph(5, 60, 300, 0, "heavy_small"), heavy_graph(6, 6000, 20000, 3000, "heavy_hub")]
+    for g in gs:
+        with L.Graph.from_csr(g) as h:
+            info = h.info()
+        assert info["two_m"] * info["k_max"] >= 1 << 62 and info["two_m"] < 1 << 62, g.name
+        _steps(L, O, g, colored=False, vf=True, phases=2, iters=3)
+        _steps(L, O, g, colored=True, vf=False, phases=2, iters=3)
+        for d in (dict(), dict(vf=1, color=1, color_cutoff=10)):
+            with L.Graph.from_csr(g) as h:
+                res = h.run(L.params(**d))
+            compare_run(res, O.run(g, oracle_params(d)), f"{g.name} {d}")
+    b = L.Batch.from_graphs(gs)
+    res = b.run(L.params())
+    b.close()
+    for g, r in zip(gs, res):
+        ref = O.run(g, oracle.Params())
+        assert np.array_equal(r.labels, ref.labels) and (r.N, r.D) == (ref.N, ref.D), g.name
