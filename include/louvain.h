@@ -294,10 +294,10 @@ const char *louvain_batch_last_error(louvain_batch_t b);
 
 /*
  * A request loop with continuous batching: jobs (host CSRs, copied at submit,
- * or borrowed until they finish) queue FIFO; a scheduler thread admits jobs
- * from the queue head into a new batch whenever fewer than
- * max_inflight_batches batches run and the HBM budget covers the batch's
- * estimated device footprint; each batch runs the batched form on its own
+ * or borrowed until they finish) queue in arrival order; a scheduler thread
+ * admits a new batch whenever fewer than max_inflight_batches batches run and
+ * the HBM budget covers its estimated device footprint (a large job at the
+ * queue head alone, else the queued small jobs in order, passing large ones); each batch runs the batched form on its own
  * worker thread and HIP stream, so batches admitted at different times
  * overlap on the device, and memory returned by a finished batch admits the
  * next jobs.  A job of at least solo_min_vertices vertices is a batch of its

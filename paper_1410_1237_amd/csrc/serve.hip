@@ -2,9 +2,10 @@
 // batches while other batches are on the device.
 //
 // Jobs are queued FIFO with a copy of their CSR (or, submitted as borrowed,
-// with the caller's arrays).  A scheduler thread forms a batch from the
-// queue head whenever a worker slot is free and the HBM budget covers the
-// batch's estimated footprint; each batch runs on its own worker thread and
+// with the caller's arrays).  A scheduler thread forms a batch whenever a
+// worker slot is free and the HBM budget covers the batch's estimated
+// footprint: a large job at the queue head alone, else the queued small jobs
+// in order (large ones they pass wait for the head); each batch runs on its own worker thread and
 // HIP stream through the batched form, so batches admitted at different
 // times overlap on the device; a batch's jobs are copied to the device as
 // they are and packed there.  A job of at least solo_min_vertices vertices
@@ -242,31 +243,53 @@ void schedule(S *s)
             if (s->stop) break;
             continue;
         }
-        // admit from the queue head while the budget allows
+        // admission: a large job at the queue head runs alone; otherwise the
+        // batch takes the small jobs in queue order up to the limits, and the
+        // large jobs it passes stay queued until they reach the head (small
+        // jobs behind a large one need not wait for it to be admitted)
         std::vector<std::shared_ptr<Job>> batch;
         uint64_t bytes = 0;
         int64_t verts = 0;
-        while (!s->queue.empty() && (int64_t)batch.size() < s->cfg.max_batch_graphs) {
-            auto &j = s->queue.front();
-            if (j->bytes > s->cfg.hbm_budget_bytes) { // can never fit: fail it
-                j->status = LOUVAIN_E_OOM;
-                j->done = true;
-                j->t_done = s->now();
-                s->pending -= 1;
-                s->queue.pop_front();
-                s->cv.notify_all();
-                continue;
-            }
-            const bool solo = j->solo;
-            if (solo && !batch.empty()) break; // a large job is the next batch, alone
-            if (s->reserved + bytes + j->bytes > s->cfg.hbm_budget_bytes) break;
-            if (!batch.empty() && s->cfg.max_batch_vertices > 0 && verts + j->n > s->cfg.max_batch_vertices) break;
-            bytes += j->bytes;
-            verts += j->n;
-            j->t_admit = s->now();
-            batch.push_back(j);
+        auto fail_oom = [&](const std::shared_ptr<Job> &j) { // can never fit
+            j->status = LOUVAIN_E_OOM;
+            j->done = true;
+            j->t_done = s->now();
+            s->pending -= 1;
+            s->cv.notify_all();
+        };
+        while (!s->queue.empty() && s->queue.front()->bytes > s->cfg.hbm_budget_bytes) {
+            fail_oom(s->queue.front());
             s->queue.pop_front();
-            if (solo) break;
+        }
+        if (!s->queue.empty() && s->queue.front()->solo) {
+            auto &j = s->queue.front();
+            if (s->reserved + j->bytes <= s->cfg.hbm_budget_bytes) {
+                bytes = j->bytes;
+                verts = j->n;
+                j->t_admit = s->now();
+                batch.push_back(j);
+                s->queue.pop_front();
+            }
+        } else {
+            for (auto it = s->queue.begin(); it != s->queue.end() && (int64_t)batch.size() < s->cfg.max_batch_graphs;) {
+                const std::shared_ptr<Job> j = *it;
+                if (j->bytes > s->cfg.hbm_budget_bytes) {
+                    fail_oom(j);
+                    it = s->queue.erase(it);
+                    continue;
+                }
+                if (j->solo) {
+                    ++it;
+                    continue;
+                }
+                if (s->reserved + bytes + j->bytes > s->cfg.hbm_budget_bytes) break;
+                if (!batch.empty() && s->cfg.max_batch_vertices > 0 && verts + j->n > s->cfg.max_batch_vertices) break;
+                bytes += j->bytes;
+                verts += j->n;
+                j->t_admit = s->now();
+                batch.push_back(j);
+                it = s->queue.erase(it);
+            }
         }
         if (batch.empty()) {
             // the head needs memory still held by running batches: wait for one to finish
