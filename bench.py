@@ -333,8 +333,8 @@ def main():
                          "known size, to calibrate HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
-              "(multi-GPU sharding is a design, not part of it); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the hot path runs on a single MI355X (sharding across GPUs is "
+              "described, not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.form == "batched":
         return bench_batched(args)
