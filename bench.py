@@ -406,9 +406,15 @@ def main():
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         tot_ms = sum(v["ms"] for v in sweep.values())
         tot_b = sum(v["bytes"] for v in sweep.values())
+        traffic = load_traffic(name, args.workload, run)
+        # the counters' bytes over the same launch time: how much of the peak
+        # the kernel's actual (line-granular) traffic takes
+        rate = traffic / (avg_ms * 1e-3) / 1e9 if traffic else None
         return {"bound": "hbm", "kernel": name, "run": run, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": load_traffic(name, args.workload, run),
+                "traffic": traffic,
+                "traffic_GBps": round(rate, 1) if rate else None,
+                "traffic_frac": round(rate / HBM_PEAK_GBS, 4) if rate else None,
                 "launches": r["launches"], "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": round(per_launch),
                 "all_sweep_kernels": {"ms": round(tot_ms, 3), "GBps": round(tot_b / (tot_ms * 1e-3) / 1e9, 1),
