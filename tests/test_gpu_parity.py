@@ -421,3 +421,18 @@ def test_wide_gains(L, O):
     for g, r in zip(gs, res):
         ref = O.run(g, oracle.Params())
         assert np.array_equal(r.labels, ref.labels) and (r.N, r.D) == (ref.N, ref.D), g.name
+
+
+def test_vf_rebuild_cases(L, O):
+    """The vertex-following rebuild on a graph with every case: a kept vertex
+    with a self-loop and two absorbed leaves, a leaf on another kept vertex,
+    an isolated pair, an isolated vertex, a vertex whose only entry is a
+    self-loop, and a chain (a degree-1 end on a degree-2 vertex)."""
+    edges = [(0, 0), (0, 1), (0, 2), (0, 3), (3, 4), (5, 6), (8, 8), (3, 9), (9, 10), (10, 11), (11, 12)]
+    w = [5, 3, 4, 2, 1, 7, 9, 1, 2, 6, 8]
+    g = SG.from_edges(14, edges, w, name="vf_cases")
+    _steps(L, O, g, colored=False, vf=True, phases=2, iters=3)
+    for d in (dict(vf=1), dict(vf=1, color=1, color_cutoff=1), dict(vf=1, singlet_rule=0)):
+        with L.Graph.from_csr(g) as h:
+            res = h.run(L.params(**d))
+        compare_run(res, O.run(g, oracle_params(d)), f"vf_cases {d}")
