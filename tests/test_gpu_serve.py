@@ -163,3 +163,24 @@ def test_served_invalid_job_fails_alone(L, O):
     for g, info in zip(good, infos[:3] + infos[5:]):
         check_job(L, O, g, info, solo(L, g, p), g.name)
     s.close()
+
+
+def test_served_invalid_large_job(L, O):
+    """A job large enough to run alone that fails the device validation fails
+    with LOUVAIN_E_BAD_CSR; the server keeps serving."""
+    big = GG.batch_sbm(150)
+    assert big.n >= 2000
+    bad = SG.CSR(big.n, big.offsets.copy(), big.cols.copy(), None if big.weights is None else big.weights.copy())
+    bad.name = "asym"
+    row0 = slice(int(bad.offsets[0]), int(bad.offsets[1]))
+    bad.cols[row0] = np.sort((bad.cols[row0] + 1) % bad.n)  # row 0's entries lose their mirrors
+    p = L.params()
+    s = L.Server(p, solo_min_vertices=1000)
+    t_bad = s.submit(bad, borrow=True)
+    t_ok = s.submit(big)
+    s.wait_all()
+    assert s.poll(t_bad).status == L.E_BAD_CSR
+    info = s.poll(t_ok)
+    check_job(L, O, big, info, solo(L, big, p), big.name)
+    assert info.batch_graphs == 1
+    s.close()
