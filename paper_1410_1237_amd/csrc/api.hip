@@ -854,10 +854,13 @@ louvain_status sum_sq(G *g, const int64_t *x, int64_t n, i128 &out)
     return read_i128(g, g->dscal + 4, out);
 }
 
+// commit of an uncoloured sweep: the vertices of bins 1..10 (bin 0 holds the
+// rows without entries, which have no candidate and never move)
 louvain_status commit_all(G *g)
 {
-    ProfScope ps(g, PR_COMMIT, 8.0 * (double)g->cur.n, 0);
-    lv::commit(nullptr, g->cur.n, g->comm_prev, g->comm_next, g->k, g->a, g->size, g->st);
+    const int64_t s = g->bin_off[1], e = g->bin_off[11];
+    ProfScope ps(g, PR_COMMIT, 8.0 * (double)(e - s), 0);
+    lv::commit(g->bin_verts + s, e - s, g->comm_prev, g->comm_next, g->k, g->a, g->size, g->st);
     g->singleton = false;
     return LOUVAIN_OK;
 }
