@@ -1225,9 +1225,14 @@ louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, 
     in.col = g->col0;
     in.w = g->w0;
     in.wk = g->w0 ? lv::W_I32 : lv::W_UNIT;
+    static const char *why[] = {"", "offsets not monotone or not spanning [0, nnz]", "column out of range",
+                                "columns not strictly ascending within a row", "weight below 1",
+                                "graph not symmetric (missing mirror entry or different weight)"};
+    const bool full = (flags & LOUVAIN_VALIDATE) != 0;
     {
-        // offsets and column range are always checked (kernels index with them);
-        // order, weights and symmetry only with LOUVAIN_VALIDATE
+        // offsets always, then with LOUVAIN_VALIDATE order, weights and
+        // symmetry; without it the column range is checked by the degree pass
+        // (which indexes nothing with a column), before any kernel that does
         int32_t code = 0;
         lv::validate_csr(in, g->vflag, g->st);
         if (hipMemcpyAsync(&code, g->vflag, sizeof(code), hipMemcpyDeviceToHost, g->st) != hipSuccess ||
@@ -1235,28 +1240,31 @@ louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, 
             g->err = "validation failed to run";
             return bail(LOUVAIN_E_HIP);
         }
-        if (code == 0) {
-            lv::validate_entries(in, (flags & LOUVAIN_VALIDATE) != 0, g->vflag, g->st);
+        if (code == 0 && full) {
+            lv::validate_entries(in, true, g->vflag, g->st);
             if (hipMemcpyAsync(&code, g->vflag, sizeof(code), hipMemcpyDeviceToHost, g->st) != hipSuccess ||
                 hipStreamSynchronize(g->st) != hipSuccess) {
                 g->err = "validation failed to run";
                 return bail(LOUVAIN_E_HIP);
             }
         }
-        static const char *why[] = {"", "offsets not monotone or not spanning [0, nnz]", "column out of range",
-                                    "columns not strictly ascending within a row", "weight below 1",
-                                    "graph not symmetric (missing mirror entry or different weight)"};
         if (code != 0) {
             g->err = std::string("invalid CSR: ") + why[code > 0 && code < 6 ? code : 0];
             return bail(LOUVAIN_E_BAD_CSR);
         }
     }
-    lv::degrees(in, g->k0, g->dscal, g->scratch, g->st);
+    lv::degrees(in, g->k0, g->dscal, g->scratch, g->st, full ? nullptr : g->vflag);
     int64_t h[3];
+    int32_t range_code = 0;
     if (hipMemcpyAsync(h, g->dscal, sizeof(h), hipMemcpyDeviceToHost, g->st) != hipSuccess ||
+        hipMemcpyAsync(&range_code, g->vflag, sizeof(range_code), hipMemcpyDeviceToHost, g->st) != hipSuccess ||
         hipStreamSynchronize(g->st) != hipSuccess) {
         g->err = "degree computation failed";
         return bail(LOUVAIN_E_HIP);
+    }
+    if (range_code != 0) {
+        g->err = std::string("invalid CSR: ") + why[range_code > 0 && range_code < 6 ? range_code : 0];
+        return bail(LOUVAIN_E_BAD_CSR);
     }
     g->two_m = h[0];
     g->kmax0 = h[1];

@@ -93,7 +93,7 @@ void validate_entries(const Csr &g, bool full, int32_t *flag, hipStream_t st)
 // combined in LDS when the tile's rows are cached (one global atomic per row
 // and block), else added to k directly.
 template <int WK>
-__global__ __launch_bounds__(BLOCK) void k_degrees(Csr g, int64_t *k, int64_t *rep)
+__global__ __launch_bounds__(BLOCK) void k_degrees(Csr g, int64_t *k, int64_t *rep, int32_t *range_flag)
 {
     __shared__ int64_t s_off[ROWCAP + 1];
     __shared__ int64_t s_meta[2];
@@ -128,9 +128,11 @@ __global__ __launch_bounds__(BLOCK) void k_degrees(Csr g, int64_t *k, int64_t *r
                 }
             }
             const int64_t w = WLoad<WK>::at(g.w, e);
+            const int32_t c = g.col[e];
             acc += w;
             tot += w;
-            if (g.col[e] == row) self += w;
+            if (c == row) self += w;
+            if (range_flag && (c < 0 || c >= g.n)) atomicCAS(range_flag, 0, 2); // the column check, same pass
         }
         if (acc) {
             if (t.cached) atomicAdd(&s_acc[row - t.rlo], (unsigned long long)acc);
@@ -194,7 +196,7 @@ void rep_fold(const int64_t *rep, int count, int64_t *out, hipStream_t st)
     k_rep_fold<<<1, REP_FOLD_THREADS, 0, st>>>(rep, count, out);
 }
 
-void degrees(const Csr &g, int64_t *k, int64_t *stats, Scratch &s, hipStream_t st)
+void degrees(const Csr &g, int64_t *k, int64_t *stats, Scratch &s, hipStream_t st, int32_t *range_flag)
 {
     fill<int64_t>(k, 0, g.n, st);
     fill<int64_t>(stats, 0, 3, st);
@@ -202,9 +204,9 @@ void degrees(const Csr &g, int64_t *k, int64_t *stats, Scratch &s, hipStream_t s
     if (g.nnz > 0) {
         unsigned ge = grid_for(g.nnz, ETILE);
         switch (g.wk) {
-        case W_UNIT: k_degrees<W_UNIT><<<ge, BLOCK, 0, st>>>(g, k, s.rep); break;
-        case W_I32: k_degrees<W_I32><<<ge, BLOCK, 0, st>>>(g, k, s.rep); break;
-        default: k_degrees<W_I64><<<ge, BLOCK, 0, st>>>(g, k, s.rep); break;
+        case W_UNIT: k_degrees<W_UNIT><<<ge, BLOCK, 0, st>>>(g, k, s.rep, range_flag); break;
+        case W_I32: k_degrees<W_I32><<<ge, BLOCK, 0, st>>>(g, k, s.rep, range_flag); break;
+        default: k_degrees<W_I64><<<ge, BLOCK, 0, st>>>(g, k, s.rep, range_flag); break;
         }
     }
     rep_fold(s.rep, 3, stats, st); // 2m, 0 (the maximum comes next), self-loops

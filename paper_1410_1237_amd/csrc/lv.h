@@ -163,7 +163,8 @@ void iota_i32(int32_t *p, int64_t n, hipStream_t st);
 void validate_csr(const Csr &g, int32_t *flag, hipStream_t st);
 void validate_entries(const Csr &g, bool full, int32_t *flag, hipStream_t st);
 // k_i = row sums; stats[0] += sum k, stats[1] = max k (atomic), stats[2] += self-loop weights
-void degrees(const Csr &g, int64_t *k, int64_t *stats, Scratch &s, hipStream_t st);
+// range_flag (may be NULL): set to 2 if a column lies outside [0, n)
+void degrees(const Csr &g, int64_t *k, int64_t *stats, Scratch &s, hipStream_t st, int32_t *range_flag = nullptr);
 // sum of a_c^2 over c in [0, n) into a 128-bit accumulator (out[0] = lo, out[1] = hi)
 void sum_squares(const int64_t *a, int64_t n, int64_t *out, Scratch &s, hipStream_t st);
 // internal weight of a partition: sum over entries with comm[u] == comm[v]

@@ -244,12 +244,14 @@ def test_bad_csr_rejected(L):
         with pytest.raises(L.LouvainError) as e:
             L.Graph.from_csr(c)
         assert e.value.status == L.E_BAD_CSR, name
-    # without full validation the column range is still checked
-    c = SG.from_edges(4, [(0, 1), (1, 2), (2, 3)])
-    c.cols = c.cols.copy()
-    c.cols[0] = 7
-    with pytest.raises(L.LouvainError):
-        L.Graph.from_csr(c, validate=False)
+    # without full validation the column range is still checked (by the degree pass)
+    for bad_col, at in ((7, 0), (-1, 0), (4, 5)):
+        c = SG.from_edges(4, [(0, 1), (1, 2), (2, 3)])
+        c.cols = c.cols.copy()
+        c.cols[at] = bad_col
+        with pytest.raises(L.LouvainError) as e:
+            L.Graph.from_csr(c, validate=False)
+        assert e.value.status == L.E_BAD_CSR, (bad_col, at)
     L.Graph.from_csr(g).close()
 
 
