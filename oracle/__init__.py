@@ -71,6 +71,7 @@ class Phase:
     moves: List[int]
     N_iter: List[int]
     N_end: int
+    undone: bool = False
 
 
 @dataclass
@@ -203,14 +204,14 @@ class Oracle:
                 iters.append((int(it[0]), _i128(it[1], it[2])))
             phases, plabels = [], []
             for p in range(int(sc[3])):
-                ph = np.zeros(9, dtype=np.int64)
+                ph = np.zeros(10, dtype=np.int64)
                 self.L.oracle_result_phase(h, p, _ptr(ph))
                 f, nit = int(ph[6]), int(ph[4])
                 phases.append(Phase(n=int(ph[0]), nnz=int(ph[1]), colored=bool(ph[2]),
                                     ncolors=int(ph[3]), iterations=nit, hit_max_iter=bool(ph[5]),
                                     moves=[m for m, _ in iters[f:f + nit]],
                                     N_iter=[N for _, N in iters[f:f + nit]],
-                                    N_end=_i128(ph[7], ph[8])))
+                                    N_end=_i128(ph[7], ph[8]), undone=bool(ph[9])))
                 if phase_labels:
                     pl = np.zeros(max(g.n, 1), dtype=np.int32)
                     self.L.oracle_result_phase_labels(h, p, _ptr(pl))

@@ -32,11 +32,16 @@
  *    processed in ascending color and each class reads the state left by the
  *    classes before it.
  *  - iteration stop (Alg. 1 threshold test, read with Sec. 5.1's remark that a
- *    minimum net gain is required to continue a phase): from the second
- *    iteration on, stop when Q_t - Q_{t-1} < theta * |Q_{t-1}| (a loss or a
- *    small gain; the absolute value of Alg. 1 would never stop a two-state
- *    swap oscillation); also when an iteration moves nothing or the
- *    iteration cap is hit.  The stopping iteration's moves are kept.
+ *    minimum net gain is required to continue a phase): an iteration that
+ *    loses modularity (Q_t < Q_{t-1}, where Q_0 is the phase's starting
+ *    partition) is not a net gain: it is undone and ends the phase (Lemma 1
+ *    of Sec. 4.1: simultaneous moves can lose).  Otherwise, from the second
+ *    iteration on, stop when Q_t - Q_{t-1} < theta * |Q_{t-1}| (Alg. 1
+ *    starts from Q_P = -infinity, so the first iteration never meets the
+ *    test; the absolute value of Alg. 1 would never stop a two-state swap
+ *    oscillation); also when an iteration moves nothing or the iteration
+ *    cap is hit.  The moves of an iteration that gains are kept.  So no
+ *    phase ends below the modularity it started from.
  *  - coarsening (Sec. 3, Sec. 5.5): non-empty communities renumbered in
  *    ascending id; coarse weight W'(C,D) = sum of all CSR entries from C to D,
  *    so an internal undirected edge contributes twice to the coarse self-loop.
@@ -425,6 +430,7 @@ struct State {
 struct PhaseRec {
     int64_t n, nnz, colored, ncolors, iterations, hit_max_iter, first_iter;
     i128 N_end;
+    int64_t undone;   /* the last iteration lost modularity and was undone */
 };
 struct IterRec { int64_t moves; i128 N; };
 
@@ -473,14 +479,24 @@ void run(const Graph &input, const Params &P, Result &R)
         ph.colored = colored;
         ph.ncolors = colored ? st.ncolors : 0;
         ph.first_iter = (int64_t)R.iters.size();
-        i128 N_prev = 0, N_t = Q_prev;
+        i128 N_prev = Q_prev, N_t = Q_prev;   /* the phase starts from singletons of G_p */
         int64_t t = 0;
         for (;;) {
             ++t;
+            const std::vector<int32_t> C_before = st.C;
             int64_t moves = st.iterate(P.singlet_rule);
             modularity(st.g, st.C, N_t, Dd);
             R.iters.push_back({moves, N_t});
             if (moves == 0) break;
+            if (N_t < N_prev) {                     /* a loss: back to the partition before it */
+                st.C = C_before;
+                std::fill(st.a.begin(), st.a.end(), 0);
+                std::fill(st.size.begin(), st.size.end(), 0);
+                for (int64_t i = 0; i < st.g.n; ++i) { st.a[st.C[i]] += st.k[i]; st.size[st.C[i]] += 1; }
+                N_t = N_prev;
+                ph.undone = 1;
+                break;
+            }
             if (t >= 2 && gain_below(N_t, N_prev, D, tnum, tden, P.threshold_mode)) break;
             if (t >= P.max_iter) { ph.hit_max_iter = 1; break; }
             N_prev = N_t;
@@ -721,13 +737,14 @@ void oracle_result_phase_labels(void *h, int64_t p, int32_t *out)
     std::copy(R->phase_labels[p].begin(), R->phase_labels[p].end(), out);
 }
 
-/* out: n, nnz, colored, ncolors, iterations, hit_max_iter, first_iter, N_end(lo,hi) */
+/* out: n, nnz, colored, ncolors, iterations, hit_max_iter, first_iter, N_end(lo,hi), undone */
 void oracle_result_phase(void *h, int64_t p, int64_t *out)
 {
     const PhaseRec &ph = ((Result *)h)->phases[p];
     out[0] = ph.n; out[1] = ph.nnz; out[2] = ph.colored; out[3] = ph.ncolors;
     out[4] = ph.iterations; out[5] = ph.hit_max_iter; out[6] = ph.first_iter;
     put128(ph.N_end, out + 7);
+    out[9] = ph.undone;
 }
 
 /* out: moves, N(lo,hi) */

@@ -50,7 +50,7 @@ def golden(workload: str, heur: str) -> dict:
         "labels_sha256": labels_sha(r.labels),
         "phases": [{"n": p.n, "nnz": p.nnz, "colored": p.colored, "ncolors": p.ncolors,
                     "iterations": p.iterations, "moves": p.moves, "N_iter": [str(x) for x in p.N_iter],
-                    "N_end": str(p.N_end)} for p in r.phases],
+                    "N_end": str(p.N_end), "undone": p.undone} for p in r.phases],
         "oracle_seconds": round(secs, 1),
     }
 

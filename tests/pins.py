@@ -432,7 +432,176 @@ def validation_codes(O):
     assert O.validate(bad2) == 4
 
 
+def _trajectory(O, g, iters, singlet=1, color_seed=None):
+    """N after each of `iters` iterations from the step calls, each checked
+    against the modularity-matrix form of the partition it leaves."""
+    st = O.state(g)
+    if color_seed is not None:
+        st.color(color_seed)
+    out = []
+    for _ in range(iters):
+        _, N = st.iterate(singlet)
+        assert N == n_modmatrix(g, st.get("comm"))[0]
+        out.append(N)
+    return out
+
+
+def p15_loss_is_undone(O):
+    """Sec. 5.1 (a phase continues only on a net gain) with Lemma 1 of
+    Sec. 4.1 (simultaneous moves can lose): an iteration that lowers Q is not
+    kept and ends the phase, also the first one of a phase.
+
+    Case 1, a 4-cycle 0-1-2-3 with the chord 0-2 (k = 3,2,3,2; 2m = 10):
+    singletons N0 = -(9+4+9+4) = -26.  Iteration 1 (by hand from Eq. 4 and
+    the minimum-label rules): 0 prefers community 1 but the singlet rule
+    keeps it, 1 and 3 join 0, 2 joins 1 -> {0,1,3},{2}: N = 10*4 - (49+9)
+    = -18.  Iteration 2: 1 and 3 move to C(2), 2 moves to C(0) -> {0,2},{1,3}:
+    N = 10*2 - (36+16) = -32, a loss.  So phase 1 ends at {0,1,3},{2} with
+    N = -18 after 2 iterations; phase 2 merges the two (N = 0).
+
+    Case 2, the 5-vertex graph 0-1, 0-4, 1-2, 1-3, 2-4, 3-4 (k = 2,3,2,2,3;
+    2m = 12): N0 = -30.  Iteration 1 moves 1 and 4 to C(0), 2 and 3 to C(1)
+    (0 is kept by the singlet rule) -> {0,1,4},{2,3}: N = 12*4 - (64+16) =
+    -32 < -30.  The first iteration itself loses, so it is undone, the phase
+    leaves every vertex alone, the graph does not shrink and the run stops at
+    the singletons: K = 5, N = -30."""
+    import oracle as OR
+    g = SG.from_edges(4, [(0, 1), (0, 2), (0, 3), (1, 2), (2, 3)])
+    assert _trajectory(O, g, 2) == [-18, -32]
+    res = O.run(g, OR.Params(), phase_labels=True)
+    p = res.phases[0]
+    assert (p.iterations, p.moves, p.N_iter, p.N_end, p.undone) == (2, [3, 3], [-18, -32], -18, True)
+    assert res.phase_labels[0].tolist() == [0, 0, 1, 0]
+    assert res.phases[1].n == 2 and res.phases[1].N_end == 0
+    assert (res.N, res.D, res.K) == (0, 100, 1)
+
+    g = SG.from_edges(5, [(0, 1), (0, 4), (1, 2), (1, 3), (2, 4), (3, 4)])
+    assert _trajectory(O, g, 1) == [-32]
+    res = O.run(g)
+    assert len(res.phases) == 1
+    p = res.phases[0]
+    assert (p.iterations, p.moves, p.N_end, p.undone) == (1, [4], -30, True)
+    assert (res.N, res.K, res.N0) == (-30, 5, -30)
+    assert res.labels.tolist() == [0, 1, 2, 3, 4]
+
+
+def p16_phases_never_lose(O):
+    """Consequence of the rule above: within a phase every kept iteration is
+    at least the one before it, every phase ends at or above the N it started
+    from (the previous phase's end, or the singletons' N0), and the run
+    reports the last phase's N, checked on the modularity-matrix form."""
+    import oracle as OR
+    graphs = rand_graphs(71, 16) + [SG.ring_of_cliques(5, 4), SG.star(7)]
+    for idx, g in enumerate(graphs):
+        for params in [OR.Params(), OR.Params(singlet_rule=0),
+                       OR.Params(vf=1, color=1, color_cutoff=1, theta_color=(1, 4))]:
+            res = O.run(g, params, phase_labels=True)
+            prev = res.N0
+            for ph, lab in zip(res.phases, res.phase_labels):
+                kept = ph.N_iter[:-1] if ph.undone else ph.N_iter
+                seq = [prev] + kept
+                assert all(b >= a for a, b in zip(seq, seq[1:]))
+                if ph.undone:
+                    assert ph.N_iter[-1] < seq[-1]
+                assert ph.N_end == seq[-1] >= prev
+                assert n_modmatrix(g, lab)[0] == ph.N_end
+                prev = ph.N_end
+            assert res.N == prev
+
+
+def p17_iteration_threshold(O):
+    """Alg. 1's threshold test, in exact rationals.  On the 5-vertex graph
+    0-1, 0-4, 1-2, 1-3, 2-3, 2-4 (2m = 12, D = 144) the iterations give
+    N = -14, 0, 16, 16 (moves 3, 3, 1, 0).
+      * relative test (gain against theta * |N_{t-1}|), theta = 1/2:
+        t = 2 gains 14 >= 7, t = 3 gains 16 >= 0, t = 4 moves nothing ->
+        4 iterations;
+      * absolute test (gain against theta * D), theta = 1/2: t = 2 gains
+        14 < 72 -> stops after 2 iterations;
+      * the test is strict: theta = 14/14 puts t = 2 exactly on the
+        threshold and the phase goes on (4 iterations); theta = 15/14 stops
+        it at t = 2;
+      * t = 1 is never tested (Alg. 1 starts from Q_P = -infinity): even
+        theta = 10^6 keeps iteration 1 and stops at t = 2."""
+    import oracle as OR
+    g = SG.from_edges(5, [(0, 1), (0, 4), (1, 2), (1, 3), (2, 3), (2, 4)])
+    assert _trajectory(O, g, 4) == [-14, 0, 16, 16]
+    runs = {"rel": OR.Params(theta_final=(1, 2)),
+            "abs": OR.Params(theta_final=(1, 2), threshold_mode=1),
+            "at": OR.Params(theta_final=(14, 14)),
+            "above": OR.Params(theta_final=(15, 14)),
+            "huge": OR.Params(theta_final=(10 ** 6, 1))}
+    first = {k: O.run(g, P).phases[0] for k, P in runs.items()}
+    assert (first["rel"].iterations, first["rel"].N_end) == (4, 16)
+    assert (first["abs"].iterations, first["abs"].N_end) == (2, 0)
+    assert (first["at"].iterations, first["at"].N_end) == (4, 16)
+    assert (first["above"].iterations, first["above"].N_end) == (2, 0)
+    assert (first["huge"].iterations, first["huge"].moves) == (2, [3, 3])
+
+
+def p18_coloring_schedule(O):
+    """Sec. 6.1's schedule.  The 5-vertex graph 0-2, 0-3, 1-2, 1-3, 2-3,
+    2-4, 3-4 (k = 2,2,4,4,2; 2m = 14; N0 = -44) colored with the default
+    seed gives N = -20, -8, 0, 0 per iteration (gains 24, 12, 8, 0).
+      * theta_color = 9/10 governs a colored phase: t = 2 gains 12 < 18
+        and stops it (theta_final = 1e-6 would run to t = 4);
+      * the phase gain is then -8 - (-44) = 36 < 0.9 * 44, so coloring
+        stops: phase 2 runs uncolored although its graph (2 vertices) is
+        above the cutoff of 1;
+      * a phase is colored when its graph has at least `color_cutoff`
+        vertices: cutoff 5 colors the 5-vertex phase, cutoff 6 does not;
+      * with color_first_phase_only (Table 4's variant) phase 2 is
+        uncolored even though phase 1 gained 44 >= 0.01 * 44."""
+    import oracle as OR
+    g = SG.from_edges(5, [(0, 2), (0, 3), (1, 2), (1, 3), (2, 3), (2, 4), (3, 4)])
+    assert _trajectory(O, g, 4, color_seed=OR.DEFAULT_SEED) == [-20, -8, 0, 0]
+    res = O.run(g, OR.Params(color=1, color_cutoff=1, theta_color=(9, 10)))
+    assert [(p.colored, p.iterations, p.N_end) for p in res.phases[:2]] == [(True, 2, -8), (False, 2, 0)]
+    res = O.run(g, OR.Params(color=1, color_cutoff=5, theta_color=(9, 10)))
+    assert res.phases[0].colored and res.phases[0].iterations == 2
+    res = O.run(g, OR.Params(color=1, color_cutoff=6, theta_color=(9, 10)))
+    assert not res.phases[0].colored
+    res = O.run(g, OR.Params(color=1, color_cutoff=1))
+    assert [p.colored for p in res.phases[:2]] == [True, True] and res.phases[0].iterations == 4
+    res = O.run(g, OR.Params(color=1, color_cutoff=1, color_first_phase_only=1))
+    assert [p.colored for p in res.phases] == [True, False]
+
+
+def p19_no_shrink_stops(O):
+    """A phase that leaves every community a single vertex cannot shrink the
+    graph, and gains nothing (its partition is the singletons again).  With
+    the thresholds at 0 only that rule ends the run:
+      * uncolored: the 5-vertex graph 0-1, 0-4, 1-2, 1-3, 2-4, 3-4 has its
+        first iteration undone (p15), so phase 1 does not shrink: 1 phase;
+      * colored (cutoff 1, theta_color = 0): the phases shrink 5 -> 2 -> 1;
+        the 1-vertex phase does not shrink, which ends coloring, and the
+        uncolored phase after it does not shrink either: 4 phases, the last
+        uncolored."""
+    import oracle as OR
+    g = SG.from_edges(5, [(0, 1), (0, 4), (1, 2), (1, 3), (2, 4), (3, 4)])
+    res = O.run(g, OR.Params(theta_final=(0, 1)))
+    assert len(res.phases) == 1 and res.K == 5
+    res = O.run(g, OR.Params(color=1, color_cutoff=1, theta_color=(0, 1), theta_final=(0, 1)))
+    assert [(p.n, p.colored) for p in res.phases] == [(5, True), (2, True), (1, True), (1, False)]
+
+
+def p20_vf_isolated_pair(O):
+    """Sec. 5.3 with the isolated-pair reading: both ends of an isolated edge
+    (2, 7) follow the smaller id, so the rebuilt graph keeps vertex 2's rank:
+    representatives 0,1,2,3,4,5,6,8,9 are renumbered 0..8, hence 2 and 7 map
+    to 2 and 8 -> 7, 9 -> 8.  Triangles 0-1-3, 4-5-6, 0-8-9 keep every other
+    vertex."""
+    g = SG.from_edges(10, [(0, 1), (0, 3), (1, 3), (4, 5), (4, 6), (5, 6), (0, 8), (0, 9), (8, 9), (2, 7)])
+    st = O.state(g)
+    st.vf()
+    assert st.get("orig_map").tolist() == [0, 1, 2, 3, 4, 5, 6, 2, 7, 8]
+    off, cols, w = st.get("offsets"), st.get("cols"), st.get("weights")
+    row2 = (cols[off[2]:off[3]].tolist(), w[off[2]:off[3]].tolist())
+    assert row2 == ([2], [2])   # the pair's edge, both entries, as a self-loop
+
+
 ALL = [p1_singleton_closed_form, p2_totals_invariant, p3_single_move_is_eq4, p4_eq6_two_moves,
        p5_lemma3, p6_coarsen_invariance, p7_phase_q_from_scratch, p8_disjoint_cliques,
        p9_ring_of_cliques, p10_bruteforce_upper_bound, p11_coloring, p12_hand_cases,
-       p13_rounding, p14_sbm_sanity, validation_codes]
+       p13_rounding, p14_sbm_sanity, validation_codes, p15_loss_is_undone, p16_phases_never_lose,
+       p17_iteration_threshold, p18_coloring_schedule, p19_no_shrink_stops, p20_vf_isolated_pair]

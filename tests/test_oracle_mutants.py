@@ -48,6 +48,37 @@ MUTANTS = {
     "vf_leaf_does_not_follow":
         ("map[i] = single[j] ? std::min<int32_t>((int32_t)i, j) : j;",
          "map[i] = single[j] ? std::min<int32_t>((int32_t)i, j) : (int32_t)i;"),
+    "loss_kept":
+        ("if (N_t < N_prev) {", "if (false && N_t < N_prev) {"),
+    "loss_checked_from_second_iteration":
+        ("if (N_t < N_prev) {", "if (t >= 2 && N_t < N_prev) {"),
+    "threshold_tested_from_first_iteration":
+        ("if (t >= 2 && gain_below(N_t, N_prev", "if (t >= 1 && gain_below(N_t, N_prev"),
+    "relative_threshold_taken_as_absolute":
+        ("u128 ref = mode == 0 ? uabs(before) : (u128)D;", "u128 ref = (u128)D;"),
+    "threshold_not_strict":
+        ("return h1 < h2 || (h1 == h2 && l1 < l2);", "return h1 < h2 || (h1 == h2 && l1 <= l2);"),
+    "colored_phase_uses_theta_final":
+        ("int64_t tnum = colored ? P.theta_color_num : P.theta_final_num;\n"
+         "        int64_t tden = colored ? P.theta_color_den : P.theta_final_den;",
+         "int64_t tnum = P.theta_final_num;\n"
+         "        int64_t tden = P.theta_final_den;"),
+    "coloring_kept_on_small_phase_gain":
+        ("P.color_first_phase_only ||\n"
+         "                gain_below(N_t, Q_prev, D, P.theta_color_num, P.theta_color_den, 0))",
+         "P.color_first_phase_only)"),
+    "first_phase_only_ignored":
+        ("n_after == n_before || P.color_first_phase_only ||", "n_after == n_before ||"),
+    "colored_no_shrink_ignored":
+        ("if (n_after < P.color_cutoff || n_after == n_before ||", "if (n_after < P.color_cutoff ||"),
+    "final_no_shrink_ignored":
+        ("stop = (n_after == n_before) || (p >= P.max_phases) ||", "stop = (p >= P.max_phases) ||"),
+    "color_cutoff_strict":
+        ("bool colored = still_coloring && st.g.n >= P.color_cutoff;",
+         "bool colored = still_coloring && st.g.n > P.color_cutoff;"),
+    "vf_pair_to_larger_id":
+        ("map[i] = single[j] ? std::min<int32_t>((int32_t)i, j) : j;",
+         "map[i] = single[j] ? std::max<int32_t>((int32_t)i, j) : j;"),
     "rounding_truncates":
         ("if (round_bit && (sticky || (mant & 1))) {",
          "if (false && round_bit && (sticky || (mant & 1))) {"),
