@@ -40,7 +40,8 @@ def _i128(lo: int, hi: int) -> int:
 @dataclass
 class Params:
     """Run parameters (defaults: the paper's baseline = minimum-label sweep,
-    singlet rule on, relative threshold 1e-6, no VF, no coloring)."""
+    singlet rule on, relative threshold 1e-6, no VF, no coloring).  vf: 0
+    none, 1 single-degree vertex following, 2 chain-compressing."""
     vf: int = 0
     color: int = 0
     singlet_rule: int = 1
@@ -52,12 +53,14 @@ class Params:
     max_iter: int = 1000
     max_phases: int = 100
     color_seed: int = DEFAULT_SEED
+    color_balance: int = 0
 
     def flat(self) -> np.ndarray:
         return np.array([self.vf, self.color, self.singlet_rule, self.threshold_mode,
                          self.color_first_phase_only, self.theta_color[0], self.theta_color[1],
                          self.theta_final[0], self.theta_final[1], self.color_cutoff,
-                         self.max_iter, self.max_phases, self.color_seed], dtype=np.int64)
+                         self.max_iter, self.max_phases, self.color_seed, self.color_balance],
+                        dtype=np.int64)
 
 
 @dataclass
@@ -85,6 +88,7 @@ class Result:
     N0: int
     phases: List[Phase] = field(default_factory=list)
     phase_labels: List[np.ndarray] = field(default_factory=list)
+    vf_rounds: int = 0
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -110,9 +114,13 @@ class Oracle:
         L.oracle_state_free.argtypes = [vp]
         L.oracle_state_info.argtypes = [vp, vp]
         L.oracle_state_vf.argtypes = [vp]
+        L.oracle_state_vf_chain.argtypes = [vp]
+        L.oracle_state_vf_chain.restype = i64
         L.oracle_state_color.argtypes = [vp, u64]
         L.oracle_state_color.restype = i32
         L.oracle_state_uncolor.argtypes = [vp]
+        L.oracle_state_balance.argtypes = [vp, u64]
+        L.oracle_state_balance.restype = i64
         L.oracle_state_iterate.argtypes = [vp, i32, vp]
         L.oracle_state_iterate.restype = i64
         L.oracle_state_coarsen.argtypes = [vp]
@@ -192,7 +200,7 @@ class Oracle:
         pf = params.flat()
         h = self.L.oracle_run(g.n, _ptr(off), _ptr(col), _ptr(w), _ptr(pf))
         try:
-            sc = np.zeros(11, dtype=np.int64)
+            sc = np.zeros(12, dtype=np.int64)
             q = ctypes.c_double()
             self.L.oracle_result_scalars(h, _ptr(sc), ctypes.byref(q))
             labels = np.zeros(max(g.n, 1), dtype=np.int32)
@@ -218,7 +226,7 @@ class Oracle:
                     plabels.append(pl[:g.n])
             return Result(labels=labels[:g.n], K=int(sc[1]), N=_i128(sc[5], sc[6]),
                           D=_i128(sc[7], sc[8]), q=q.value, n_vf=int(sc[2]), N0=_i128(sc[9], sc[10]),
-                          phases=phases, phase_labels=plabels)
+                          phases=phases, phase_labels=plabels, vf_rounds=int(sc[11]))
         finally:
             self.L.oracle_result_free(h)
 
@@ -247,8 +255,16 @@ class State:
     def vf(self):
         self.O.L.oracle_state_vf(self.h)
 
+    def vf_chain(self) -> int:
+        """Chain-compressing vertex following; returns the rounds that merged."""
+        return int(self.O.L.oracle_state_vf_chain(self.h))
+
     def color(self, seed: int = DEFAULT_SEED) -> int:
         return int(self.O.L.oracle_state_color(self.h, seed))
+
+    def balance(self, seed: int = DEFAULT_SEED) -> int:
+        """Balanced colouring of the current colouring; returns the vertices moved."""
+        return int(self.O.L.oracle_state_balance(self.h, seed))
 
     def uncolor(self):
         self.O.L.oracle_state_uncolor(self.h)

@@ -48,8 +48,17 @@
  *  - vertex following (Sec. 5.3): a vertex whose row is exactly one entry
  *    (i,j), j != i, merges into j; an isolated pair merges into the smaller
  *    id; applied once, before the first phase.
+ *  - chain-compressing vertex following (the extension closing Sec. 5.3):
+ *    rounds of the same merge for single-neighbour vertices (one neighbour
+ *    j != i, a self-loop allowed), each taken only while the bound in the
+ *    proof of Lemma 3 stays positive, 2m * w_ij > k_i * k_j (the exact gain
+ *    of moving i into j's one-vertex community, Eq. 4); every round rebuilds
+ *    the graph, and the rounds repeat until no vertex qualifies.
  *  - coloring (Sec. 5.2): distance-1, greedy in descending priority
  *    pi(v) = splitmix64_finalizer((seed << 32) ^ v); self-loops ignored.
+ *  - balanced coloring (optional; Sec. 6.2 leaves class-size balance to
+ *    future work): the greedy colouring's over-full classes hand vertices to
+ *    under-full ones, as defined at balance_colors below.
  *  - schedule (Sec. 6.1): colored phases while the phase graph has at least
  *    `color_cutoff` vertices and the phase-to-phase net gain stays at or
  *    above theta_color * |Q_prev|; then uncolored phases with theta_final until
@@ -192,6 +201,30 @@ std::vector<int32_t> vf_map(const Graph &g)
     return map;
 }
 
+/* one round of chain-compressing vertex following: i qualifies when its row
+ * holds exactly one neighbour j != i (besides an optional self-loop) and
+ * 2m * w_ij > k_i * k_j; it then merges into j, or, when j qualifies too
+ * (the two only see each other), both go to the smaller id */
+std::vector<int32_t> vf_chain_map(const Graph &g, const std::vector<int64_t> &k, int64_t two_m)
+{
+    std::vector<char> single(g.n, 0);
+    std::vector<int32_t> nbr(g.n, -1);
+    for (int64_t i = 0; i < g.n; ++i) {
+        int64_t others = 0, w = 0;
+        for (int64_t e = g.off[i]; e < g.off[i + 1]; ++e)
+            if (g.col[e] != i) { ++others; nbr[i] = g.col[e]; w = g.w[e]; }
+        single[i] = others == 1 && (i128)two_m * w > (i128)k[i] * k[nbr[i]];
+    }
+    std::vector<int32_t> map(g.n);
+    for (int64_t i = 0; i < g.n; ++i) {
+        map[i] = (int32_t)i;
+        if (!single[i]) continue;
+        const int32_t to = nbr[i];
+        map[i] = single[to] ? std::min<int32_t>((int32_t)i, to) : to;
+    }
+    return map;
+}
+
 /* SplitMix64 output finalizer (Steele, Lea, Flood, OOPSLA 2014) */
 uint64_t splitmix64_finalizer(uint64_t z)
 {
@@ -221,6 +254,73 @@ int32_t color_greedy(const Graph &g, uint64_t seed, std::vector<int32_t> &color)
         ncolors = std::max(ncolors, c + 1);
     }
     return ncolors;
+}
+
+/* Balanced colouring: equalises the class sizes of a proper colouring with
+ * chi colours on n vertices towards gamma = ceil(n / chi), keeping it proper
+ * and using no new colour.  The over-full classes (more than gamma vertices)
+ * are taken one after another in ascending colour c.  A vertex v of K_c may
+ * go to any colour c' != c that none of its neighbours has (self-loops
+ * ignored) and whose class holds fewer than gamma vertices.  K_c is an
+ * independent set, so these permissions do not change while K_c is handled.
+ * Moves happen in rounds: every vertex of K_c still waiting proposes its
+ * smallest admissible colour (a vertex with none stops waiting); the
+ * proposers of each c' are taken in descending priority, at most
+ * gamma - |K_c'| of them; of all the vertices taken, the first |K_c| - gamma
+ * in descending priority move.  K_c is done when it is down to gamma or a
+ * round moves nobody.  Returns the number of vertices moved. */
+int64_t balance_colors(const Graph &g, uint64_t seed, std::vector<int32_t> &color, int32_t ncolors)
+{
+    if (g.n == 0 || ncolors == 0) return 0;
+    const int64_t gamma = (g.n + ncolors - 1) / ncolors;
+    std::vector<int64_t> size(ncolors, 0);
+    for (int64_t v = 0; v < g.n; ++v) size[color[v]]++;
+    std::vector<int32_t> order(g.n);
+    for (int64_t v = 0; v < g.n; ++v) order[v] = (int32_t)v;
+    std::sort(order.begin(), order.end(),
+              [&](int32_t x, int32_t y) { return priority(seed, x) > priority(seed, y); });
+    int64_t moved_total = 0;
+    for (int32_t c = 0; c < ncolors; ++c) {
+        if (size[c] <= gamma) continue;
+        std::vector<int32_t> waiting;                    /* K_c in descending priority */
+        for (int32_t v : order)
+            if (color[v] == c) waiting.push_back(v);
+        std::map<int32_t, std::set<int32_t>> used;       /* colours of each vertex's neighbours */
+        for (int32_t v : waiting)
+            for (int64_t e = g.off[v]; e < g.off[v + 1]; ++e)
+                if (g.col[e] != v) used[v].insert(color[g.col[e]]);
+        while (size[c] > gamma) {
+            std::vector<int32_t> still, taken;
+            std::map<int32_t, int32_t> proposal;
+            std::map<int32_t, int64_t> count;
+            for (int32_t v : waiting) {
+                int32_t to = -1;
+                for (int32_t d = 0; d < ncolors && to < 0; ++d)
+                    if (d != c && size[d] < gamma && !used[v].count(d)) to = d;
+                if (to < 0) continue;                    /* nothing admissible: stops waiting */
+                still.push_back(v);
+                proposal[v] = to;
+                if (count[to] < gamma - size[to]) { taken.push_back(v); count[to]++; }
+            }
+            const int64_t room = size[c] - gamma;
+            int64_t moved = 0;
+            std::set<int32_t> gone;
+            for (int32_t v : taken) {
+                if (moved == room) break;
+                size[c]--;
+                size[proposal[v]]++;
+                color[v] = proposal[v];
+                gone.insert(v);
+                ++moved;
+            }
+            if (moved == 0) break;
+            moved_total += moved;
+            waiting.clear();
+            for (int32_t v : still)
+                if (!gone.count(v)) waiting.push_back(v);
+        }
+    }
+    return moved_total;
 }
 
 /* |x| for i128 as unsigned */
@@ -287,7 +387,7 @@ double ratio_to_double(i128 N, i128 D)
 }
 
 struct Params {
-    int32_t vf = 0, color = 0, singlet_rule = 1, threshold_mode = 0, color_first_phase_only = 0;
+    int32_t vf = 0, color = 0, singlet_rule = 1, threshold_mode = 0, color_first_phase_only = 0, color_balance = 0;
     int64_t theta_color_num = 1, theta_color_den = 100;
     int64_t theta_final_num = 1, theta_final_den = 1000000;
     int64_t color_cutoff = 100000;
@@ -425,6 +525,21 @@ struct State {
         C = m;
         coarsen_step();
     }
+
+    /* chain compression: rounds until no vertex qualifies; returns the rounds that merged */
+    int64_t vf_chain_step()
+    {
+        int64_t rounds = 0;
+        for (;;) {
+            std::vector<int32_t> m = vf_chain_map(g, k, two_m);
+            bool any = false;
+            for (int64_t i = 0; i < g.n && !any; ++i) any = m[i] != i;
+            if (!any) return rounds;
+            C = m;
+            coarsen_step();
+            ++rounds;
+        }
+    }
 };
 
 struct PhaseRec {
@@ -435,7 +550,7 @@ struct PhaseRec {
 struct IterRec { int64_t moves; i128 N; };
 
 struct Result {
-    int64_t n_orig = 0, K = 0, n_vf = 0;
+    int64_t n_orig = 0, K = 0, n_vf = 0, vf_rounds = 0;
     i128 N = 0, D = 1, N0 = 0;
     double q = 0.0;
     std::vector<int32_t> labels;
@@ -461,7 +576,8 @@ void run(const Graph &input, const Params &P, Result &R)
         return;
     }
     const i128 D = (i128)st.two_m * st.two_m;
-    if (P.vf) st.vf_step();
+    if (P.vf == 1) st.vf_step();
+    if (P.vf == 2) R.vf_rounds = st.vf_chain_step();
     R.n_vf = st.g.n;
     i128 N, Dd;
     modularity(st.g, st.C, N, Dd);
@@ -472,7 +588,10 @@ void run(const Graph &input, const Params &P, Result &R)
         bool colored = still_coloring && st.g.n >= P.color_cutoff;
         int64_t tnum = colored ? P.theta_color_num : P.theta_final_num;
         int64_t tden = colored ? P.theta_color_den : P.theta_final_den;
-        if (colored) st.ncolors = color_greedy(st.g, P.color_seed, st.color);
+        if (colored) {
+            st.ncolors = color_greedy(st.g, P.color_seed, st.color);
+            if (P.color_balance) balance_colors(st.g, P.color_seed, st.color, st.ncolors);
+        }
         PhaseRec ph{};
         ph.n = st.g.n;
         ph.nnz = st.g.nnz();
@@ -534,7 +653,7 @@ Params params_from(const int64_t *p)
 {
     /* flat parameter vector: vf, color, singlet_rule, threshold_mode,
      * color_first_phase_only, tc_num, tc_den, tf_num, tf_den, cutoff,
-     * max_iter, max_phases, seed */
+     * max_iter, max_phases, seed, color_balance */
     Params P;
     P.vf = (int32_t)p[0]; P.color = (int32_t)p[1]; P.singlet_rule = (int32_t)p[2];
     P.threshold_mode = (int32_t)p[3]; P.color_first_phase_only = (int32_t)p[4];
@@ -542,6 +661,7 @@ Params params_from(const int64_t *p)
     P.theta_final_num = p[7]; P.theta_final_den = p[8];
     P.color_cutoff = p[9]; P.max_iter = (int32_t)p[10]; P.max_phases = (int32_t)p[11];
     P.color_seed = (uint64_t)p[12];
+    P.color_balance = (int32_t)p[13];
     return P;
 }
 
@@ -613,11 +733,21 @@ void oracle_state_info(void *h, int64_t *out)
 
 void oracle_state_vf(void *h) { ((State *)h)->vf_step(); }
 
+/* chain-compressing vertex following; returns the rounds that merged */
+int64_t oracle_state_vf_chain(void *h) { return ((State *)h)->vf_chain_step(); }
+
 int32_t oracle_state_color(void *h, uint64_t seed)
 {
     State *st = (State *)h;
     st->ncolors = color_greedy(st->g, seed, st->color);
     return st->ncolors;
+}
+
+/* balanced colouring of the current colouring; returns the vertices moved */
+int64_t oracle_state_balance(void *h, uint64_t seed)
+{
+    State *st = (State *)h;
+    return balance_colors(st->g, seed, st->color, st->ncolors);
 }
 
 void oracle_state_uncolor(void *h)
@@ -713,7 +843,7 @@ void *oracle_run(int64_t n, const int64_t *off, const int32_t *col, const int32_
 
 void oracle_result_free(void *h) { delete (Result *)h; }
 
-/* out: n_orig, K, n_vf, phases, iterations, N(lo,hi), D(lo,hi), N0(lo,hi) */
+/* out: n_orig, K, n_vf, phases, iterations, N(lo,hi), D(lo,hi), N0(lo,hi), vf_rounds */
 void oracle_result_scalars(void *h, int64_t *out, double *q)
 {
     Result *R = (Result *)h;
@@ -722,6 +852,7 @@ void oracle_result_scalars(void *h, int64_t *out, double *q)
     put128(R->N, out + 5);
     put128(R->D, out + 7);
     put128(R->N0, out + 9);
+    out[11] = R->vf_rounds;
     *q = R->q;
 }
 

@@ -600,8 +600,133 @@ def p20_vf_isolated_pair(O):
     assert row2 == ([2], [2])   # the pair's edge, both entries, as a self-loop
 
 
+def _chain_qualifies(n, off, cols, w):
+    """Vertices of a CSR that the chain rule would still merge: one
+    neighbour j != i (a self-loop allowed) and 2m * w_ij > k_i * k_j."""
+    k = np.array([int(w[off[i]:off[i + 1]].sum()) for i in range(n)], dtype=object)
+    two_m = int(sum(k))
+    out = []
+    for i in range(n):
+        nb = [(int(c), int(x)) for c, x in zip(cols[off[i]:off[i + 1]], w[off[i]:off[i + 1]]) if c != i]
+        if len(nb) == 1 and two_m * nb[0][1] > k[i] * k[nb[0][0]]:
+            out.append(i)
+    return out
+
+
+def p21_chain_vertex_following(O):
+    """The chain-compressing extension of Sec. 5.3: single-neighbour vertices
+    merge into their neighbour round after round while the bound of Lemma 3's
+    proof stays positive, 2m * w_ij > k_i * k_j.
+
+      * path 0-1-2-3 ending in the triangle 3-4-5 (unit weights, 2m = 12):
+        round 1 merges the leaf 0 into 1 (12 > 1*2); {0,1} now has a
+        self-loop of 2 and the single neighbour 2, and 12 > 3*2 merges it into
+        2; {0,1,2} (self-loop 4, k = 5) with neighbour 3 (k = 3) gives
+        12 > 15, false: two rounds, map 0,0,0,1,2,3, self-loop 4;
+      * a vertex with a self-loop of 10 and one edge into a triangle
+        (2m = 18): 18 * 1 > 11 * 3 is false, nothing merges; with a self-loop
+        of 2 (2m = 10): 10 > 3 * 3 merges it;
+      * an isolated pair whose ends carry self-loops of 1 (2m = 10 with a
+        triangle beside it): both qualify (10 > 2*2) and go to the smaller
+        id; the merged self-loop is 1 + 1 + 2 * 1 = 4.
+    On random graphs the rounds keep 2m and Q (the partition of the original
+    graph by the composed map has the rebuilt graph's singleton Q), and no
+    vertex of the result qualifies any more."""
+    g = SG.from_edges(6, [(0, 1), (1, 2), (2, 3), (3, 4), (3, 5), (4, 5)])
+    st = O.state(g)
+    assert st.vf_chain() == 2
+    assert st.get("orig_map").tolist() == [0, 0, 0, 1, 2, 3]
+    off, cols, w = st.get("offsets"), st.get("cols"), st.get("weights")
+    assert (cols[off[0]:off[1]].tolist(), w[off[0]:off[1]].tolist()) == ([0, 1], [4, 1])
+    for sw, rounds, om in [(10, 0, [0, 1, 2, 3]), (2, 1, [0, 0, 1, 2])]:
+        g = SG.from_edges(4, [(0, 0), (0, 1), (1, 2), (1, 3), (2, 3)], [sw, 1, 1, 1, 1])
+        st = O.state(g)
+        assert st.vf_chain() == rounds and st.get("orig_map").tolist() == om
+    g = SG.from_edges(5, [(0, 0), (0, 1), (1, 1), (2, 3), (2, 4), (3, 4)])
+    st = O.state(g)
+    assert st.vf_chain() == 1 and st.get("orig_map").tolist() == [0, 0, 1, 2, 3]
+    assert st.get("weights")[0] == 4
+    # the bound is strict: self-loop 6 and an edge of weight 2 into a triangle
+    # give 2m = 16, k_0 = 8, k_1 = 4 and 16 * 2 = 8 * 4: no merge
+    g = SG.from_edges(4, [(0, 0), (0, 1), (1, 2), (1, 3), (2, 3)], [6, 2, 1, 1, 1])
+    st = O.state(g)
+    assert st.vf_chain() == 0 and st.get("orig_map").tolist() == [0, 1, 2, 3]
+    # an isolated pair with non-adjacent ids (2, 7) follows the smaller id here too
+    g = SG.from_edges(10, [(0, 1), (0, 3), (1, 3), (4, 5), (4, 6), (5, 6), (0, 8), (0, 9), (8, 9), (2, 7)])
+    st = O.state(g)
+    assert st.vf_chain() == 1 and st.get("orig_map").tolist() == [0, 1, 2, 3, 4, 5, 6, 2, 7, 8]
+    # single-degree VF on the path case takes the leaf only
+    st = O.state(SG.from_edges(6, [(0, 1), (1, 2), (2, 3), (3, 4), (3, 5), (4, 5)]))
+    st.vf()
+    assert st.get("orig_map").tolist() == [0, 0, 1, 2, 3, 4]
+    rng = np.random.default_rng(43)
+    for t in range(24):
+        n = int(rng.integers(4, 16))
+        g = SG.random_graph(rng, n, p=float(rng.uniform(0.08, 0.3)), self_loops=0.3 if t % 2 else 0.0,
+                            wmax=1 if t % 3 == 0 else 6)
+        if g.nnz == 0:
+            continue
+        st = O.state(g)
+        two_m = st.info()["two_m"]
+        st.vf_chain()
+        info = st.info()
+        off, cols, w = st.get("offsets"), st.get("cols"), st.get("weights")
+        _check_csr(info["n"], off, cols, w)
+        assert info["two_m"] == two_m
+        A2 = dense_w64(info["n"], off, cols, w)
+        assert n_modmatrix(g, st.get("orig_map")) == n_modmatrix_A(A2, np.arange(info["n"]))
+        assert _chain_qualifies(info["n"], off, cols, w) == []
+
+
+def p22_balanced_coloring(O):
+    """Balanced colouring (class-size equalisation of the greedy colouring).
+    A triangle 0-1-2 beside 7 isolated vertices 3..9: the greedy colouring
+    has chi = 3 (the triangle) and puts every isolated vertex in class 0, so
+    |K_0| = 8, |K_1| = |K_2| = 1 and gamma = ceil(10 / 3) = 4.  The triangle's
+    vertex in K_0 sees colours 1 and 2 and cannot move; the isolated ones can
+    go anywhere.  Round 1: all propose colour 1, which takes 3 (4 - 1) in
+    descending priority, within the room of 8 - 4 = 4: they move.  Round 2: the
+    other 4 propose colour 2, which could take 3, but only 1 more may leave
+    K_0: the highest-priority one moves.  Sizes 4, 4, 2.
+    On random graphs: still proper, no new colour, no class pushed past gamma,
+    and a vertex left in a class above gamma has no admissible colour."""
+    g = SG.from_edges(10, [(0, 1), (0, 2), (1, 2)])
+    st = O.state(g)
+    seed = 0x4C4F5556
+    assert st.color(seed) == 3
+    before = st.get("color")
+    assert (before[3:] == 0).all()
+    assert st.balance(seed) == 4
+    after = st.get("color")
+    pri = {v: O.mix64(((seed << 32) ^ v) & ((1 << 64) - 1)) for v in range(3, 10)}
+    iso = sorted(range(3, 10), key=lambda v: -pri[v])
+    assert [int(after[v]) for v in iso] == [1, 1, 1, 2, 0, 0, 0]
+    assert np.array_equal(after[:3], before[:3])
+    assert np.bincount(after, minlength=3).tolist() == [4, 4, 2]
+    rng = np.random.default_rng(53)
+    for t in range(20):
+        n = int(rng.integers(6, 40))
+        g = SG.random_graph(rng, n, p=float(rng.uniform(0.03, 0.4)), self_loops=0.2 if t % 2 else 0.0)
+        st = O.state(g)
+        chi = st.color(seed)
+        size0 = np.bincount(st.get("color"), minlength=chi)
+        st.balance(seed)
+        col = st.get("color")
+        assert col.max() < chi
+        gamma = -(-n // chi)
+        size1 = np.bincount(col, minlength=chi)
+        assert all(size1[c] <= max(gamma, size0[c]) for c in range(chi))
+        for v in range(n):
+            nb = [int(u) for u in g.cols[g.offsets[v]:g.offsets[v + 1]] if u != v]
+            assert all(col[u] != col[v] for u in nb)
+            if size1[col[v]] > gamma:
+                used = {int(col[u]) for u in nb}
+                assert not [d for d in range(chi) if d != col[v] and size1[d] < gamma and d not in used]
+
+
 ALL = [p1_singleton_closed_form, p2_totals_invariant, p3_single_move_is_eq4, p4_eq6_two_moves,
        p5_lemma3, p6_coarsen_invariance, p7_phase_q_from_scratch, p8_disjoint_cliques,
        p9_ring_of_cliques, p10_bruteforce_upper_bound, p11_coloring, p12_hand_cases,
        p13_rounding, p14_sbm_sanity, validation_codes, p15_loss_is_undone, p16_phases_never_lose,
-       p17_iteration_threshold, p18_coloring_schedule, p19_no_shrink_stops, p20_vf_isolated_pair]
+       p17_iteration_threshold, p18_coloring_schedule, p19_no_shrink_stops, p20_vf_isolated_pair,
+       p21_chain_vertex_following, p22_balanced_coloring]

@@ -40,8 +40,8 @@ MUTANTS = {
         ("W[{new_of[C[u]], new_of[C[g.col[e]]]}] += g.w[e];",
          "if (new_of[C[u]] != new_of[C[g.col[e]]] || u <= g.col[e]) W[{new_of[C[u]], new_of[C[g.col[e]]]}] += g.w[e];"),
     "coloring_ascending_priority":
-        ("return priority(seed, x) > priority(seed, y);",
-         "return priority(seed, x) < priority(seed, y);"),
+        ("return priority(seed, x) > priority(seed, y); });\n    color.assign(g.n, -1);",
+         "return priority(seed, x) < priority(seed, y); });\n    color.assign(g.n, -1);"),
     "coloring_priority_unshifted_seed":
         ("return splitmix64_finalizer((seed << 32) ^ (uint64_t)v);",
          "return splitmix64_finalizer(seed ^ (uint64_t)v);"),
@@ -79,6 +79,29 @@ MUTANTS = {
     "vf_pair_to_larger_id":
         ("map[i] = single[j] ? std::min<int32_t>((int32_t)i, j) : j;",
          "map[i] = single[j] ? std::max<int32_t>((int32_t)i, j) : j;"),
+    "chain_vf_without_the_bound":
+        ("single[i] = others == 1 && (i128)two_m * w > (i128)k[i] * k[nbr[i]];", "single[i] = others == 1;"),
+    "chain_vf_bound_not_strict":
+        ("single[i] = others == 1 && (i128)two_m * w > (i128)k[i] * k[nbr[i]];",
+         "single[i] = others == 1 && (i128)two_m * w >= (i128)k[i] * k[nbr[i]];"),
+    "chain_vf_one_round":
+        ("            coarsen_step();\n            ++rounds;\n",
+         "            coarsen_step();\n            return 1;\n"),
+    "chain_vf_self_loop_rows_excluded":
+        ("if (g.col[e] != i) { ++others; nbr[i] = g.col[e]; w = g.w[e]; }",
+         "{ ++others; nbr[i] = g.col[e]; w = g.w[e]; }"),
+    "chain_vf_pair_to_larger_id":
+        ("map[i] = single[to] ? std::min<int32_t>((int32_t)i, to) : to;",
+         "map[i] = single[to] ? std::max<int32_t>((int32_t)i, to) : to;"),
+    "balance_target_floor":
+        ("const int64_t gamma = (g.n + ncolors - 1) / ncolors;", "const int64_t gamma = g.n / ncolors;"),
+    "balance_without_room_cap":
+        ("                if (moved == room) break;\n", ""),
+    "balance_largest_admissible_colour":
+        ("for (int32_t d = 0; d < ncolors && to < 0; ++d)", "for (int32_t d = ncolors - 1; d >= 0 && to < 0; --d)"),
+    "balance_ascending_priority":
+        ("[&](int32_t x, int32_t y) { return priority(seed, x) > priority(seed, y); });\n    int64_t moved_total",
+         "[&](int32_t x, int32_t y) { return priority(seed, x) < priority(seed, y); });\n    int64_t moved_total"),
     "rounding_truncates":
         ("if (round_bit && (sticky || (mant & 1))) {",
          "if (false && round_bit && (sticky || (mant & 1))) {"),
