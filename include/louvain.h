@@ -75,14 +75,15 @@ typedef struct {
 } louvain_i128;
 
 typedef struct {
-    int32_t vf;                     /* vertex following before the first phase (Sec. 5.3) */
+    int32_t vf;                     /* vertex following before the first phase (Sec. 5.3): 0 none,
+                                       1 single-degree vertices, 2 chain compression */
     int32_t color;                  /* coloring in early phases (Sec. 5.2, Sec. 6.1) */
     int32_t singlet_rule;           /* singlet minimum-label heuristic (Sec. 5.1) */
     int32_t threshold_mode;         /* 0: gain relative to |Q_prev|; 1: absolute gain */
     int32_t color_first_phase_only; /* color the first phase only (Table 4 variant) */
     int32_t max_iter;               /* iteration cap per phase */
     int32_t max_phases;             /* phase cap */
-    int32_t reserved;               /* must be 0 */
+    int32_t color_balance;          /* balance the colour classes' sizes (1) or not (0) */
     louvain_ratio theta_color;      /* threshold while coloring (paper: 1e-2) */
     louvain_ratio theta_final;      /* threshold otherwise (paper: 1e-6) */
     int64_t color_cutoff;           /* color a phase only if it has >= this many vertices (100,000) */
@@ -103,10 +104,12 @@ typedef struct {
     int64_t n, nnz;          /* phase graph */
     int32_t colored;         /* phase ran colored sub-sweeps */
     int32_t num_colors;      /* colors used (0 if uncolored) */
-    int32_t iterations;      /* iterations run in the phase */
+    int32_t iterations;      /* iterations run in the phase (an undone one included) */
     int32_t hit_max_iter;    /* the iteration cap ended the phase */
+    int32_t loss_undone;     /* the last iteration lowered Q and was undone (Sec. 5.1) */
+    int32_t reserved;
     int64_t first_iter;      /* index of the phase's first record in louvain_result.iter */
-    louvain_i128 q_num;      /* N at the end of the phase */
+    louvain_i128 q_num;      /* N at the end of the phase (after any undo) */
     double ms_color, ms_sweep, ms_coarsen;
 } louvain_phase_stats;
 
@@ -118,7 +121,9 @@ typedef struct {
     int64_t iterations;      /* total over phases (records in iter) */
     louvain_i128 q_num, q_den, q0_num; /* final N, D = (2m)^2, singleton N of the first phase graph */
     double q;                /* correctly rounded N / D */
-    int64_t sweep_entries;   /* CSR entries gathered by all sweeps, including discarded look-ahead */
+    int64_t sweep_entries;   /* CSR entries gathered by the sweeps of the iterations run */
+    int64_t lookahead_entries; /* CSR entries gathered by look-ahead sweeps that only measured Q */
+    int64_t vf_rounds;       /* rebuilds done by vertex following (chain mode: its rounds) */
     double ms_total, ms_vf, ms_color, ms_sweep, ms_coarsen; /* host wall-clock split */
     const louvain_phase_stats *phase; /* owned by the handle; valid until the next call */
     const louvain_iter_stats *iter;   /* owned by the handle; valid until the next call */
@@ -151,6 +156,19 @@ louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, 
 louvain_status louvain_vf(louvain_graph_t g, int64_t *n_new_out);
 
 /*
+ * Chain-compressing vertex following (the extension closing Sec. 5.3):
+ * rounds of the rule above for single-neighbour vertices (one neighbour
+ * j != i besides an optional self-loop), each vertex merging only while the
+ * bound in the proof of Lemma 3 stays positive, 2m * w_ij > k_i * k_j (the
+ * exact gain of moving i into j's one-vertex community); each round rebuilds
+ * the graph (the absorbed self-loops join the merged self-loop) and the
+ * rounds repeat until no vertex qualifies.  Valid on the input graph before
+ * any sweep.  *n_new_out: vertices after; *rounds_out (may be NULL): the
+ * rounds that merged.
+ */
+louvain_status louvain_vf_chain(louvain_graph_t g, int64_t *n_new_out, int64_t *rounds_out);
+
+/*
  * Distance-1 coloring of the current phase graph (Sec. 5.2) by
  * Jones-Plassmann rounds with priority pi(v) = SplitMix64 finalizer of
  * (seed << 32) ^ v; the result equals greedy coloring in descending
@@ -159,6 +177,22 @@ louvain_status louvain_vf(louvain_graph_t g, int64_t *n_new_out);
  * the next louvain_coarsen.  *num_colors_out receives the class count.
  */
 louvain_status louvain_color(louvain_graph_t g, uint64_t seed, int32_t *num_colors_out);
+
+/*
+ * Balanced colouring (Sec. 6.2 finds skewed colour classes costly and leaves
+ * balanced sets to future work): after louvain_color, with chi colours on n
+ * vertices and gamma = ceil(n / chi), the over-full classes (more than gamma
+ * vertices) are taken in ascending colour c; in rounds, each waiting vertex of
+ * K_c proposes the smallest colour c' != c that none of its neighbours has and
+ * whose class holds fewer than gamma vertices (none: it stops waiting); each
+ * c' takes its proposers in descending priority, at most gamma - |K_c'|, and of
+ * all taken the first |K_c| - gamma in descending priority move; K_c is done at
+ * gamma or after a round that moves nobody.  The colouring stays proper and
+ * uses no new colour.  seed: the priority seed of the colouring.  At most 4096
+ * colours (LOUVAIN_E_INVALID_ARG beyond).  *moved_out (may be NULL): vertices
+ * that changed class.
+ */
+louvain_status louvain_color_balance(louvain_graph_t g, uint64_t seed, int64_t *moved_out);
 
 /*
  * One synchronous iteration of Alg. 1 on the current phase graph: every
@@ -184,7 +218,9 @@ louvain_status louvain_coarsen(louvain_graph_t g, int64_t *n_new_out);
 /*
  * The full method from the ingested input graph (any earlier step calls are
  * discarded): optional VF, then phases (colored while the schedule of
- * Sec. 6.1 allows), each iterated until a loss or a net gain below
+ * Sec. 6.1 allows), each iterated until an iteration loses modularity (that
+ * iteration is undone: Sec. 5.1 continues a phase only on a net gain, and
+ * Lemma 1 shows simultaneous moves can lose), a net gain below
  * theta * |Q_prev| (from the second iteration), no move, or max_iter, then
  * rebuilt; stops when a final-mode phase gains less than theta_final, does
  * not shrink the graph, or max_phases is reached.  labels_out receives

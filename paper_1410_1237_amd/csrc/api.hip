@@ -202,6 +202,12 @@ struct louvain_graph_s {
     std::string err;
     bool poisoned = false;
     std::vector<std::pair<void *, size_t>> owned;
+    // set for the allocation-free entry point: buffers are carved in order
+    // from this device range instead of the pool (count_only: sizes summed,
+    // nothing carved, no device work)
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+    bool count_only = false;
 
     // input graph (level 0)
     int64_t n0 = 0, nnz0 = 0, two_m = 0, kmax0 = 0, self0 = 0;
@@ -218,13 +224,16 @@ struct louvain_graph_s {
     // phase state
     int64_t *k = nullptr, *a = nullptr;
     int32_t *comm_prev = nullptr, *comm_next = nullptr, *size = nullptr, *orig_map = nullptr;
+    int32_t *comm_save = nullptr; // partition before the last committed iteration (undo of a loss)
     int64_t sigma_in = 0; // internal weight of the current partition (step API)
     int64_t swept_entries = 0; // entries gathered by every sweep of the current run
+    int64_t lookahead_entries = 0; // of those, by look-ahead sweeps whose moves were discarded
 
     // coloring
     int32_t *color = nullptr, *jp_cnt = nullptr, *front_a = nullptr, *front_b = nullptr, *counters = nullptr;
     int32_t *jp_chunk = nullptr;            // two chunk lists
     uint64_t *jp_bm = nullptr;              // colour bitmaps of long rows (kept zero)
+    unsigned long long *bal_closed = nullptr; // closed-colour bitmap of the balanced colouring (64 words)
     int64_t jp_chunk_cap = 0, jp_bm_cap = 0;
     int32_t num_colors = 0;
     bool colored = false;
@@ -290,6 +299,7 @@ struct louvain_graph_s {
         double bytes, entries;
         int stat_slot;
         bool from_stats;
+        bool singleton; // a sweep from the singleton partition (no community gather)
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> event_pool;
@@ -321,6 +331,21 @@ louvain_status hip_fail(G *g, hipError_t e, const char *where)
 template <typename T> louvain_status alloc(G *g, T **p, int64_t count)
 {
     const size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
+    if (g->arena || g->count_only) {
+        const size_t need = (bytes + 255) & ~(size_t)255;
+        if (g->count_only) {
+            g->arena_used += need;
+            *p = nullptr;
+            return LOUVAIN_OK;
+        }
+        if (need > g->arena_cap - g->arena_used)
+            return fail(g, LOUVAIN_E_OOM,
+                        "the allocation-free entry point's scratch (" + std::to_string(g->arena_cap) +
+                            " bytes) cannot hold this run: " + std::to_string(g->arena_used + need) + " bytes needed");
+        *p = (T *)(g->arena + g->arena_used);
+        g->arena_used += need;
+        return LOUVAIN_OK;
+    }
     void *q = nullptr;
     if (pool().get(&q, bytes, g->dev) != hipSuccess) {
         (void)hipGetLastError();
@@ -349,7 +374,8 @@ void release_all(G *g)
         (void)hipStreamDestroy(g->gst);
         g->gst = nullptr;
     }
-    for (auto &b : g->owned) pool().put(b.first, b.second, g->dev);
+    if (!g->arena)
+        for (auto &b : g->owned) pool().put(b.first, b.second, g->dev);
     g->owned.clear();
     for (auto ev : g->event_pool) (void)hipEventDestroy(ev);
     for (auto &p : g->pending) {
@@ -406,7 +432,7 @@ struct ProfScope {
         if (!g->prof) return;
         b = take_event(g);
         (void)hipEventRecord(b, g->st);
-        g->pending.push_back({a, b, rec, bytes, entries, slot, from_stats});
+        g->pending.push_back({a, b, rec, bytes, entries, slot, from_stats, g->singleton});
     }
 };
 
@@ -424,7 +450,9 @@ void prof_collect(G *g, const lv::SweepStats *host_stats, int wb)
         r.ms += ms;
         if (p.from_stats && host_stats) {
             // per vertex: list entry 4, offsets 16, comm 4, k 8, a[A] 8, sizes 8, comm_next 4
-            // per entry: column 4 + weight wb + comm of the neighbour 4; per distinct community: a 8
+            // per entry: column 4 + weight wb + comm of the neighbour 4 (not read by a sweep
+            // from the singleton partition, where it is the neighbour itself); per distinct
+            // community: a 8
             // (a slot sums all launches of its bin since the last read: counted once)
             // hub rows: the entries are gathered by the pass-1 blocks of the
             // large (or all-bins) launch, the distinct pairs read by pass 2
@@ -435,7 +463,7 @@ void prof_collect(G *g, const lv::SweepStats *host_stats, int wb)
                 const lv::SweepStats &s = host_stats[b];
                 const bool hub = b >= 9;
                 if (!hub || !hub_pass2) {
-                    r.bytes += (8.0 + wb) * (double)s.entries;
+                    r.bytes += ((p.singleton ? 4.0 : 8.0) + wb) * (double)s.entries;
                     r.entries += (double)s.entries;
                 }
                 if (!hub || hub_pass2) r.bytes += 8.0 * (double)s.pairs;
@@ -491,6 +519,7 @@ bool wide_gains(const G *g) { return (i128)g->two_m * (i128)g->kmax >= ((i128)1 
 
 void release_buffer(G *g, void *p)
 {
+    if (g->arena) return; // carved from the scratch: nothing to give back
     for (auto it = g->owned.begin(); it != g->owned.end(); ++it)
         if (it->first == p) {
             pool().put(it->first, it->second, g->dev);
@@ -865,6 +894,24 @@ louvain_status commit_all(G *g)
     return LOUVAIN_OK;
 }
 
+// keeps the current partition so that the next iteration can be undone
+louvain_status save_partition(G *g)
+{
+    if (g->cur.n)
+        HIPCHK(g, hipMemcpyAsync(g->comm_save, g->comm_prev, g->cur.n * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                 g->st));
+    return LOUVAIN_OK;
+}
+
+// an iteration that lost modularity is undone: every vertex goes back to its
+// saved community, with the community degrees and sizes moved back alike
+louvain_status undo_iteration(G *g)
+{
+    ProfScope ps(g, PR_COMMIT, 12.0 * (double)g->cur.n, 0);
+    lv::commit(nullptr, g->cur.n, g->comm_prev, g->comm_save, g->k, g->a, g->size, g->st);
+    return LOUVAIN_OK;
+}
+
 // colored iteration: classes in ascending colour, each synchronous on the
 // state after the classes before it (Sec. 5.4 step 3)
 louvain_status colored_iteration(G *g, int singlet, SweepSum &sum, lv::SweepStats *host)
@@ -896,12 +943,12 @@ louvain_status coarsen_current(G *g, const int32_t *comm, int64_t &n_new, bool v
     int64_t nnz_new = 0;
     {
         ProfScope ps(g, PR_COARSEN, 0, (double)g->cur.nnz);
-        if (vf)
-            lv::coarsen_vf(g->cur, comm, g->k, g->orig_map, g->n0, b, g->off_b[dst], g->col_b[dst], g->w_b[dst], g->k,
-                           g->dscal, &n_new, &nnz_new, g->scratch, g->st);
-        else
-            lv::coarsen(g->cur, comm, g->orig_map, g->n0, b, g->off_b[dst], g->col_b[dst], g->w_b[dst], g->k,
-                        g->dscal, &n_new, &nnz_new, g->scratch, g->st);
+        const hipError_t e =
+            vf ? lv::coarsen_vf(g->cur, comm, g->k, g->orig_map, g->n0, b, g->off_b[dst], g->col_b[dst], g->w_b[dst],
+                                g->k, g->dscal, &n_new, &nnz_new, g->scratch, g->st)
+               : lv::coarsen(g->cur, comm, g->orig_map, g->n0, b, g->off_b[dst], g->col_b[dst], g->w_b[dst], g->k,
+                             g->dscal, &n_new, &nnz_new, g->scratch, g->st);
+        if (e != hipSuccess) return hip_fail(g, e, "graph rebuild");
     }
     g->cur.n = n_new;
     g->cur.nnz = nnz_new;
@@ -920,6 +967,36 @@ louvain_status coarsen_current(G *g, const int32_t *comm, int64_t &n_new, bool v
     g->kmax = h[1];
     g->self = h[2];
     return init_state(g);
+}
+
+// vertex following before the first phase (Sec. 5.3): mode 1 single-degree
+// vertices, one round; mode 2 chain compression, rounds until no vertex
+// follows another.  after(n_before, n_after) runs after every rebuild (the
+// batched form's bookkeeping).  *rounds_out: the rounds that rebuilt.
+template <class F> louvain_status vertex_following(G *g, int mode, F after, int64_t *rounds_out)
+{
+    louvain_status s;
+    int64_t rounds = 0;
+    for (;;) {
+        const int64_t n0 = g->cur.n;
+        if (mode == 1) {
+            lv::vf_map(g->cur, g->comm_prev, g->st);
+        } else {
+            lv::vf_chain_map(g->cur, g->k, g->two_m, g->b_gid, g->b_two_m, g->comm_prev, g->dscal + 12, g->scratch,
+                             g->st);
+            int64_t moved = 0;
+            HIPCHK(g, hipMemcpyAsync(&moved, g->dscal + 12, sizeof(int64_t), hipMemcpyDeviceToHost, g->st));
+            if ((s = sync(g))) return s;
+            if (moved == 0) break;
+        }
+        int64_t nv = 0;
+        if ((s = coarsen_current(g, g->comm_prev, nv, true))) return s;
+        if ((s = after(n0, nv))) return s;
+        ++rounds;
+        if (mode == 1) break;
+    }
+    if (rounds_out) *rounds_out = rounds;
+    return LOUVAIN_OK;
 }
 
 louvain_status do_color(G *g, uint64_t seed)
@@ -953,6 +1030,7 @@ louvain_status do_color(G *g, uint64_t seed)
         c.chunk[1] = g->jp_chunk + 2 * g->jp_chunk_cap;
         c.bm = (unsigned long long *)g->jp_bm;
         g->num_colors = lv::color_jp(g->cur, seed, c, g->scratch, g->st);
+        if (g->num_colors < 0) return hip_fail(g, hipGetLastError(), "coloring (copy or wait on the stream)");
     }
     louvain_status s = sync(g);
     if (s) return s;
@@ -966,6 +1044,39 @@ louvain_status do_color(G *g, uint64_t seed)
     }
     g->colored = true;
     g->bins_valid = false;
+    return LOUVAIN_OK;
+}
+
+// balanced colouring of the current colouring (after do_color); *moved_out:
+// the vertices that changed class
+louvain_status do_balance(G *g, uint64_t seed, int64_t *moved_out)
+{
+    if (!g->colored) return fail(g, LOUVAIN_E_STATE, "balancing needs a colouring of the current graph");
+    const int64_t n = g->cur.n;
+    lv::BalanceBufs b;
+    b.color = g->color;
+    b.list = g->bin_verts;
+    b.waiting = g->jp_cnt;
+    b.prop = g->jp_cnt + n;
+    b.taken = g->jp_cnt + 2 * n;
+    b.before = g->jp_cnt + 3 * n;
+    b.size = g->front_a;
+    b.closed = g->bal_closed;
+    b.keys = g->keys;
+    b.keys_alt = g->keys_alt;
+    b.vals = g->vals;
+    b.vals_alt = g->vals_alt;
+    b.first = g->bin_offd;
+    int64_t moved;
+    {
+        ProfScope ps(g, PR_COLOR, 0, (double)g->cur.nnz);
+        moved = lv::color_balance(g->cur, seed, g->num_colors, b, g->scratch, g->st);
+    }
+    if (moved == -2) return fail(g, LOUVAIN_E_INVALID_ARG, "balanced colouring takes at most 4096 colours");
+    if (moved < 0) return hip_fail(g, hipGetLastError(), "balanced colouring (copy or wait on the stream)");
+    prof_collect(g, nullptr, 0);
+    g->bins_valid = false;
+    if (moved_out) *moved_out = moved;
     return LOUVAIN_OK;
 }
 
@@ -983,8 +1094,9 @@ louvain_status check_params(G *g, const louvain_params *p)
     if (p->theta_color.den <= 0 || p->theta_final.den <= 0 || p->theta_color.num < 0 || p->theta_final.num < 0)
         return fail(g, LOUVAIN_E_INVALID_ARG, "thresholds need num >= 0 and den > 0");
     if (p->max_iter < 1 || p->max_phases < 1) return fail(g, LOUVAIN_E_INVALID_ARG, "max_iter and max_phases must be >= 1");
+    if (p->vf < 0 || p->vf > 2) return fail(g, LOUVAIN_E_INVALID_ARG, "vf is 0, 1 or 2");
     if (p->threshold_mode != 0 && p->threshold_mode != 1) return fail(g, LOUVAIN_E_INVALID_ARG, "threshold_mode is 0 or 1");
-    if (p->reserved != 0) return fail(g, LOUVAIN_E_INVALID_ARG, "reserved must be 0");
+    if (p->color_balance != 0 && p->color_balance != 1) return fail(g, LOUVAIN_E_INVALID_ARG, "color_balance is 0 or 1");
     return LOUVAIN_OK;
 }
 
@@ -999,6 +1111,9 @@ louvain_status copy_out(G *g, void *dst, const void *src, size_t bytes, uint32_t
 // Sweep s reads C_{s-1}, so its gather also yields the internal weight of
 // C_{s-1} and hence Q_{s-1}; the stop test for iteration s-1 is therefore
 // taken after sweep s, whose moves are discarded if iteration s-1 was the last.
+// If iteration s-1 lost modularity (against Q_{s-2}; Q_0 is the phase's
+// start), it is undone from the partition saved before its commit, and the
+// phase ends (Sec. 5.1: a phase continues only on a net gain).
 louvain_status run_phase_plain(G *g, const louvain_params *p, louvain_ratio th, louvain_phase_stats &ph, i128 N0)
 {
     lv::SweepStats host[lv::NBINS];
@@ -1024,11 +1139,20 @@ louvain_status run_phase_plain(G *g, const louvain_params *p, louvain_ratio th, 
         if (s_idx >= 2) {
             N[s_idx - 1] = (i128)g->two_m * sum.sigma_prev - S2[s_idx - 1];
             g->iters.back().q_num = to_abi(N[s_idx - 1]);
+            if (N[s_idx - 1] < N[s_idx - 2]) {
+                g->lookahead_entries += sum.entries;
+                if ((s = undo_iteration(g))) return s;
+                ph.loss_undone = 1;
+                t_end = s_idx - 1;
+                break;
+            }
             if (s_idx - 1 >= 2 && below_threshold(N[s_idx - 1], N[s_idx - 2], D, th, p->threshold_mode)) {
+                g->lookahead_entries += sum.entries;
                 t_end = s_idx - 1;
                 break;
             }
             if (s_idx - 1 >= p->max_iter) { // only reached when the cap needed N of the last iteration
+                g->lookahead_entries += sum.entries;
                 ph.hit_max_iter = 1;
                 t_end = s_idx - 1;
                 break;
@@ -1048,6 +1172,7 @@ louvain_status run_phase_plain(G *g, const louvain_params *p, louvain_ratio th, 
             t_end = s_idx;
             break;
         }
+        if ((s = save_partition(g))) return s;
         commit_all(g);
         lv::sum_squares(g->a, g->cur.n, g->dscal + 4, g->scratch, g->st);
         if ((s = read_i128(g, g->dscal + 4, S2[s_idx]))) return s;
@@ -1055,7 +1180,7 @@ louvain_status run_phase_plain(G *g, const louvain_params *p, louvain_ratio th, 
         // at the iteration cap, one more sweep (whose moves are discarded) yields N[s_idx]
     }
     ph.iterations = t_end;
-    ph.q_num = to_abi(N[t_end]);
+    ph.q_num = to_abi(ph.loss_undone ? N[t_end - 1] : N[t_end]);
     // drop the look-ahead record if it was pushed
     while ((int64_t)g->iters.size() > ph.first_iter + t_end) g->iters.pop_back();
     // comm_next may hold a discarded look-ahead; resync it with comm_prev
@@ -1076,6 +1201,7 @@ louvain_status run_phase_colored(G *g, const louvain_params *p, louvain_ratio th
     for (;;) {
         ++t;
         SweepSum sum;
+        if ((s = save_partition(g))) return s;
         if ((s = colored_iteration(g, p->singlet_rule, sum, host))) return s;
         g->swept_entries += sum.entries;
         i128 S2;
@@ -1089,6 +1215,12 @@ louvain_status run_phase_colored(G *g, const louvain_params *p, louvain_ratio th
         rec.entries = sum.entries;
         g->iters.push_back(rec);
         if (sum.moves == 0) break;
+        if (N_t < N_prev) { // a loss (Sec. 5.1): back to the partition before this iteration
+            if ((s = undo_iteration(g))) return s;
+            ph.loss_undone = 1;
+            N_t = N_prev;
+            break;
+        }
         if (t >= 2 && below_threshold(N_t, N_prev, D, th, p->threshold_mode)) break;
         if (t >= p->max_iter) {
             ph.hit_max_iter = 1;
@@ -1127,86 +1259,79 @@ void louvain_params_default(louvain_params *p)
 
 const char *louvain_last_error(louvain_graph_t g) { return g ? g->err.c_str() : g_init_error.c_str(); }
 
-louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
-                                const int32_t *weights, uint32_t flags, void *hip_stream, louvain_graph_t *out)
+} // extern "C"
+
+namespace {
+
+// device buffers of a handle for a graph of n vertices and nnz entries
+louvain_status alloc_buffers(G *g, int64_t n, int64_t nnz, bool weighted)
 {
-    g_init_error.clear();
-    if (!out) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "out is NULL");
-    *out = nullptr;
-    if (n < 0 || nnz < 0) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "negative size");
-    if (n >= ((int64_t)1 << 31) - 1) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "n must be below 2^31 - 1");
-    if (!offsets) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "offsets is NULL");
-    if (nnz > 0 && !cols) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "cols is NULL");
-    if (flags & ~(LOUVAIN_DEVICE_PTRS | LOUVAIN_VALIDATE)) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "unknown flags");
-    const bool dev_ptrs = flags & LOUVAIN_DEVICE_PTRS;
-    if (!dev_ptrs) {
-        if (offsets[0] != 0 || offsets[n] != nnz)
-            return fail(nullptr, LOUVAIN_E_BAD_CSR, "offsets[0] must be 0 and offsets[n] must equal nnz");
-    }
-    G *g = new G();
-    g->st = (hipStream_t)hip_stream;
-    if (hipGetDevice(&g->dev) != hipSuccess) {
-        delete g;
-        return fail(nullptr, LOUVAIN_E_HIP, "hipGetDevice failed");
-    }
-    louvain_status s = LOUVAIN_OK;
-    auto bail = [&](louvain_status st) {
-        g_init_error = g->err;
-        release_all(g);
-        delete g;
-        return st;
-    };
-    g->n0 = n;
-    g->nnz0 = nnz;
+    louvain_status s;
     const int64_t big = (nnz > n ? nnz : n) + 1;
     if ((s = alloc(g, &g->off0, n + 1)) || (s = alloc(g, &g->col0, nnz)) || (s = alloc(g, &g->k0, n)) ||
-        (weights && (s = alloc(g, &g->w0, nnz))))
-        return bail(s);
+        (weighted && (s = alloc(g, &g->w0, nnz))))
+        return s;
     for (int b = 0; b < 2; ++b)
         if ((s = alloc(g, &g->off_b[b], n + 1)) || (s = alloc(g, &g->col_b[b], nnz)) ||
             (s = alloc(g, &g->w_b[b], nnz)))
-            return bail(s);
+            return s;
     if ((s = alloc(g, &g->k, n)) || (s = alloc(g, &g->a, n)) || (s = alloc(g, &g->comm_prev, n)) ||
-        (s = alloc(g, &g->comm_next, n)) || (s = alloc(g, &g->size, n)) || (s = alloc(g, &g->orig_map, n)) ||
+        (s = alloc(g, &g->comm_next, n)) || (s = alloc(g, &g->comm_save, n)) || (s = alloc(g, &g->size, n)) ||
+        (s = alloc(g, &g->orig_map, n)) ||
         (s = alloc(g, &g->color, n)) || (s = alloc(g, &g->jp_cnt, 5 * n)) || (s = alloc(g, &g->front_a, n)) ||
         (s = alloc(g, &g->front_b, n)) || (s = alloc(g, &g->counters, 16)) || (s = alloc(g, &g->keys, big)) ||
         (s = alloc(g, &g->keys_alt, big)) || (s = alloc(g, &g->vals, big)) || (s = alloc(g, &g->vals_alt, big)) ||
         (s = alloc(g, &g->run, big)) || (s = alloc(g, &g->bin_verts, n)) || (s = alloc(g, &g->cpre, n + 1)) ||
-        (s = alloc(g, &g->bpre, n + 1)) || (s = alloc(g, &g->xpre, n + 1)) || (s = alloc(g, &g->flag, n + 1)) || (s = alloc(g, &g->new_id, n + 1)) ||
-        (s = alloc(g, &g->stats, lv::NBINS * lv::STAT_REP)) || (s = alloc(g, &g->dscal, 16)) || (s = alloc(g, &g->vflag, 4)))
-        return bail(s);
+        (s = alloc(g, &g->bpre, n + 1)) || (s = alloc(g, &g->xpre, n + 1)) || (s = alloc(g, &g->flag, n + 1)) ||
+        (s = alloc(g, &g->new_id, n + 1)) || (s = alloc(g, &g->stats, lv::NBINS * lv::STAT_REP)) ||
+        (s = alloc(g, &g->dscal, 16)) || (s = alloc(g, &g->vflag, 4)) || (s = alloc(g, &g->bal_closed, 64)))
+        return s;
     g->bin_hist_cap = 16 * 64;
     if ((s = alloc(g, &g->bin_hist, g->bin_hist_cap)) || (s = alloc(g, &g->bin_offd, g->bin_hist_cap + 1)))
-        return bail(s);
+        return s;
     const int64_t part = lv::radix_partials_needed(big) + lv::scan_partials_needed(256 * (big / 4096 + 1)) +
                          lv::scan_partials_needed(big) + 4096;
-    if ((s = alloc(g, &g->scratch.part, part))) return bail(s);
+    if ((s = alloc(g, &g->scratch.part, part))) return s;
     g->scratch.part_cap = part;
-    if ((s = alloc(g, &g->scratch.scalar, 8))) return bail(s);
-    if ((s = alloc(g, &g->scratch.rep, 8 * lv::RED_REP + 8))) return bail(s);
-    {
-        // LOUVAIN_HIP_GRAPHS: 0 no graph capture, 1 (default) the batched
-        // sweep stage, 2 also the colour classes of an iteration
-        const char *env = std::getenv("LOUVAIN_HIP_GRAPHS");
-        const int mode = env && env[0] >= '0' && env[0] <= '2' ? env[0] - '0' : 1;
-        g->graphs_ok = mode > 0;
-        g->graph_colored = mode > 1;
-        const char *tune = std::getenv("LOUVAIN_AUTOTUNE");
-        g->tune = !(tune && tune[0] == '0');
-        // LOUVAIN_LANES=l1,l2,...: fixed lanes per vertex for bins 1, 2, ...
-        // (each one of the bin's choices; no tuning)
-        if (const char *ln = std::getenv("LOUVAIN_LANES")) {
-            int b = 1;
-            for (const char *q = ln; *q && b <= 8; ++b) {
-                const int v = std::atoi(q);
-                for (int c = 0; c < 4 && lv::kLaneChoices[b][c]; ++c)
-                    if (lv::kLaneChoices[b][c] == v) g->lanes[b] = v;
-                while (*q && *q != ',') ++q;
-                if (*q == ',') ++q;
-            }
-            g->tune = false;
+    if ((s = alloc(g, &g->scratch.scalar, 8))) return s;
+    if ((s = alloc(g, &g->scratch.rep, 8 * lv::RED_REP + 8))) return s;
+    return LOUVAIN_OK;
+}
+
+// environment choices of a new handle
+void read_env(G *g)
+{
+    // LOUVAIN_HIP_GRAPHS: 0 no graph capture, 1 (default) the batched
+    // sweep stage, 2 also the colour classes of an iteration
+    const char *env = std::getenv("LOUVAIN_HIP_GRAPHS");
+    const int mode = env && env[0] >= '0' && env[0] <= '2' ? env[0] - '0' : 1;
+    g->graphs_ok = mode > 0;
+    g->graph_colored = mode > 1;
+    const char *tune = std::getenv("LOUVAIN_AUTOTUNE");
+    g->tune = !(tune && tune[0] == '0');
+    // LOUVAIN_LANES=l1,l2,...: fixed lanes per vertex for bins 1, 2, ...
+    // (each one of the bin's choices; no tuning)
+    if (const char *ln = std::getenv("LOUVAIN_LANES")) {
+        int b = 1;
+        for (const char *q = ln; *q && b <= 8; ++b) {
+            const int v = std::atoi(q);
+            for (int c = 0; c < 4 && lv::kLaneChoices[b][c]; ++c)
+                if (lv::kLaneChoices[b][c] == v) g->lanes[b] = v;
+            while (*q && *q != ',') ++q;
+            if (*q == ',') ++q;
         }
+        g->tune = false;
     }
+}
+
+// copies (or validates in place) the input CSR into the handle's buffers,
+// computes degrees and 2m and sets the first phase's singleton state
+louvain_status ingest(G *g, int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                      const int32_t *weights, uint32_t flags)
+{
+    const bool dev_ptrs = flags & LOUVAIN_DEVICE_PTRS;
+    g->n0 = n;
+    g->nnz0 = nnz;
     g->recs.resize(PR_COUNT);
     for (int r = 0; r < PR_COUNT; ++r) g->recs[r].name = kNames[r];
 
@@ -1216,7 +1341,7 @@ louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, 
         (weights && nnz && hipMemcpyAsync(g->w0, weights, nnz * sizeof(int32_t), kind, g->st) != hipSuccess)) {
         (void)hipGetLastError();
         g->err = "copy of the input CSR failed";
-        return bail(LOUVAIN_E_HIP);
+        return LOUVAIN_E_HIP;
     }
     lv::Csr in;
     in.n = n;
@@ -1238,19 +1363,19 @@ louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, 
         if (hipMemcpyAsync(&code, g->vflag, sizeof(code), hipMemcpyDeviceToHost, g->st) != hipSuccess ||
             hipStreamSynchronize(g->st) != hipSuccess) {
             g->err = "validation failed to run";
-            return bail(LOUVAIN_E_HIP);
+            return LOUVAIN_E_HIP;
         }
         if (code == 0 && full) {
             lv::validate_entries(in, true, g->vflag, g->st);
             if (hipMemcpyAsync(&code, g->vflag, sizeof(code), hipMemcpyDeviceToHost, g->st) != hipSuccess ||
                 hipStreamSynchronize(g->st) != hipSuccess) {
                 g->err = "validation failed to run";
-                return bail(LOUVAIN_E_HIP);
+                return LOUVAIN_E_HIP;
             }
         }
         if (code != 0) {
             g->err = std::string("invalid CSR: ") + why[code > 0 && code < 6 ? code : 0];
-            return bail(LOUVAIN_E_BAD_CSR);
+            return LOUVAIN_E_BAD_CSR;
         }
     }
     lv::degrees(in, g->k0, g->dscal, g->scratch, g->st, full ? nullptr : g->vflag);
@@ -1260,20 +1385,66 @@ louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, 
         hipMemcpyAsync(&range_code, g->vflag, sizeof(range_code), hipMemcpyDeviceToHost, g->st) != hipSuccess ||
         hipStreamSynchronize(g->st) != hipSuccess) {
         g->err = "degree computation failed";
-        return bail(LOUVAIN_E_HIP);
+        return LOUVAIN_E_HIP;
     }
     if (range_code != 0) {
         g->err = std::string("invalid CSR: ") + why[range_code > 0 && range_code < 6 ? range_code : 0];
-        return bail(LOUVAIN_E_BAD_CSR);
+        return LOUVAIN_E_BAD_CSR;
     }
     g->two_m = h[0];
     g->kmax0 = h[1];
     g->self0 = h[2];
     if (g->two_m < 0 || g->two_m >= ((int64_t)1 << 62)) {
         g->err = "2m >= 2^62";
-        return bail(LOUVAIN_E_OVERFLOW);
+        return LOUVAIN_E_OVERFLOW;
     }
-    if ((s = reset_level0(g)) || (s = sync(g))) return bail(s);
+    louvain_status s;
+    if ((s = reset_level0(g)) || (s = sync(g))) return s;
+    return LOUVAIN_OK;
+}
+
+// argument checks shared by the ingest entry points
+louvain_status check_csr_args(int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols, uint32_t flags)
+{
+    if (n < 0 || nnz < 0) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "negative size");
+    if (n >= ((int64_t)1 << 31) - 1) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "n must be below 2^31 - 1");
+    if (!offsets) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "offsets is NULL");
+    if (nnz > 0 && !cols) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "cols is NULL");
+    if (flags & ~(LOUVAIN_DEVICE_PTRS | LOUVAIN_VALIDATE)) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "unknown flags");
+    if (!(flags & LOUVAIN_DEVICE_PTRS)) {
+        if (offsets[0] != 0 || offsets[n] != nnz)
+            return fail(nullptr, LOUVAIN_E_BAD_CSR, "offsets[0] must be 0 and offsets[n] must equal nnz");
+    }
+    return LOUVAIN_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+louvain_status louvain_init_csr(int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                                const int32_t *weights, uint32_t flags, void *hip_stream, louvain_graph_t *out)
+{
+    g_init_error.clear();
+    if (!out) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    louvain_status s = check_csr_args(n, nnz, offsets, cols, flags);
+    if (s) return s;
+    G *g = new G();
+    g->st = (hipStream_t)hip_stream;
+    if (const hipError_t e = hipGetDevice(&g->dev)) {
+        delete g;
+        return fail(nullptr, LOUVAIN_E_HIP, std::string("hipGetDevice failed: ") + hipGetErrorString(e));
+    }
+    auto bail = [&](louvain_status st) {
+        g_init_error = g->err;
+        release_all(g);
+        delete g;
+        return st;
+    };
+    if ((s = alloc_buffers(g, n, nnz, weights != nullptr))) return bail(s);
+    read_env(g);
+    if ((s = ingest(g, n, nnz, offsets, cols, weights, flags))) return bail(s);
     *out = g;
     return LOUVAIN_OK;
 }
@@ -1291,10 +1462,18 @@ louvain_status louvain_vf(louvain_graph_t g, int64_t *n_new_out)
     louvain_status s = check_handle(g);
     if (s) return s;
     if (g->level != 0) return fail(g, LOUVAIN_E_STATE, "vertex following applies to the input graph only");
-    lv::vf_map(g->cur, g->comm_prev, g->st);
-    int64_t n_new = 0;
-    if ((s = coarsen_current(g, g->comm_prev, n_new, true))) return s;
-    if (n_new_out) *n_new_out = n_new;
+    if ((s = vertex_following(g, 1, [](int64_t, int64_t) { return LOUVAIN_OK; }, nullptr))) return s;
+    if (n_new_out) *n_new_out = g->cur.n;
+    return LOUVAIN_OK;
+}
+
+louvain_status louvain_vf_chain(louvain_graph_t g, int64_t *n_new_out, int64_t *rounds_out)
+{
+    louvain_status s = check_handle(g);
+    if (s) return s;
+    if (g->level != 0) return fail(g, LOUVAIN_E_STATE, "vertex following applies to the input graph only");
+    if ((s = vertex_following(g, 2, [](int64_t, int64_t) { return LOUVAIN_OK; }, rounds_out))) return s;
+    if (n_new_out) *n_new_out = g->cur.n;
     return LOUVAIN_OK;
 }
 
@@ -1305,6 +1484,13 @@ louvain_status louvain_color(louvain_graph_t g, uint64_t seed, int32_t *num_colo
     if ((s = do_color(g, seed))) return s;
     if (num_colors_out) *num_colors_out = g->num_colors;
     return LOUVAIN_OK;
+}
+
+louvain_status louvain_color_balance(louvain_graph_t g, uint64_t seed, int64_t *moved_out)
+{
+    louvain_status s = check_handle(g);
+    if (s) return s;
+    return do_balance(g, seed, moved_out);
 }
 
 louvain_status louvain_sweep(louvain_graph_t g, const louvain_params *p, louvain_iter_stats *out)
@@ -1364,6 +1550,7 @@ louvain_status louvain_run(louvain_graph_t g, const louvain_params *p, int32_t *
     g->phases.clear();
     g->iters.clear();
     g->swept_entries = 0;
+    g->lookahead_entries = 0;
     if ((s = reset_level0(g))) return s;
     louvain_result res;
     std::memset(&res, 0, sizeof(res));
@@ -1375,9 +1562,8 @@ louvain_status louvain_run(louvain_graph_t g, const louvain_params *p, int32_t *
     if (g->two_m > 0) {
         if (p->vf) {
             const auto t0 = std::chrono::steady_clock::now();
-            int64_t nv = 0;
-            lv::vf_map(g->cur, g->comm_prev, g->st);
-            if ((s = coarsen_current(g, g->comm_prev, nv, true))) return s;
+            if ((s = vertex_following(g, p->vf, [](int64_t, int64_t) { return LOUVAIN_OK; }, &res.vf_rounds)))
+                return s;
             ms_vf = ms_since(t0);
         }
         res.n_vf = g->cur.n;
@@ -1398,6 +1584,7 @@ louvain_status louvain_run(louvain_graph_t g, const louvain_params *p, int32_t *
             auto t0 = std::chrono::steady_clock::now();
             if (colored) {
                 if ((s = do_color(g, p->color_seed))) return s;
+                if (p->color_balance && (s = do_balance(g, p->color_seed, nullptr))) return s;
                 ph.num_colors = g->num_colors;
             }
             ph.ms_color = ms_since(t0);
@@ -1447,7 +1634,8 @@ louvain_status louvain_run(louvain_graph_t g, const louvain_params *p, int32_t *
         res.q_den = to_abi(g->two_m > 0 ? D : (i128)1);
         res.q0_num = to_abi(N0);
         res.q = g->two_m > 0 ? exact_ratio(N_final, D) : 0.0;
-        res.sweep_entries = g->swept_entries;
+        res.sweep_entries = g->swept_entries - g->lookahead_entries;
+        res.lookahead_entries = g->lookahead_entries;
         res.ms_total = ms_since(t_start);
         res.ms_vf = ms_vf;
         res.ms_color = ms_color;
@@ -1546,6 +1734,8 @@ louvain_status louvain_profile_get(louvain_graph_t g, int32_t idx, const char **
     return LOUVAIN_OK;
 }
 
+
+
 } // extern "C"
 
 // ===========================================================================
@@ -1573,7 +1763,7 @@ struct louvain_batch_s {
         // current phase
         bool sweeping = false;
         std::vector<i128> S2, Nt;
-        int t_end = 0, hit = 0;
+        int t_end = 0, hit = 0, undone = 0;
     };
     std::vector<Run> runs;
 };
@@ -1828,11 +2018,10 @@ louvain_status louvain_batch_run(louvain_batch_t b, const louvain_params *p, int
     } unbind{g};
 
     if (p->vf && g->two_m > 0) {
-        const int64_t n0 = g->cur.n;
-        int64_t nv = 0;
-        lv::vf_map(g->cur, g->comm_prev, g->st);
-        if ((s = coarsen_current(g, g->comm_prev, nv, true))) return s;
-        if ((s = batch_after_coarsen(b, n0, nv))) return s;
+        // chain rounds take each graph's own 2m (b_gid, b_two_m are bound)
+        if ((s = vertex_following(g, p->vf, [&](int64_t n0, int64_t nv) { return batch_after_coarsen(b, n0, nv); },
+                                  nullptr)))
+            return s;
     }
     if ((s = batch_sums(b, g->k, true, sq, nullptr, &self))) return s;
     for (int32_t i = 0; i < ng; ++i) {
@@ -1863,6 +2052,7 @@ louvain_status louvain_batch_run(louvain_batch_t b, const louvain_params *p, int
             r.Nt.assign(1, r.Q_prev);
             r.t_end = 0;
             r.hit = 0;
+            r.undone = 0;
         }
         HIPCHK(g, hipMemcpyAsync(b->active_d, active.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, g->st));
         // the bins hold only the vertices of sweeping graphs; they are rebuilt
@@ -1896,12 +2086,23 @@ louvain_status louvain_batch_run(louvain_batch_t b, const louvain_params *p, int
                 if (sidx >= 2) {
                     r.Nt[sidx - 1] = (i128)b->two_m[i] * sigma - r.S2[sidx - 1];
                     r.iters.back().q_num = to_abi(r.Nt[sidx - 1]);
+                    const int64_t look = gst[8 * i + 4];
+                    if (r.Nt[sidx - 1] < r.Nt[sidx - 2]) { // a loss: undone, the phase ends (Sec. 5.1)
+                        g->lookahead_entries += look;
+                        keep[i] = 2;
+                        r.undone = 1;
+                        r.t_end = sidx - 1;
+                        r.sweeping = false;
+                        continue;
+                    }
                     if (sidx - 1 >= 2 && below_threshold(r.Nt[sidx - 1], r.Nt[sidx - 2], D, th, p->threshold_mode)) {
+                        g->lookahead_entries += look;
                         r.t_end = sidx - 1;
                         r.sweeping = false;
                         continue;
                     }
                     if (sidx - 1 >= p->max_iter) {
+                        g->lookahead_entries += look;
                         r.hit = 1;
                         r.t_end = sidx - 1;
                         r.sweeping = false;
@@ -1929,15 +2130,15 @@ louvain_status louvain_batch_run(louvain_batch_t b, const louvain_params *p, int
             HIPCHK(g, hipMemcpyAsync(b->keep_d, keep.data(), ng * sizeof(int32_t), hipMemcpyHostToDevice, g->st));
             {
                 ProfScope ps(g, PR_COMMIT, 8.0 * (double)g->cur.n, 0);
-                lv::commit_graphs(g->cur.n, g->comm_prev, g->comm_next, g->k, g->a, g->size, b->gid, b->keep_d,
-                                  g->st);
+                lv::commit_graphs(g->cur.n, g->comm_prev, g->comm_next, g->comm_save, g->k, g->a, g->size, b->gid,
+                                  b->keep_d, g->st);
                 g->singleton = false;
             }
             if (any_keep) {
                 std::vector<i128> s2;
                 if ((s = batch_sums(b, g->a, false, s2, nullptr, nullptr))) return s;
                 for (int32_t i = 0; i < ng; ++i)
-                    if (keep[i]) b->runs[i].S2[sidx] = s2[i];
+                    if (keep[i] == 1) b->runs[i].S2[sidx] = s2[i];
             }
             bool still = false;
             for (int32_t i = 0; i < ng; ++i) {
@@ -1967,7 +2168,8 @@ louvain_status louvain_batch_run(louvain_batch_t b, const louvain_params *p, int
             louvain_phase_stats &ph = r.phases.back();
             ph.iterations = r.t_end;
             ph.hit_max_iter = r.hit;
-            const i128 Np = r.Nt[r.t_end];
+            ph.loss_undone = r.undone;
+            const i128 Np = r.undone ? r.Nt[r.t_end - 1] : r.Nt[r.t_end];
             ph.q_num = to_abi(Np);
             const int64_t n_after = b->goff[i + 1] - b->goff[i];
             const i128 D = (i128)b->two_m[i] * b->two_m[i];

@@ -160,19 +160,29 @@ void graph_sums(const Csr &g, bool with_self, const int64_t *x, const int32_t *g
     }
 }
 
-// commits the moves of graphs with keep[g] != 0; other graphs drop the
-// sweep's proposals (comm_next reset to comm_prev)
+// per graph g, by mode[g]: 1 commits the sweep's moves and keeps the
+// partition they replace in comm_save; 2 undoes the last committed iteration
+// (every vertex back to comm_save, Sec. 5.1: a loss ends the phase and is not
+// kept); 0 drops the sweep's proposals (comm_next reset to comm_prev)
 __global__ __launch_bounds__(BLOCK) void k_commit_graphs(int64_t n, int32_t *comm_prev, int32_t *comm_next,
-                                                         const int64_t *k, int64_t *a, int32_t *size,
-                                                         const int32_t *gid, const int32_t *keep)
+                                                         int32_t *comm_save, const int64_t *k, int64_t *a,
+                                                         int32_t *size, const int32_t *gid, const int32_t *mode)
 {
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
-        const int32_t A = comm_prev[i], B = comm_next[i];
-        if (A == B) continue;
-        if (!keep[gid[i]]) {
-            comm_next[i] = A;
+        const int32_t m = mode[gid[i]];
+        const int32_t A = comm_prev[i];
+        int32_t B;
+        if (m == 1) {
+            B = comm_next[i];
+            comm_save[i] = A;
+        } else if (m == 2) {
+            B = comm_save[i];
+            if (comm_next[i] != B) comm_next[i] = B;
+        } else {
+            if (comm_next[i] != A) comm_next[i] = A;
             continue;
         }
+        if (A == B) continue;
         const int64_t ki = k[i];
         atomicAdd((unsigned long long *)&a[A], (unsigned long long)(-ki));
         atomicAdd((unsigned long long *)&a[B], (unsigned long long)ki);
@@ -182,13 +192,13 @@ __global__ __launch_bounds__(BLOCK) void k_commit_graphs(int64_t n, int32_t *com
     }
 }
 
-void commit_graphs(int64_t n, int32_t *comm_prev, int32_t *comm_next, const int64_t *k, int64_t *a, int32_t *size,
-                   const int32_t *gid, const int32_t *keep, hipStream_t st)
+void commit_graphs(int64_t n, int32_t *comm_prev, int32_t *comm_next, int32_t *comm_save, const int64_t *k,
+                   int64_t *a, int32_t *size, const int32_t *gid, const int32_t *mode, hipStream_t st)
 {
     if (n <= 0) return;
     unsigned gc = grid_for(n, BLOCK * 4);
     if (gc > 65536) gc = 65536;
-    k_commit_graphs<<<gc, BLOCK, 0, st>>>(n, comm_prev, comm_next, k, a, size, gid, keep);
+    k_commit_graphs<<<gc, BLOCK, 0, st>>>(n, comm_prev, comm_next, comm_save, k, a, size, gid, mode);
 }
 
 // graph boundaries after a rebuild: new_goff[g] = new id of the first vertex

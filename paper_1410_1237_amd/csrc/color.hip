@@ -20,6 +20,8 @@
 // counts the next frontier into slot r+1 and clears slot r+2.
 #include "lv.h"
 
+#include <vector>
+
 namespace lv {
 
 constexpr int64_t JP_LIGHT = 256;         // rows up to this length: one wavefront per vertex
@@ -321,8 +323,10 @@ int32_t color_jp(const Csr &g, uint64_t seed, const ColorBufs &c, Scratch &s, hi
             k_jp_final<<<JP_FINAL_BLOCKS, BLOCK, 0, st>>>(g, seed, in.lng, ring, r, c.color, c.long_id, c.bm);
         }
         int32_t nf[3] = {0, 0, 0};
-        hipMemcpyAsync(nf, ring + 3 * (r % JP_RING), 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st);
-        hipStreamSynchronize(st);
+        if (hipMemcpyAsync(nf, ring + 3 * (r % JP_RING), 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return -1;
         if (nf[0] == 0 && nf[1] == 0 && nf[2] == 0) break;
         if (batch < 256) batch *= 2;
     }
@@ -330,9 +334,190 @@ int32_t color_jp(const Csr &g, uint64_t seed, const ColorBufs &c, Scratch &s, hi
     fill<int32_t>(mx_slot, -1, 1, st);
     k_color_max<<<gv, BLOCK, 0, st>>>(c.color, g.n, mx_slot);
     int32_t mx = -1;
-    hipMemcpyAsync(&mx, mx_slot, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-    hipStreamSynchronize(st);
+    if (read_back(&mx, mx_slot, st) != hipSuccess) return -1;
     return mx + 1;
+}
+
+} // namespace lv
+
+namespace lv {
+
+// ---- balanced colouring ---------------------------------------------------------
+// Class-size equalisation of the greedy colouring (Sec. 6.2 finds skewed
+// colour classes costly and leaves balanced sets to future work).  With chi
+// colours on n vertices the target is gamma = ceil(n / chi).  Over-full
+// classes (more than gamma vertices) are taken in ascending colour c; a vertex
+// of K_c may go to a colour c' != c that none of its neighbours has and whose
+// class holds fewer than gamma vertices (K_c is independent, so this does not
+// change while K_c is handled).  In rounds, every waiting vertex of K_c
+// proposes its smallest admissible colour (one with none stops waiting); each
+// c' takes its proposers in descending priority, at most gamma - |K_c'|; of all
+// taken, the first |K_c| - gamma in descending priority move.  K_c is done at
+// gamma or after a round that moves nobody.  Every step is a kernel; the host
+// keeps the class sizes (chi values) between rounds.
+
+constexpr int BAL_WORDS = 64; // colour bitmap words: up to 4096 colours
+
+__global__ __launch_bounds__(BLOCK) void k_bal_prio_keys(int64_t n, uint64_t seed, uint64_t *keys, int64_t *vals)
+{
+    for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK) {
+        keys[v] = ~jp_priority(seed, v); // ascending order = descending priority
+        vals[v] = v;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_bal_color_keys(int64_t n, const int64_t *vals, const int32_t *color,
+                                                          uint64_t *keys, int32_t *size)
+{
+    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < n; p += (int64_t)gridDim.x * BLOCK) {
+        const int32_t c = color[vals[p]];
+        keys[p] = (uint64_t)c;
+        atomicAdd(&size[c], 1);
+    }
+}
+
+// one workgroup per waiting vertex of the class: its neighbours' colours into
+// an LDS bitmap over the closed colours, then the smallest free colour
+__global__ __launch_bounds__(BLOCK) void k_bal_propose(Csr g, const int32_t *list, int64_t count,
+                                                       const int32_t *color, const unsigned long long *closed,
+                                                       int32_t ncolors, int32_t *waiting, int32_t *prop)
+{
+    __shared__ unsigned long long s_bm[BAL_WORDS];
+    __shared__ int32_t s_first;
+    const int words = (ncolors + 63) / 64;
+    for (int64_t p = blockIdx.x; p < count; p += gridDim.x) {
+        if (!waiting[p]) { // block-uniform
+            if (threadIdx.x == 0) prop[p] = -1;
+            continue;
+        }
+        const int32_t v = list[p];
+        for (int k = threadIdx.x; k < words; k += BLOCK) s_bm[k] = closed[k];
+        if (threadIdx.x == 0) s_first = ncolors;
+        __syncthreads();
+        for (int64_t e = g.off[v] + threadIdx.x; e < g.off[v + 1]; e += BLOCK) {
+            const int32_t u = g.col[e];
+            if (u != v) {
+                const int32_t cu = color[u];
+                atomicOr(&s_bm[cu >> 6], 1ull << (cu & 63));
+            }
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < words; k += BLOCK) {
+            unsigned long long free_bits = ~s_bm[k];
+            const int top = ncolors - 64 * k; // colours of this word that exist
+            if (top < 64) free_bits &= (1ull << top) - 1;
+            if (free_bits) atomicMin(&s_first, 64 * k + __ffsll((long long)free_bits) - 1);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int32_t d = s_first < ncolors ? s_first : -1;
+            prop[p] = d;
+            if (d < 0) waiting[p] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_bal_rank_keys(const int32_t *prop, int64_t count, uint64_t *keys,
+                                                         int64_t *vals, int32_t *taken)
+{
+    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < count; p += (int64_t)gridDim.x * BLOCK) {
+        keys[p] = (uint64_t)(prop[p] + 1); // 0: no proposal
+        vals[p] = p;
+        taken[p] = 0;
+    }
+}
+
+// proposers grouped by colour (stable: positions ascend = priority descends)
+// are taken while their rank is below the colour's room gamma - |K_c'|
+__global__ __launch_bounds__(BLOCK) void k_bal_take(const uint64_t *keys, const int64_t *vals, int64_t count,
+                                                    const int64_t *first, const int32_t *size, int64_t gamma,
+                                                    int32_t *taken)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < count; i += (int64_t)gridDim.x * BLOCK) {
+        const uint64_t key = keys[i];
+        if (key == 0) continue;
+        const int64_t rank = i - first[key];
+        if (rank < gamma - size[key - 1]) taken[vals[i]] = 1;
+    }
+}
+
+// the first `room` taken vertices in priority order move
+__global__ __launch_bounds__(BLOCK) void k_bal_apply(const int32_t *list, int64_t count, const int32_t *taken,
+                                                     const int32_t *before, int64_t room, const int32_t *prop,
+                                                     int32_t c, int32_t *color, int32_t *size, int32_t *waiting)
+{
+    for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < count; p += (int64_t)gridDim.x * BLOCK) {
+        if (!taken[p] || before[p] >= room) continue;
+        const int32_t d = prop[p];
+        color[list[p]] = d;
+        atomicAdd(&size[d], 1);
+        atomicSub(&size[c], 1);
+        waiting[p] = 0;
+    }
+}
+
+int64_t color_balance(const Csr &g, uint64_t seed, int32_t ncolors, const BalanceBufs &b, Scratch &s, hipStream_t st)
+{
+    const int64_t n = g.n;
+    if (n < 2 || ncolors < 2) return 0;
+    if (ncolors > BAL_WORDS * 64) return -2;
+    const int64_t gamma = (n + ncolors - 1) / ncolors;
+    unsigned gv = grid_for(n, BLOCK * 4);
+    if (gv > 65536) gv = 65536;
+    // vertices by colour, descending priority within each class
+    k_bal_prio_keys<<<gv, BLOCK, 0, st>>>(n, seed, b.keys, b.vals);
+    radix_sort(b.keys, b.keys_alt, b.vals, b.vals_alt, n, 64, s, st);
+    fill<int32_t>(b.size, 0, ncolors, st);
+    k_bal_color_keys<<<gv, BLOCK, 0, st>>>(n, b.vals, b.color, b.keys, b.size);
+    int cbits = 1;
+    while ((1 << cbits) < ncolors) ++cbits;
+    radix_sort(b.keys, b.keys_alt, b.vals, b.vals_alt, n, cbits, s, st);
+    narrow_ids(b.vals, b.list, n, st);
+    key_offsets(b.keys, n, ncolors, b.first, st);
+    std::vector<int64_t> start(ncolors + 1);
+    std::vector<int32_t> size(ncolors);
+    if (hipMemcpyAsync(start.data(), b.first, (ncolors + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(size.data(), b.size, ncolors * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return -1;
+    int rbits = 1;
+    while ((1 << rbits) < ncolors + 1) ++rbits;
+    std::vector<unsigned long long> closed(BAL_WORDS);
+    int64_t moved_total = 0;
+    for (int32_t c = 0; c < ncolors; ++c) {
+        if (size[c] <= gamma) continue;
+        const int64_t count = size[c]; // K_c has not changed since the grouping
+        const int32_t *list = b.list + start[c];
+        fill<int32_t>(b.waiting, 1, count, st);
+        const unsigned gc = grid_for(count, BLOCK * 4) > 65536 ? 65536 : grid_for(count, BLOCK * 4);
+        const unsigned gp = count < 8192 ? (unsigned)count : 8192;
+        while (size[c] > gamma) {
+            for (auto &w : closed) w = 0;
+            for (int32_t d = 0; d < ncolors; ++d)
+                if (d == c || size[d] >= gamma) closed[d >> 6] |= 1ull << (d & 63);
+            if (hipMemcpyAsync(b.closed, closed.data(), BAL_WORDS * sizeof(unsigned long long), hipMemcpyHostToDevice,
+                               st) != hipSuccess)
+                return -1;
+            k_bal_propose<<<gp, BLOCK, 0, st>>>(g, list, count, b.color, b.closed, ncolors, b.waiting, b.prop);
+            k_bal_rank_keys<<<gc, BLOCK, 0, st>>>(b.prop, count, b.keys, b.vals, b.taken);
+            radix_sort(b.keys, b.keys_alt, b.vals, b.vals_alt, count, rbits, s, st);
+            key_offsets(b.keys, count, ncolors + 1, b.first, st);
+            k_bal_take<<<gc, BLOCK, 0, st>>>(b.keys, b.vals, count, b.first, b.size, gamma, b.taken);
+            scan_i32_to_i32(b.taken, b.before, count, nullptr, s, st);
+            k_bal_apply<<<gc, BLOCK, 0, st>>>(list, count, b.taken, b.before, size[c] - gamma, b.prop, c, b.color,
+                                              b.size, b.waiting);
+            const int32_t was = size[c];
+            if (hipMemcpyAsync(size.data(), b.size, ncolors * sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
+                    hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return -1;
+            if (size[c] == was) break;
+            moved_total += was - size[c];
+        }
+    }
+    return moved_total;
 }
 
 } // namespace lv

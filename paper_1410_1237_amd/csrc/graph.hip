@@ -321,6 +321,74 @@ void vf_map(const Csr &g, int32_t *map, hipStream_t st)
     k_vf<<<gv, BLOCK, 0, st>>>(g.off, g.col, g.n, map);
 }
 
+// the one neighbour j != i of row i and its weight, if the row holds exactly
+// one besides an optional self-loop (rows are sorted and have no repeats, so
+// such a row has one or two entries)
+template <int WK>
+__device__ __forceinline__ bool one_neighbour(const Csr &g, int64_t i, int32_t &j, int64_t &w)
+{
+    const int64_t b = g.off[i], len = g.off[i + 1] - b;
+    if (len == 1) {
+        j = g.col[b];
+        w = WLoad<WK>::at(g.w, b);
+        return j != i;
+    }
+    if (len == 2) {
+        const int32_t c0 = g.col[b], c1 = g.col[b + 1];
+        if (c0 == i || c1 == i) {
+            const int64_t e = c0 == i ? b + 1 : b;
+            j = g.col[e];
+            w = WLoad<WK>::at(g.w, e);
+            return true;
+        }
+    }
+    return false;
+}
+
+// one round of chain-compressing vertex following (the extension closing
+// Sec. 5.3): i qualifies when it has a single neighbour j and the bound of
+// Lemma 3's proof is positive, 2m * w_ij > k_i * k_j (the gain of moving i
+// into j's one-vertex community, Eq. 4, exact in 128 bits); it then follows j,
+// or the smaller id of the two when j qualifies as well (they only see each
+// other).  2m is the graph's own (g_two_m[gid[i]] in a batch).  Counter 0 of
+// rep gets the vertices that follow another.
+template <int WK>
+__global__ __launch_bounds__(BLOCK) void k_vf_chain(Csr g, const int64_t *k, int64_t two_m, const int32_t *gid,
+                                                    const int64_t *g_two_m, int32_t *map, int64_t *rep)
+{
+    __shared__ int64_t s_red[BLOCK / 64];
+    int64_t moved = 0;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < g.n; i += (int64_t)gridDim.x * BLOCK) {
+        int32_t m = (int32_t)i, j, jj;
+        int64_t w, wj;
+        const int64_t tm = gid ? g_two_m[gid[i]] : two_m;
+        if (one_neighbour<WK>(g, i, j, w) && (__int128)tm * w > (__int128)k[i] * k[j]) {
+            m = j;
+            if (one_neighbour<WK>(g, j, jj, wj) && (__int128)tm * wj > (__int128)k[j] * k[i]) m = min((int32_t)i, j);
+        }
+        map[i] = m;
+        moved += m != i;
+    }
+    moved = block_total(moved, s_red);
+    if (threadIdx.x == 0) rep_add(rep, 0, moved);
+}
+
+void vf_chain_map(const Csr &g, const int64_t *k, int64_t two_m, const int32_t *gid, const int64_t *g_two_m,
+                  int32_t *map, int64_t *moved, Scratch &s, hipStream_t st)
+{
+    rep_clear(s.rep, st);
+    if (g.n > 0) {
+        unsigned gv = grid_for(g.n, BLOCK * 4);
+        if (gv > 65536) gv = 65536;
+        switch (g.wk) {
+        case W_UNIT: k_vf_chain<W_UNIT><<<gv, BLOCK, 0, st>>>(g, k, two_m, gid, g_two_m, map, s.rep); break;
+        case W_I32: k_vf_chain<W_I32><<<gv, BLOCK, 0, st>>>(g, k, two_m, gid, g_two_m, map, s.rep); break;
+        default: k_vf_chain<W_I64><<<gv, BLOCK, 0, st>>>(g, k, two_m, gid, g_two_m, map, s.rep); break;
+        }
+    }
+    rep_fold(s.rep, 1, moved, st);
+}
+
 // ---- coarsening ---------------------------------------------------------------------
 __global__ __launch_bounds__(BLOCK) void k_mark(const int32_t *comm, int64_t n, int32_t *flag)
 {
@@ -430,9 +498,9 @@ static int bits_for(int64_t n)
     return b;
 }
 
-void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_orig, CoarsenBufs &b,
-             int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *k_out, int64_t *stats, int64_t *n_new,
-             int64_t *nnz_new, Scratch &s, hipStream_t st)
+hipError_t coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_orig, CoarsenBufs &b,
+                   int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *k_out, int64_t *stats, int64_t *n_new,
+                   int64_t *nnz_new, Scratch &s, hipStream_t st)
 {
     fill<int64_t>(stats, 0, 3, st);
     const int64_t n = g.n, nnz = g.nnz;
@@ -443,8 +511,7 @@ void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_ori
     if (n > 0) k_mark<<<gv, BLOCK, 0, st>>>(comm, n, b.flag);
     scan_i32_to_i32(b.flag, b.new_id, n, s.scalar, s, st);
     int64_t nn = 0;
-    hipMemcpyAsync(&nn, s.scalar, sizeof(int64_t), hipMemcpyDeviceToHost, st);
-    hipStreamSynchronize(st);
+    if (const hipError_t e = read_back(&nn, s.scalar, st)) return e;
     unsigned gx = grid_for(n_orig, BLOCK * 4);
     if (gx > 65536) gx = 65536;
     if (n_orig > 0) k_compose<<<gx, BLOCK, 0, st>>>(orig_map, n_orig, comm, b.new_id);
@@ -453,7 +520,7 @@ void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_ori
         fill<int64_t>(off_out, 0, nn + 1, st);
         fill<int64_t>(k_out, 0, nn, st);
         *nnz_new = 0;
-        return;
+        return hipGetLastError();
     }
     const int bits = bits_for(nn > 1 ? nn : 2);
     const bool hv = g.wk != W_UNIT;
@@ -468,8 +535,7 @@ void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_ori
     radix_sort(b.keys, b.keys_alt, hv ? b.vals : nullptr, b.vals_alt, nnz, 2 * bits, s, st);
     scan_heads(b.keys, b.run, nnz, s.scalar, s, st);
     int64_t nruns = 0;
-    hipMemcpyAsync(&nruns, s.scalar, sizeof(int64_t), hipMemcpyDeviceToHost, st);
-    hipStreamSynchronize(st);
+    if (const hipError_t e = read_back(&nruns, s.scalar, st)) return e;
     int64_t *rstart = b.vals_alt; // free after the sort; nnz + 1 entries
     unsigned gr = grid_for(nnz, BLOCK * 4);
     if (gr > 65536) gr = 65536;
@@ -498,27 +564,34 @@ void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_ori
         if (gm > 4096) gm = 4096;
         k_max<<<gm, BLOCK, 0, st>>>(k_out, nn, stats + 1);
     }
-    if (pref) hipMemcpyAsync(stats, pref + nnz, sizeof(int64_t), hipMemcpyDeviceToDevice, st);
-    else fill<int64_t>(stats, nnz, 1, st);
+    if (pref) {
+        if (const hipError_t e = hipMemcpyAsync(stats, pref + nnz, sizeof(int64_t), hipMemcpyDeviceToDevice, st))
+            return e;
+    } else {
+        fill<int64_t>(stats, nnz, 1, st);
+    }
     rep_fold(s.rep, 1, stats + 2, st);
+    return hipGetLastError();
 }
 
 // ---- rebuild after vertex following -------------------------------------------
 // Under a vertex-following map each community is one kept vertex u (a fixed
-// point of the map) with the vertices whose only entry leads to u, so the
+// point of the map) with the vertices whose only neighbour is u, so the
 // coarse row of u is u's row without the entries into its own community,
 // columns renumbered (the renumbering is monotone on the kept vertices, so
 // the row stays sorted), plus the self-loop that collects everything inside
-// the community: w_uu once and every edge to an absorbed vertex twice (both
-// of its directions lie inside).  Entry tags in A: >= 0 the coarse column,
-// else one of the following.
+// the community: w_uu and the absorbed vertices' self-loops once, every edge
+// to an absorbed vertex twice (both of its directions lie inside).  Entry
+// tags in A: >= 0 the coarse column, else one of the following.
 constexpr int32_t VF_INSIDE = -1; // entry to a vertex the row's vertex absorbs
 constexpr int32_t VF_DROP = -2;   // entry of an absorbed vertex's row
 constexpr int32_t VF_SELF = -3;   // the row's own self-loop
 
+// wself[u]: u's own self-loop; aself[u]: the absorbed vertices' self-loops
+// (zero unless a chain round absorbs vertices that carry one)
 template <int WK>
 __global__ __launch_bounds__(BLOCK) void k_vf_entries(Csr g, const int32_t *map, const int32_t *cmap, int32_t *A,
-                                                      int64_t *wself)
+                                                      int64_t *wself, int64_t *aself)
 {
     __shared__ int64_t s_off[ROWCAP + 1];
     __shared__ int64_t s_meta[2];
@@ -529,11 +602,13 @@ __global__ __launch_bounds__(BLOCK) void k_vf_entries(Csr g, const int32_t *map,
         const int64_t e = e0 + r * BLOCK + threadIdx.x;
         if (e > e1) break;
         const int64_t u = tile_row(t, g.off, s_off, e);
+        const int32_t v = g.col[e];
         if (map[u] != u) {
             A[e] = VF_DROP;
+            if (v == u)
+                atomicAdd((unsigned long long *)&aself[map[u]], (unsigned long long)WLoad<WK>::at(g.w, e));
             continue;
         }
-        const int32_t v = g.col[e];
         if (v == u) {
             A[e] = VF_SELF;
             wself[u] = WLoad<WK>::at(g.w, e);
@@ -545,21 +620,25 @@ __global__ __launch_bounds__(BLOCK) void k_vf_entries(Csr g, const int32_t *map,
 }
 
 // entries of each coarse row (turned into offsets by a scan) and the
-// community degree k_u + the weight of u's edges to the vertices it absorbs
-// (their degrees); run / pin: exclusive prefix counts of the kept entries and
-// prefix sums of the inside entries' weights, nnz + 1 entries each
+// community degree k_u + the weight of u's edges to the vertices it absorbs +
+// their self-loops (the absorbed degrees); run / pin: exclusive prefix counts
+// of the kept entries and prefix sums of the inside entries' weights, nnz + 1
+// entries each.  kt holds the absorbed self-loops (aself) on entry; wself[u]
+// becomes everything but the inside edges of the community's self-loop.
 __global__ __launch_bounds__(BLOCK) void k_vf_rows(const int64_t *off, int64_t n, const int32_t *map,
                                                    const int32_t *cmap, const int64_t *run, const int64_t *pin,
-                                                   const int64_t *wself, const int64_t *k_in, int64_t *cnt_out,
+                                                   int64_t *wself, const int64_t *k_in, int64_t *cnt_out,
                                                    int64_t *kt)
 {
     for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < n; u += (int64_t)gridDim.x * BLOCK) {
         if (map[u] != u) continue;
         const int64_t b = off[u], e = off[u + 1];
         const int64_t inside = pin[e] - pin[b];
+        const int64_t as = kt[u];
+        if (as) wself[u] += as;
         const int64_t self = wself[u] + 2 * inside;
         cnt_out[cmap[u]] = run[e] - run[b] + (self > 0 ? 1 : 0);
-        kt[u] = k_in[u] + inside;
+        kt[u] = k_in[u] + inside + as;
     }
 }
 
@@ -627,9 +706,9 @@ __global__ __launch_bounds__(BLOCK) void k_vf_self(const int64_t *off, const int
     }
 }
 
-void coarsen_vf(const Csr &g, const int32_t *map, const int64_t *k_in, int32_t *orig_map, int64_t n_orig,
-                CoarsenBufs &b, int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *k_out, int64_t *stats,
-                int64_t *n_new, int64_t *nnz_new, Scratch &s, hipStream_t st)
+hipError_t coarsen_vf(const Csr &g, const int32_t *map, const int64_t *k_in, int32_t *orig_map, int64_t n_orig,
+                      CoarsenBufs &b, int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *k_out,
+                      int64_t *stats, int64_t *n_new, int64_t *nnz_new, Scratch &s, hipStream_t st)
 {
     fill<int64_t>(stats, 0, 3, st);
     const int64_t n = g.n, nnz = g.nnz;
@@ -640,8 +719,7 @@ void coarsen_vf(const Csr &g, const int32_t *map, const int64_t *k_in, int32_t *
     if (n > 0) k_mark<<<gv, BLOCK, 0, st>>>(map, n, b.flag);
     scan_i32_to_i32(b.flag, b.new_id, n, s.scalar, s, st);
     int64_t nn = 0;
-    hipMemcpyAsync(&nn, s.scalar, sizeof(int64_t), hipMemcpyDeviceToHost, st);
-    hipStreamSynchronize(st);
+    if (const hipError_t e = read_back(&nn, s.scalar, st)) return e;
     unsigned gx = grid_for(n_orig, BLOCK * 4);
     if (gx > 65536) gx = 65536;
     if (n_orig > 0) k_compose<<<gx, BLOCK, 0, st>>>(orig_map, n_orig, map, b.new_id);
@@ -650,25 +728,26 @@ void coarsen_vf(const Csr &g, const int32_t *map, const int64_t *k_in, int32_t *
         fill<int64_t>(off_out, 0, nn + 1, st);
         fill<int64_t>(k_out, 0, nn, st);
         *nnz_new = 0;
-        return;
+        return hipGetLastError();
     }
     int32_t *cmap = b.flag; // free after the renumbering scan
     k_cmap<<<gv, BLOCK, 0, st>>>(map, b.new_id, n, cmap);
     int32_t *A = (int32_t *)b.keys;
     int64_t *run = b.vals_alt, *pin = b.vals, *wself = b.run, *kt = (int64_t *)b.keys_alt;
     fill<int64_t>(wself, 0, n, st);
+    fill<int64_t>(kt, 0, n, st); // absorbed self-loops first, then the community degrees
     const unsigned ge = grid_for(nnz, ETILE);
     switch (g.wk) {
-    case W_UNIT: k_vf_entries<W_UNIT><<<ge, BLOCK, 0, st>>>(g, map, cmap, A, wself); break;
-    case W_I32: k_vf_entries<W_I32><<<ge, BLOCK, 0, st>>>(g, map, cmap, A, wself); break;
-    default: k_vf_entries<W_I64><<<ge, BLOCK, 0, st>>>(g, map, cmap, A, wself); break;
+    case W_UNIT: k_vf_entries<W_UNIT><<<ge, BLOCK, 0, st>>>(g, map, cmap, A, wself, kt); break;
+    case W_I32: k_vf_entries<W_I32><<<ge, BLOCK, 0, st>>>(g, map, cmap, A, wself, kt); break;
+    default: k_vf_entries<W_I64><<<ge, BLOCK, 0, st>>>(g, map, cmap, A, wself, kt); break;
     }
     scan_nonneg(A, run, nnz, run + nnz, s, st);
     scan_tagged_weights(A, VF_INSIDE, g.w, g.wk, pin, nnz, pin + nnz, s, st);
     k_vf_rows<<<gv, BLOCK, 0, st>>>(g.off, n, map, cmap, run, pin, wself, k_in, off_out, kt);
     scan_i64(off_out, off_out, nn, off_out + nn, s, st); // in place; the total is nnz'
     int64_t tot = 0;
-    hipMemcpyAsync(&tot, off_out + nn, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    if (const hipError_t e = hipMemcpyAsync(&tot, off_out + nn, sizeof(int64_t), hipMemcpyDeviceToHost, st)) return e;
     switch (g.wk) {
     case W_UNIT: k_vf_write<W_UNIT><<<ge, BLOCK, 0, st>>>(g, cmap, A, run, pin, wself, off_out, col_out, w_out); break;
     case W_I32: k_vf_write<W_I32><<<ge, BLOCK, 0, st>>>(g, cmap, A, run, pin, wself, off_out, col_out, w_out); break;
@@ -683,8 +762,9 @@ void coarsen_vf(const Csr &g, const int32_t *map, const int64_t *k_in, int32_t *
         if (gm > 4096) gm = 4096;
         k_max<<<gm, BLOCK, 0, st>>>(k_out, nn, stats + 1);
     }
-    hipStreamSynchronize(st);
+    if (const hipError_t e = hipStreamSynchronize(st)) return e;
     *nnz_new = tot;
+    return hipGetLastError();
 }
 
 template <int WK>

@@ -153,6 +153,15 @@ void radix_sort(uint64_t *keys, uint64_t *keys_alt, int64_t *vals, int64_t *vals
 int64_t radix_partials_needed(int64_t n);
 
 template <typename T> void fill(T *p, T v, int64_t n, hipStream_t st);
+
+// one device value copied to the host after the work queued before it: the
+// first error of the copy or of the wait
+template <typename T> hipError_t read_back(T *host, const T *dev, hipStream_t st)
+{
+    hipError_t e = hipMemcpyAsync(host, dev, sizeof(T), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+}
 void iota_i32(int32_t *p, int64_t n, hipStream_t st);
 
 // ---- graph kernels (graph.hip) -------------------------------------------
@@ -185,13 +194,15 @@ struct CoarsenBufs {
 // the same rebuild for a vertex-following map (every community is one kept
 // vertex and vertices whose only entry leads to it), by compaction of the
 // kept rows instead of a sort; k_in: degrees of g (read before k_out is
-// written, so k_out may alias it)
-void coarsen_vf(const Csr &g, const int32_t *map, const int64_t *k_in, int32_t *orig_map, int64_t n_orig,
-                CoarsenBufs &b, int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *k_out, int64_t *stats,
-                int64_t *n_new, int64_t *nnz_new, Scratch &s, hipStream_t st);
-void coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_orig, CoarsenBufs &b,
-             int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *k_out, int64_t *stats, int64_t *n_new,
-             int64_t *nnz_new, Scratch &s, hipStream_t st);
+// written, so k_out may alias it).  Both return the first error of a copy to
+// the host or a wait on the stream (the sizes they read decide the launches
+// that follow, so nothing is launched past such an error).
+hipError_t coarsen_vf(const Csr &g, const int32_t *map, const int64_t *k_in, int32_t *orig_map, int64_t n_orig,
+                      CoarsenBufs &b, int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *k_out,
+                      int64_t *stats, int64_t *n_new, int64_t *nnz_new, Scratch &s, hipStream_t st);
+hipError_t coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_orig, CoarsenBufs &b,
+                   int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *k_out, int64_t *stats, int64_t *n_new,
+                   int64_t *nnz_new, Scratch &s, hipStream_t st);
 // expands weights of g to int64
 void weights_i64(const Csr &g, int64_t *w_out, hipStream_t st);
 
@@ -371,8 +382,15 @@ void cross_edges(const Csr &g, const int32_t *gid, int32_t *flag, hipStream_t st
 // out[4g..4g+3]: sum x, sum x^2 (lo, hi), self-loop weight (if with_self)
 void graph_sums(const Csr &g, bool with_self, const int64_t *x, const int32_t *gid, int32_t ng, int64_t *out,
                 hipStream_t st);
-void commit_graphs(int64_t n, int32_t *comm_prev, int32_t *comm_next, const int64_t *k, int64_t *a, int32_t *size,
-                   const int32_t *gid, const int32_t *keep, hipStream_t st);
+// chain-compressing vertex following, one round: map[i] = the vertex i
+// follows (itself if none); *moved (device) = vertices that follow another.
+// gid/g_two_m (may be null): per-graph 2m of a batch
+void vf_chain_map(const Csr &g, const int64_t *k, int64_t two_m, const int32_t *gid, const int64_t *g_two_m,
+                  int32_t *map, int64_t *moved, Scratch &s, hipStream_t st);
+// per graph: mode 1 commits (keeping the replaced partition in comm_save),
+// 2 restores comm_save, 0 drops the proposals
+void commit_graphs(int64_t n, int32_t *comm_prev, int32_t *comm_next, int32_t *comm_save, const int64_t *k,
+                   int64_t *a, int32_t *size, const int32_t *gid, const int32_t *mode, hipStream_t st);
 void new_graph_offsets(const int64_t *goff, int32_t ng, int64_t n, const int32_t *new_id, int64_t total,
                        int64_t *new_goff, hipStream_t st);
 void local_labels(const int32_t *orig_map, const int32_t *gid0, int64_t n0, const int64_t *goff, int32_t *labels,
@@ -398,6 +416,22 @@ struct ColorBufs {
 int64_t color_bitmap_words(const Csr &g);
 int64_t color_chunk_pairs(const Csr &g);
 // Jones-Plassmann coloring; returns the number of colors (synchronizes)
+// returns the colour count, or -1 if a copy or wait of the stream failed
 int32_t color_jp(const Csr &g, uint64_t seed, const ColorBufs &c, Scratch &s, hipStream_t st);
+
+// buffers of the balanced colouring: color (in/out); list, waiting, prop,
+// taken, before int32[n]; size int32[ncolors]; closed u64[64]; the radix
+// sort's keys/vals pairs (n each); first int64[ncolors + 2]
+struct BalanceBufs {
+    int32_t *color, *list, *waiting, *prop, *taken, *before, *size;
+    unsigned long long *closed;
+    uint64_t *keys, *keys_alt;
+    int64_t *vals, *vals_alt, *first;
+};
+// balances the class sizes of a greedy colouring (color.hip); returns the
+// vertices moved, -1 if a copy or wait of the stream failed, -2 if ncolors
+// exceeds 4096
+int64_t color_balance(const Csr &g, uint64_t seed, int32_t ncolors, const BalanceBufs &b, Scratch &s,
+                      hipStream_t st);
 
 } // namespace lv

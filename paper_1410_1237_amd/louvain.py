@@ -45,7 +45,7 @@ class I128(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("vf", ctypes.c_int32), ("color", ctypes.c_int32), ("singlet_rule", ctypes.c_int32),
                 ("threshold_mode", ctypes.c_int32), ("color_first_phase_only", ctypes.c_int32),
-                ("max_iter", ctypes.c_int32), ("max_phases", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("max_phases", ctypes.c_int32), ("color_balance", ctypes.c_int32),
                 ("theta_color", Ratio), ("theta_final", Ratio), ("color_cutoff", ctypes.c_int64),
                 ("color_seed", ctypes.c_uint64)]
 
@@ -58,7 +58,7 @@ class IterStats(ctypes.Structure):
 class PhaseStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("colored", ctypes.c_int32),
                 ("num_colors", ctypes.c_int32), ("iterations", ctypes.c_int32), ("hit_max_iter", ctypes.c_int32),
-                ("first_iter", ctypes.c_int64), ("q_num", I128), ("ms_color", ctypes.c_double),
+                ("loss_undone", ctypes.c_int32), ("reserved", ctypes.c_int32), ("first_iter", ctypes.c_int64), ("q_num", I128), ("ms_color", ctypes.c_double),
                 ("ms_sweep", ctypes.c_double), ("ms_coarsen", ctypes.c_double)]
 
 
@@ -66,7 +66,7 @@ class Result(ctypes.Structure):
     _fields_ = [("n_orig", ctypes.c_int64), ("n_vf", ctypes.c_int64), ("num_communities", ctypes.c_int64),
                 ("phases", ctypes.c_int64), ("iterations", ctypes.c_int64), ("q_num", I128), ("q_den", I128),
                 ("q0_num", I128), ("q", ctypes.c_double), ("sweep_entries", ctypes.c_int64),
-                ("ms_total", ctypes.c_double), ("ms_vf", ctypes.c_double), ("ms_color", ctypes.c_double),
+                ("lookahead_entries", ctypes.c_int64), ("vf_rounds", ctypes.c_int64), ("ms_total", ctypes.c_double), ("ms_vf", ctypes.c_double), ("ms_color", ctypes.c_double),
                 ("ms_sweep", ctypes.c_double), ("ms_coarsen", ctypes.c_double),
                 ("phase", ctypes.POINTER(PhaseStats)), ("iter", ctypes.POINTER(IterStats))]
 
@@ -100,7 +100,8 @@ EXPORTS = ["louvain_params_default", "louvain_init_csr", "louvain_vf", "louvain_
            "louvain_server_config_default",
            "louvain_server_create", "louvain_server_submit", "louvain_server_submit_borrowed",
            "louvain_server_poll", "louvain_server_release",
-           "louvain_server_wait_all", "louvain_server_last_error", "louvain_server_destroy"]
+           "louvain_server_wait_all", "louvain_server_last_error", "louvain_server_destroy",
+           "louvain_vf_chain", "louvain_color_balance"]
 
 
 def lib():
@@ -110,6 +111,13 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1410_1237_amd.build`")
+    # torch ships its own HIP runtime under the same soname: load it first so
+    # that the library binds to that one instead of bringing a second runtime
+    # into the process (the second to initialise finds no device)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, u32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
     st = ctypes.c_int
@@ -119,8 +127,12 @@ def lib():
     L.louvain_init_csr.restype = st
     L.louvain_vf.argtypes = [vp, ctypes.POINTER(i64)]
     L.louvain_vf.restype = st
+    L.louvain_vf_chain.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.louvain_vf_chain.restype = st
     L.louvain_color.argtypes = [vp, u64, ctypes.POINTER(i32)]
     L.louvain_color.restype = st
+    L.louvain_color_balance.argtypes = [vp, u64, ctypes.POINTER(i64)]
+    L.louvain_color_balance.restype = st
     L.louvain_sweep.argtypes = [vp, ctypes.POINTER(Params), ctypes.POINTER(IterStats)]
     L.louvain_sweep.restype = st
     L.louvain_coarsen.argtypes = [vp, ctypes.POINTER(i64)]
@@ -191,7 +203,7 @@ def _check(status: int, handle=None):
 
 def params(**kw) -> Params:
     """louvain_params with the paper's defaults, overridden by keyword:
-    vf, color, singlet_rule, threshold_mode, color_first_phase_only, max_iter,
+    vf, color, color_balance, singlet_rule, threshold_mode, color_first_phase_only, max_iter,
     max_phases, theta_color=(num, den), theta_final=(num, den), color_cutoff,
     color_seed."""
     p = Params()
@@ -205,6 +217,8 @@ def params(**kw) -> Params:
 
 
 def _stream_ptr(stream) -> Optional[int]:
+    if stream == 0:
+        return None  # the null stream
     if stream is None:
         import torch
         if torch.cuda.is_available():
@@ -234,9 +248,23 @@ def louvain_vf(h) -> int:
     return out.value
 
 
+def louvain_vf_chain(h):
+    """Chain-compressing vertex following: (vertices after, rounds that merged)."""
+    out = ctypes.c_int64()
+    rounds = ctypes.c_int64()
+    _check(lib().louvain_vf_chain(h, ctypes.byref(out), ctypes.byref(rounds)), h)
+    return out.value, rounds.value
+
+
 def louvain_color(h, seed=DEFAULT_SEED) -> int:
     out = ctypes.c_int32()
     _check(lib().louvain_color(h, seed, ctypes.byref(out)), h)
+    return out.value
+
+
+def louvain_color_balance(h, seed=DEFAULT_SEED) -> int:
+    out = ctypes.c_int64()
+    _check(lib().louvain_color_balance(h, seed, ctypes.byref(out)), h)
     return out.value
 
 
@@ -284,6 +312,7 @@ class PhaseInfo:
     ms_color: float
     ms_sweep: float
     ms_coarsen: float
+    undone: bool = False
 
 
 @dataclass
@@ -302,6 +331,8 @@ class RunResult:
     ms_sweep: float
     ms_coarsen: float
     phases: List[PhaseInfo] = field(default_factory=list)
+    lookahead_entries: int = 0
+    vf_rounds: int = 0
 
 
 def _convert(res: Result, labels) -> RunResult:
@@ -315,11 +346,12 @@ def _convert(res: Result, labels) -> RunResult:
                                 moves=[it.moves for it in its], N_iter=[it.q_num.value() for it in its],
                                 N_end=ph.q_num.value(), pairs=[it.pairs for it in its],
                                 entries=[it.entries for it in its], ms_color=ph.ms_color,
-                                ms_sweep=ph.ms_sweep, ms_coarsen=ph.ms_coarsen))
+                                ms_sweep=ph.ms_sweep, ms_coarsen=ph.ms_coarsen, undone=bool(ph.loss_undone)))
     return RunResult(labels=labels, K=res.num_communities, N=res.q_num.value(), D=res.q_den.value(), q=res.q,
                      n_vf=res.n_vf, N0=res.q0_num.value(), sweep_entries=res.sweep_entries,
                      ms_total=res.ms_total, ms_vf=res.ms_vf, ms_color=res.ms_color, ms_sweep=res.ms_sweep,
-                     ms_coarsen=res.ms_coarsen, phases=phases)
+                     ms_coarsen=res.ms_coarsen, phases=phases, lookahead_entries=res.lookahead_entries,
+                     vf_rounds=res.vf_rounds)
 
 
 class Graph:
@@ -362,8 +394,14 @@ class Graph:
         self.close()
 
     # steps
+    def vf_chain(self):
+        return louvain_vf_chain(self.h)
+
     def vf(self) -> int:
         return louvain_vf(self.h)
+
+    def balance(self, seed: int = DEFAULT_SEED) -> int:
+        return louvain_color_balance(self.h, seed)
 
     def color(self, seed: int = DEFAULT_SEED) -> int:
         return louvain_color(self.h, seed)
@@ -577,7 +615,7 @@ class Batch:
                                             moves=[it.moves for it in its], N_iter=[it.q_num.value() for it in its],
                                             N_end=ph.q_num.value(), pairs=[it.pairs for it in its],
                                             entries=[it.entries for it in its], ms_color=0.0, ms_sweep=0.0,
-                                            ms_coarsen=0.0))
+                                            ms_coarsen=0.0, undone=bool(ph.loss_undone)))
             lab = out[self.goff[gi]:self.goff[gi + 1]].copy() if host else None
             results.append(RunResult(labels=lab, K=r.num_communities, N=r.q_num.value(), D=r.q_den.value(), q=r.q,
                                      n_vf=r.n_vf, N0=r.q0_num.value(), sweep_entries=0, ms_total=0.0, ms_vf=0.0,

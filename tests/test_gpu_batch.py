@@ -38,7 +38,7 @@ def mixed_graphs():
 
 
 PARAMS = [dict(), dict(vf=1), dict(singlet_rule=0), dict(max_iter=3, max_phases=2),
-          dict(threshold_mode=1, theta_final=(1, 10000))]
+          dict(threshold_mode=1, theta_final=(1, 10000)), dict(vf=2)]
 
 
 @pytest.mark.parametrize("pi", range(len(PARAMS)))

@@ -147,8 +147,8 @@ def compare_run(res, ref, tag=""):
     assert res.N0 == ref.N0 and res.n_vf == ref.n_vf, tag + ": first phase"
     assert len(res.phases) == len(ref.phases), tag + ": phases"
     for a, b in zip(res.phases, ref.phases):
-        assert (a.n, a.nnz, a.colored, a.num_colors, a.iterations, a.hit_max_iter) == \
-               (b.n, b.nnz, b.colored, b.ncolors, b.iterations, b.hit_max_iter), tag + ": phase shape"
+        assert (a.n, a.nnz, a.colored, a.num_colors, a.iterations, a.hit_max_iter, a.undone) == \
+               (b.n, b.nnz, b.colored, b.ncolors, b.iterations, b.hit_max_iter, b.undone), tag + ": phase shape"
         assert a.moves == b.moves, tag + ": moves"
         assert a.N_iter == b.N_iter, tag + ": per-iteration modularity"
         assert a.N_end == b.N_end, tag + ": phase modularity"
@@ -185,6 +185,126 @@ def test_run_medium(L, O, case):
         print(f"[run] {g.name} {d}", flush=True)
         with L.Graph.from_csr(g) as gs:
             res = gs.run(L.params(**d))
+        compare_run(res, O.run(g, oracle_params(d)), f"{g.name} {d}")
+
+
+STOP_RULE_CASES = [
+    # (vertices, edges, params): the hand-worked cases of the oracle's
+    # stop-rule and schedule pins (a loss undone at t = 2 and at t = 1,
+    # relative/absolute/strict thresholds, theta_color, cutoff, no-shrink)
+    (4, [(0, 1), (0, 2), (0, 3), (1, 2), (2, 3)], dict()),
+    (5, [(0, 1), (0, 4), (1, 2), (1, 3), (2, 4), (3, 4)], dict()),
+    (5, [(0, 1), (0, 4), (1, 2), (1, 3), (2, 4), (3, 4)], dict(theta_final=(0, 1))),
+    (5, [(0, 1), (0, 4), (1, 2), (1, 3), (2, 4), (3, 4)],
+     dict(color=1, color_cutoff=1, theta_color=(0, 1), theta_final=(0, 1))),
+    (5, [(0, 1), (0, 4), (1, 2), (1, 3), (2, 3), (2, 4)], dict(theta_final=(1, 2))),
+    (5, [(0, 1), (0, 4), (1, 2), (1, 3), (2, 3), (2, 4)], dict(theta_final=(1, 2), threshold_mode=1)),
+    (5, [(0, 1), (0, 4), (1, 2), (1, 3), (2, 3), (2, 4)], dict(theta_final=(14, 14))),
+    (5, [(0, 1), (0, 4), (1, 2), (1, 3), (2, 3), (2, 4)], dict(theta_final=(15, 14))),
+    (5, [(0, 2), (0, 3), (1, 2), (1, 3), (2, 3), (2, 4), (3, 4)], dict(color=1, color_cutoff=1, theta_color=(9, 10))),
+    (5, [(0, 2), (0, 3), (1, 2), (1, 3), (2, 3), (2, 4), (3, 4)], dict(color=1, color_cutoff=5, theta_color=(9, 10))),
+    (5, [(0, 2), (0, 3), (1, 2), (1, 3), (2, 3), (2, 4), (3, 4)], dict(color=1, color_cutoff=6, theta_color=(9, 10))),
+    (5, [(0, 2), (0, 3), (1, 2), (1, 3), (2, 3), (2, 4), (3, 4)],
+     dict(color=1, color_cutoff=1, color_first_phase_only=1)),
+    (10, [(0, 1), (0, 3), (1, 3), (4, 5), (4, 6), (5, 6), (0, 8), (0, 9), (8, 9), (2, 7)], dict(vf=1)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(STOP_RULE_CASES)))
+def test_run_stop_rule_cases(L, O, case):
+    n, edges, d = STOP_RULE_CASES[case]
+    g = SG.from_edges(n, edges)
+    res = L.Graph.from_csr(g).run(L.params(**d))
+    compare_run(res, O.run(g, oracle_params(d)), f"stop-rule case {case} {d}")
+
+
+def chain_graph(seed=9, n=3000):
+    """A sparse random graph with hanging paths of several lengths and some
+    self-loops, so that chain rounds merge, stop on the bound and repeat."""
+    rng = np.random.default_rng(seed)
+    edges, ws = set(), {}
+    core = n // 3
+    while len(edges) < 3 * core:
+        u, v = (int(x) for x in rng.integers(0, core, 2))
+        if u != v:
+            edges.add((min(u, v), max(u, v)))
+    nxt = core
+    while nxt < n:
+        length = int(rng.integers(1, 12))
+        prev = int(rng.integers(0, core))
+        for _ in range(length):
+            if nxt >= n:
+                break
+            edges.add((min(prev, nxt), max(prev, nxt)))
+            prev = nxt
+            nxt += 1
+    for v in rng.choice(n, size=n // 20, replace=False):
+        edges.add((int(v), int(v)))
+    edges = sorted(edges)
+    w = rng.integers(1, 9, size=len(edges))
+    return SG.from_edges(n, edges, w, name="chain_graph")
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_vf_chain_steps(L, O, case):
+    """Chain-compressing vertex following through the step call: the
+    rebuilt graph (CSR byte-equal), the composed map and the round count
+    equal the oracle's, then one phase of sweeps."""
+    g = [chain_graph(), chain_graph(seed=10, n=20000), SG.ring_of_cliques(6, 5), GG.rmat(12, 4, seed=3)][case]
+    gs = L.Graph.from_csr(g)
+    st = O.state(g)
+    n1, r1 = gs.vf_chain()
+    r2 = st.vf_chain()
+    assert (n1, r1) == (st.info()["n"], r2)
+    compare_graph(gs, st, "vf chain")
+    compare_state(gs, st, "vf chain")
+    p = L.params()
+    for t in range(4):
+        r = gs.sweep(p)
+        moves, N = st.iterate(1)
+        assert (r["moves"], r["N"]) == (moves, N)
+        compare_state(gs, st, f"iteration {t}")
+        if moves == 0:
+            break
+    gs.close()
+
+
+@pytest.mark.parametrize("d", [dict(vf=2), dict(vf=2, color=1, color_cutoff=1000)])
+def test_run_vf_chain(L, O, d):
+    for g in small_cases() + [chain_graph(), chain_graph(seed=10, n=20000), GG.rmat(13, 4, wmax=20, seed=4)]:
+        res = L.Graph.from_csr(g).run(L.params(**d))
+        ref = O.run(g, oracle_params(d))
+        compare_run(res, ref, f"{g.name} {d}")
+        assert res.vf_rounds == ref.vf_rounds
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_balanced_coloring_steps(L, O, case):
+    """Balanced colouring through the step call: the colours after balancing
+    and the moved count equal the oracle's, then the coloured sweeps."""
+    rng = np.random.default_rng(200 + case)
+    g = [SG.from_edges(10, [(0, 1), (0, 2), (1, 2)]), SG.random_graph(rng, 300, p=0.02, self_loops=0.1),
+         GG.rmat(12, 8, seed=5), hub_graph(), GG.rmat(14, 16, wmax=10, seed=7)][case]
+    gs = L.Graph.from_csr(g)
+    st = O.state(g)
+    assert gs.color() == st.color()
+    assert gs.balance() == st.balance()
+    assert np.array_equal(gs.colors(), st.get("color")), "balanced colours"
+    p = L.params(color=1)
+    for t in range(3):
+        r = gs.sweep(p)
+        moves, N = st.iterate(1)
+        assert (r["moves"], r["N"]) == (moves, N)
+        compare_state(gs, st, f"iteration {t}")
+        if moves == 0:
+            break
+    gs.close()
+
+
+def test_run_balanced_coloring(L, O):
+    d = dict(vf=1, color=1, color_cutoff=50, color_balance=1)
+    for g in small_cases() + [GG.rmat(12, 8, seed=5), hub_graph(), GG.sbm_1000()]:
+        res = L.Graph.from_csr(g).run(L.params(**d))
         compare_run(res, O.run(g, oracle_params(d)), f"{g.name} {d}")
 
 
@@ -262,7 +382,7 @@ def test_profiling_records(L):
     res = gs.run(L.params())
     recs = {r["name"]: r for r in gs.profile_records()}
     swept = sum(r["entries"] for n, r in recs.items() if n.startswith("sweep"))
-    assert swept == res.sweep_entries
+    assert swept == res.sweep_entries + res.lookahead_entries
     assert all(r["ms"] >= 0 for r in recs.values())
     gs.close()
 
