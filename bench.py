@@ -7,15 +7,19 @@ vertex following, Jones-Plassmann coloring of the early phases, the
 synchronous local-moving sweeps with community-degree updates and exact
 modularity, threshold cycling, and graph rebuilding between phases.
 
-Printed value: local-move GTEPS = CSR entries gathered by all sweeps of a
-step / wall time of the step (so coloring, rebuilding and ingest count
-against it); ms_per_step is the time to converge.  The roofline object is
-for the sweep kernel with the largest device time in the bandwidth run
-(plain synchronous sweeps over the same graph: no colour classes), from HIP
-events recorded by the library around every launch on its stream during an
-untimed step; roofline_timed_config gives the same for the timed
-configuration.  --form batched and --form served measure the batched and served
-forms (graphs/s; p50/p99 latency for the served form).
+Printed value: local-move GTEPS = CSR entries gathered by the sweeps of the
+iterations of a step (look-ahead sweeps that only measure Q are left out) /
+wall time of the step (so coloring, rebuilding and ingest count against it);
+ms_per_step is the time to converge with the CSR resident in HBM, and
+time_to_converge_incl_h2d_ms the same from the host CSR.  The roofline
+object is for the sweep kernel with the largest device time in the bandwidth
+run (plain synchronous sweeps over the same graph: no colour classes), from
+HIP events recorded by the library around every launch on its stream during
+an untimed step; roofline_timed_config gives the same for the timed
+configuration.  The same line carries the batched form (4,096 SBMs in one
+batched run, against one-at-a-time runs) and the served form (a job mix under
+Poisson arrivals: capacity, p50/p99 latency), each output checked against the
+oracle's stored results; --form batched and --form served print those alone.
 """
 from __future__ import annotations
 
@@ -77,36 +81,59 @@ def load_traffic(kernel, wl, mode):
         return None
 
 
-def cpu_baseline(g, seconds_target=15.0):
-    """The oracle's first synchronous sweep decisions on a prefix of the
-    vertices (all singletons), sized to about `seconds_target` of one core."""
+def cpu_info():
+    """The host CPU model (from /proc/cpuinfo) and its logical core count."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model or platform.processor() or platform.machine(), "nproc": os.cpu_count()}
+
+
+# sample graphs for the oracle's time to converge: the benched family at a
+# size the serial oracle finishes in seconds
+CPU_SAMPLES = {
+    "rmat_s24": ("rmat_scale(19, 3)", lambda G: G.rmat_scale(19, 3)),
+    "rmat_s20": ("rmat_scale(18, 2)", lambda G: G.rmat_scale(18, 2)),
+    "chunglu_8m": ("chung_lu(500000, 2.1, 12500, 1.25e7, 6250000, wmax=100, seed=4)",
+                   lambda G: G.chung_lu(500_000, 2.1, 12_500.0, 1.25e7, 6_250_000, wmax=100, seed=4)),
+    "sbm_n1000": ("sbm_1000()", lambda G: G.sbm_1000()),
+}
+
+
+def cpu_baseline(workload_name, heuristics):
+    """The serial oracle's time to converge, on one host core, on a smaller
+    graph of the benched family with the same heuristics; GTEPS on the
+    library's formula (CSR entries of every iteration's sweep / time).  The
+    oracle's time on the full benched graph, where its golden record holds
+    it, is reported beside it (measured when the golden was written)."""
     import oracle
+    from paper_1410_1237_amd import graphs as G
+    desc, make = CPU_SAMPLES[workload_name]
+    g = make(G)
     O = oracle.default()
     t0 = time.time()
-    st = O.state(g)
-    setup = time.time() - t0
-    # calibrate on a small prefix, then run the sample
-    lo, hi = 0, min(g.n, 2000)
-    t1 = time.time()
-    _, ent = st.decide_range(lo, hi)
-    dt = max(time.time() - t1, 1e-6)
-    rate = ent / dt if ent else 1e6
-    target_entries = rate * seconds_target
-    off = g.offsets
-    import numpy as np
-    end = int(np.searchsorted(off, off[hi] + target_entries, side="right")) - 1
-    end = max(hi + 1, min(end, g.n))
-    t2 = time.time()
-    _, ent2 = st.decide_range(hi, end)
-    dt2 = time.time() - t2
-    del st
-    return {
-        "value": round(ent2 / dt2 / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-        "sample": f"first synchronous sweep decisions of vertices [{hi}, {end}) from singletons "
-                  f"({ent2} CSR entries, {dt2:.1f} s on one host core, serial oracle; "
-                  f"state setup {setup:.1f} s not counted)",
-        "cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count(),
-    }
+    r = O.run(g, oracle.Params(**HEURISTICS[heuristics]))
+    dt = time.time() - t0
+    entries = sum(p.iterations * p.nnz for p in r.phases)
+    out = {"value": round(entries / dt / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+           "sample": f"serial oracle run to convergence on {desc} (n={g.n}, nnz={g.nnz}), heuristics "
+                     f"{heuristics}: {len(r.phases)} phases, {entries} CSR entries swept in {dt:.1f} s on one core",
+           "time_to_converge_s": round(dt, 2)}
+    golden = os.path.join(ROOT, "tests", "golden", f"{workload_name}_{heuristics}.json")
+    if os.path.exists(golden):
+        with open(golden) as f:
+            rec = json.load(f)
+        out["full_workload_time_to_converge_s"] = rec.get("oracle_seconds")
+        out["full_workload_note"] = ("the same oracle on the full benched graph, one core, measured when the "
+                                     "golden record was written (not in this run)")
+    out.update(cpu_info())
+    return out
 
 
 def _gen_many(fn, idx, threads):
@@ -143,9 +170,25 @@ def cpu_baseline_graphs(graphs, params, seconds_target=15.0):
         fin, _ = cf.wait(running)
         done += len(fin)
     dt = time.time() - t0
-    return {"value": round(done / dt, 2), "unit": "graphs/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} graphs of the same mix, serial oracle per graph, {threads} threads, {dt:.1f} s",
-            "cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
+    out = {"value": round(done / dt, 2), "unit": "graphs/s", "cores": threads, "kind": "oracle",
+           "sample": f"{done} graphs of the same mix, serial oracle per graph, {threads} threads, {dt:.1f} s"}
+    out.update(cpu_info())
+    return out
+
+
+def load_mix_golden(mix, count):
+    """Per-graph oracle records of a mix (tests/golden), keyed by graph index."""
+    path = os.path.join(ROOT, "tests", "golden", f"{mix}_x{count}_plain.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    return {r[0]: r for r in data["graphs"]}
+
+
+def labels_sha16(labels):
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(labels, dtype="<i4").tobytes()).hexdigest()[:16]
 
 
 def bench_batched(args):
@@ -206,6 +249,16 @@ def bench_batched(args):
     solo_gps = len(sample) / (time.perf_counter() - t1)
     for j, i in enumerate(sample):  # identical outputs (exact modularity, communities)
         assert (solo_res[j].N, solo_res[j].D, solo_res[j].K) == (res[i].N, res[i].D, res[i].K), f"graph {i}"
+    # every graph against the oracle's stored result (labels, K, exact Q)
+    gold = load_mix_golden("batch_sbm", len(gs))
+    checked = 0
+    if gold is not None:
+        lab = labels.cpu().numpy()
+        for i, r in enumerate(res):
+            rec = gold[i]
+            assert (r.K, str(r.N), str(r.D)) == (rec[3], rec[4], rec[5]), f"graph {i} differs from the oracle"
+            assert labels_sha16(lab[goff[i]:goff[i + 1]]) == rec[8], f"graph {i} labels differ from the oracle"
+            checked += 1
     sizes = np.array([g.n for g in gs])
     out = {
         "metric": "batched graphs/s", "value": round(gps, 2), "unit": "graphs/s", "n_gpus": 1,
@@ -218,10 +271,11 @@ def bench_batched(args):
                           "sample": f"{len(sample)} graphs (every {max(1, len(gs) // args.solo_sample)}th), "
                                     "sequential louvain_run on one stream, CSR resident",
                           "batched_over_one_at_a_time": round(gps / solo_gps, 2)},
+        "oracle_checked_graphs": checked,
         "roofline": None,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_graphs(gs, {}, args.cpu_seconds),
     }
-    print(json.dumps(out))
+    return out
 
 
 def bench_served(args):
@@ -257,7 +311,7 @@ def bench_served(args):
                 time.sleep(wait)
             tickets.append(s.submit(g, borrow=True))  # the job arrays outlive the server
         s.wait_all()
-        infos = [s.poll(tk, labels=False) for tk in tickets]
+        infos = [s.poll(tk, labels=True) for tk in tickets]
         s.close()
         assert all(i.status == L.OK for i in infos)
         lat = np.array([i.t_done - i.t_submit for i in infos])
@@ -280,6 +334,15 @@ def bench_served(args):
         h.close()
         assert (r.N, r.D, r.K) == (infos[j].N, infos[j].D, infos[j].K), f"job {j}"
     solo_gps = len(jobs) / (time.perf_counter() - t1)
+    # every job against the oracle's stored result (labels, K, exact Q)
+    gold = load_mix_golden("served", len(jobs))
+    checked = 0
+    if gold is not None:
+        for j, inf in enumerate(infos):
+            rec = gold[j]
+            assert (inf.K, str(inf.N), str(inf.D)) == (rec[3], rec[4], rec[5]), f"job {j} differs from the oracle"
+            assert labels_sha16(inf.labels) == rec[8], f"job {j} labels differ from the oracle"
+            checked += 1
     out = {
         "metric": "served graphs/s", "value": round(len(jobs) / span, 2), "unit": "graphs/s", "n_gpus": 1,
         "steps": 1, "warmup": 1, "ms_per_step": round(span * 1e3, 3), "higher_is_better": True,
@@ -303,10 +366,11 @@ def bench_served(args):
         "one_at_a_time": {"value": round(solo_gps, 2), "unit": "graphs/s",
                           "sample": f"all {len(jobs)} jobs, sequential louvain_init_csr (host CSR) + louvain_run",
                           "capacity_over_one_at_a_time": round(capacity / solo_gps, 2)},
+        "oracle_checked_jobs": checked,
         "roofline": None,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_graphs(jobs, {}, args.cpu_seconds),
     }
-    print(json.dumps(out))
+    return out
 
 
 def main():
@@ -319,6 +383,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-profile", action="store_true", help="skip the profiled step after the timed ones")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="single form only: leave out the batched and served figures of the default line")
     ap.add_argument("--form", default="single", choices=["single", "batched", "served"],
                     help="single graph (default); batched: many SBMs in one batched run; served: request loop")
     ap.add_argument("--graphs", type=int, default=4096, help="batched form: graphs in the batch")
@@ -337,9 +403,11 @@ def main():
               "described, not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.form == "batched":
-        return bench_batched(args)
+        print(json.dumps(bench_batched(args)))
+        return
     if args.form == "served":
-        return bench_served(args)
+        print(json.dumps(bench_served(args)))
+        return
 
     import numpy as np
     import torch
@@ -385,6 +453,15 @@ def main():
     gteps = entries / elapsed / 1e9
     last = results[-1]
     assert all(r.N == last.N and r.K == last.K for r in results), "steps disagree"
+    # time to converge from the host CSR (H2D copy of offsets, columns and
+    # weights inside the time), one untimed-loop step
+    t_h = time.perf_counter()
+    gh = L.Graph.from_csr(g, validate=False, stream=stream)
+    res_h = gh.run(p, labels=labels)
+    gh.close()
+    torch.cuda.synchronize()
+    ttc_h2d_ms = (time.perf_counter() - t_h) * 1e3
+    assert res_h.N == last.N and res_h.K == last.K, "host-ingest step disagrees"
 
     def profiled(params):
         """One untimed step with HIP events around every launch on the
@@ -444,9 +521,10 @@ def main():
                    "color_cutoff": p.color_cutoff, "theta_color": [p.theta_color.num, p.theta_color.den],
                    "theta_final": [p.theta_final.num, p.theta_final.den]},
         "time_to_converge_ms": round(ms_per_step, 3),
+        "time_to_converge_incl_h2d_ms": round(ttc_h2d_ms, 3),
         "result": {"communities": last.K, "q": last.q, "phases": len(last.phases),
                    "iterations": sum(ph.iterations for ph in last.phases), "n_after_vf": last.n_vf,
-                   "sweep_entries": last.sweep_entries,
+                   "sweep_entries": last.sweep_entries, "lookahead_entries": last.lookahead_entries,
                    "phase_shape": [[ph.n, ph.nnz, int(ph.colored), ph.num_colors, ph.iterations] for ph in last.phases]},
         "time_split_ms": {"vf": round(last.ms_vf, 2), "color": round(last.ms_color, 2),
                           "sweep": round(last.ms_sweep, 2), "coarsen": round(last.ms_coarsen, 2)},
@@ -464,8 +542,26 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = nb
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.heuristics)
         out["cpu_baseline"]["gpu_over_cpu"] = round(gteps / out["cpu_baseline"]["value"], 1)
+    if not args.no_forms:
+        # the batched (4,096 SBMs) and served (job mix) forms, each with its
+        # one-at-a-time reference and the oracle's check of every output
+        del off, col, w, labels
+        torch.cuda.empty_cache()
+        fa = argparse.Namespace(**vars(args))
+        fa.steps, fa.warmup = 3, 1
+        bt = bench_batched(fa)
+        out["batched"] = {"graphs_per_s": bt["value"], "ms_per_batch": bt["ms_per_step"], "config": bt["config"],
+                          "one_at_a_time_graphs_per_s": bt["one_at_a_time"]["value"],
+                          "batched_over_one_at_a_time": bt["one_at_a_time"]["batched_over_one_at_a_time"],
+                          "oracle_checked_graphs": bt["oracle_checked_graphs"], "cpu_baseline": bt["cpu_baseline"]}
+        sv = bench_served(fa)
+        out["served"] = {"graphs_per_s": sv["value"], "capacity_graphs_per_s": sv["config"]["capacity_per_s"],
+                         "rate_per_s": sv["config"]["rate_per_s"], "latency_ms": sv["latency_ms"],
+                         "config": sv["config"], "one_at_a_time_graphs_per_s": sv["one_at_a_time"]["value"],
+                         "capacity_over_one_at_a_time": sv["one_at_a_time"]["capacity_over_one_at_a_time"],
+                         "oracle_checked_jobs": sv["oracle_checked_jobs"], "cpu_baseline": sv["cpu_baseline"]}
     print(json.dumps(out))
 
 

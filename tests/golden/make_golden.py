@@ -5,12 +5,15 @@ synthetic graphs of ``paper_1410_1237_amd.graphs``; nothing is taken from the
 HIP library.  Usage::
 
     python tests/golden/make_golden.py rmat_s20:full rmat_s20:plain ...
+    python tests/golden/make_golden.py batch_sbm:4096 served:128
 
 Each target writes ``<workload>_<heuristics>.json`` beside this script with
 the number of communities, the exact modularity pair (N, D), the
 per-phase shape (vertices, entries, colouring, colours, iterations, moves and
 exact per-iteration modularity numerators) and the SHA-256 of the final
-labels (int32, little endian).
+labels (int32, little endian).  A mix target (``batch_sbm:<count>``,
+``served:<count>``) writes one compact record per graph of the batched or
+served mix instead.
 """
 import hashlib
 import json
@@ -55,9 +58,59 @@ def golden(workload: str, heur: str) -> dict:
     }
 
 
+MIXES = {
+    # the batched mix: planted SBMs of uneven sizes (batch_sbm(i))
+    "batch_sbm": G.batch_sbm,
+    # the served mix: SBM and R-MAT jobs from 1e3 to 2e6 vertices (served_job(i))
+    "served": G.served_job,
+}
+
+
+def golden_mix(mix: str, count: int, threads: int) -> dict:
+    """Oracle results of graphs 0..count-1 of a mix, plain heuristics, one
+    compact record per graph: [i, n, nnz, K, N, D, phases, iterations,
+    first 16 hex digits of the labels' SHA-256].  The graphs are independent:
+    they run on a thread pool (the oracle and the generator release the GIL)."""
+    import concurrent.futures as cf
+    O = oracle.default()
+
+    def one(i):
+        g = MIXES[mix](i)
+        r = O.run(g, oracle.Params())
+        return [i, g.n, g.nnz, r.K, str(r.N), str(r.D), len(r.phases), sum(p.iterations for p in r.phases),
+                labels_sha(r.labels)[:16]]
+    t = time.time()
+    # largest first, so that the pool's tail is short
+    order = sorted(range(count), key=lambda i: -MIXES[mix + "_n"](i)) if mix + "_n" in MIXES else range(count)
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        recs = sorted(ex.map(one, order), key=lambda r: r[0])
+    return {"mix": mix, "count": count, "heuristics": "plain",
+            "fields": ["i", "n", "nnz", "K", "N", "D", "phases", "iterations", "labels_sha256_16"],
+            "graphs": recs, "oracle_seconds": round(time.time() - t, 1), "threads": threads}
+
+
+MIXES["batch_sbm_n"] = lambda i: G.batch_sbm_params(i)["n"]
+MIXES["served_n"] = lambda i: G.served_job_params(i)["n"]
+
+
 def main(targets):
     for t in targets:
         wl, heur = t.split(":")
+        if wl in ("batch_sbm", "served"):
+            count = int(heur)
+            threads = int(os.environ.get("GOLDEN_THREADS", "8"))
+            out = golden_mix(wl, count, threads)
+            path = os.path.join(HERE, f"{wl}_x{count}_plain.json")
+            with open(path, "w") as f:
+                f.write("{\n")
+                items = [(k, v) for k, v in out.items() if k != "graphs"]
+                for k, v in items:
+                    f.write(f" {json.dumps(k)}: {json.dumps(v)},\n")
+                f.write(' "graphs": [\n')
+                f.write(",\n".join("  " + json.dumps(r) for r in out["graphs"]))
+                f.write("\n ]\n}\n")
+            print(f"wrote {path}: {count} graphs ({out['oracle_seconds']} s)", flush=True)
+            continue
         out = golden(wl, heur)
         path = os.path.join(HERE, f"{wl}_{heur}.json")
         with open(path, "w") as f:
