@@ -234,6 +234,34 @@ louvain_status louvain_run(louvain_graph_t g, const louvain_params *params, int3
 /* Releases the handle and its device memory (NULL is a no-op). */
 void louvain_destroy(louvain_graph_t g);
 
+/* Size of the fixed device scratch of louvain_run_noalloc (64 MiB per GPU). */
+#define LOUVAIN_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * louvain_init_csr with device pointers followed by louvain_run, in one call
+ * that makes no device allocation.  Every working buffer of the run is carved
+ * from a fixed LOUVAIN_NOALLOC_SCRATCH_BYTES device array of the library; each
+ * GPU the library runs on holds its own copy until the process ends.
+ *   offsets, cols, weights: device CSR as in louvain_init_csr (weights NULL =
+ *     unit); flags: 0 or LOUVAIN_VALIDATE.  labels_out: device int32[n] (may
+ *     be NULL).  *out (may be NULL): as louvain_run; its phase and iter arrays
+ *     stay valid until the next louvain_run_noalloc call of the same thread.
+ * The result equals louvain_init_csr + louvain_run on the same input.  A graph
+ * whose handle buffers (about 72 bytes per CSR entry plus 136 per vertex)
+ * exceed the scratch is refused up front with LOUVAIN_E_INVALID_ARG; buffers
+ * sized during the run (hub pair lists, colouring bitmaps) that no longer fit
+ * end it with LOUVAIN_E_OOM.  Graphs of up to 65,536 vertices and 524,288 CSR
+ * entries fit.  Errors are read with louvain_last_error(NULL).  All calls on
+ * one GPU share its scratch, which keeps the last call's contents: calls that
+ * overlap on one GPU (two threads, or two streams in flight) race and must
+ * not be made.  The call synchronizes hip_stream before it returns.
+ */
+louvain_status louvain_run_noalloc(int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                                   const int32_t *weights, uint32_t flags, const louvain_params *params,
+                                   int32_t *labels_out, void *hip_stream, louvain_result *out);
+
 /* Last error message of g (or of the last failed louvain_init_csr when g is
  * NULL); never NULL, "" when there was none. */
 const char *louvain_last_error(louvain_graph_t g);

@@ -1739,6 +1739,94 @@ louvain_status louvain_profile_get(louvain_graph_t g, int32_t idx, const char **
 } // extern "C"
 
 // ===========================================================================
+// Allocation-free run.  Every buffer of the run is carved from `scratch`, a
+// fixed device array of this file (one copy per GPU, held until the process
+// ends), so the call makes no device allocation.  In host code `scratch`
+// names a host-side stand-in: its device address is taken once per device
+// with hipGetSymbolAddress and only that address is ever used.
+// ===========================================================================
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)LOUVAIN_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, char *> g_scratch_ptr; // device -> device address of its copy of scratch
+
+// the current device's copy of scratch, looked up once per device
+louvain_status scratch_address(int dev, char **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return LOUVAIN_OK;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return fail(nullptr, LOUVAIN_E_HIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = (char *)p;
+    *out = (char *)p;
+    return LOUVAIN_OK;
+}
+
+// phase and iteration records of the last allocation-free run of this thread
+thread_local std::vector<louvain_phase_stats> t_noalloc_phases;
+thread_local std::vector<louvain_iter_stats> t_noalloc_iters;
+
+} // namespace
+
+extern "C" {
+
+louvain_status louvain_run_noalloc(int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                                   const int32_t *weights, uint32_t flags, const louvain_params *params,
+                                   int32_t *labels_out, void *hip_stream, louvain_result *out)
+{
+    g_init_error.clear();
+    if (flags & ~LOUVAIN_VALIDATE) return fail(nullptr, LOUVAIN_E_INVALID_ARG, "only LOUVAIN_VALIDATE is accepted");
+    flags |= LOUVAIN_DEVICE_PTRS;
+    louvain_status s = check_csr_args(n, nnz, offsets, cols, flags);
+    if (s) return s;
+    // the buffers the handle needs, measured without carving anything
+    G probe;
+    probe.count_only = true;
+    (void)alloc_buffers(&probe, n, nnz, weights != nullptr);
+    if (probe.arena_used > kScratchBytes)
+        return fail(nullptr, LOUVAIN_E_INVALID_ARG,
+                    "graph too large for louvain_run_noalloc: its buffers need " + std::to_string(probe.arena_used) +
+                        " bytes of the " + std::to_string(kScratchBytes) + "-byte scratch");
+    G g;
+    g.st = (hipStream_t)hip_stream;
+    if (const hipError_t e = hipGetDevice(&g.dev))
+        return fail(nullptr, LOUVAIN_E_HIP, std::string("hipGetDevice failed: ") + hipGetErrorString(e));
+    if ((s = scratch_address(g.dev, &g.arena))) return s;
+    g.arena_cap = kScratchBytes;
+    // no HIP graphs, no timing events, default lanes: nothing but kernels and copies
+    g.graphs_ok = false;
+    g.tune = false;
+    auto done = [&](louvain_status st) {
+        if (st) g_init_error = g.err;
+        release_all(&g);
+        return st;
+    };
+    if ((s = alloc_buffers(&g, n, nnz, weights != nullptr))) return done(s);
+    if ((s = ingest(&g, n, nnz, offsets, cols, weights, flags))) return done(s);
+    louvain_result res;
+    if ((s = louvain_run(&g, params, labels_out, 1, &res))) return done(s);
+    t_noalloc_phases = g.phases;
+    t_noalloc_iters = g.iters;
+    res.phase = t_noalloc_phases.data();
+    res.iter = t_noalloc_iters.data();
+    if (out) *out = res;
+    return done(LOUVAIN_OK);
+}
+
+} // extern "C"
+
+// ===========================================================================
 // Batched form: many independent graphs in one disjoint-union CSR.  Every
 // launch covers all graphs; each graph keeps its own iteration and phase
 // decisions (the rules of louvain_run, applied per graph on the host from

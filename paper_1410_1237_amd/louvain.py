@@ -101,7 +101,7 @@ EXPORTS = ["louvain_params_default", "louvain_init_csr", "louvain_vf", "louvain_
            "louvain_server_create", "louvain_server_submit", "louvain_server_submit_borrowed",
            "louvain_server_poll", "louvain_server_release",
            "louvain_server_wait_all", "louvain_server_last_error", "louvain_server_destroy",
-           "louvain_vf_chain", "louvain_color_balance"]
+           "louvain_run_noalloc", "louvain_vf_chain", "louvain_color_balance"]
 
 
 def lib():
@@ -139,6 +139,9 @@ def lib():
     L.louvain_coarsen.restype = st
     L.louvain_run.argtypes = [vp, ctypes.POINTER(Params), vp, u32, ctypes.POINTER(Result)]
     L.louvain_run.restype = st
+    L.louvain_run_noalloc.argtypes = [i64, i64, vp, vp, vp, u32, ctypes.POINTER(Params), vp, vp,
+                                      ctypes.POINTER(Result)]
+    L.louvain_run_noalloc.restype = st
     L.louvain_destroy.argtypes = [vp]
     L.louvain_destroy.restype = None
     L.louvain_last_error.argtypes = [vp]
@@ -283,6 +286,16 @@ def louvain_coarsen(h) -> int:
 def louvain_run(h, p: Params, labels_ptr=None, labels_on_device=0) -> Result:
     out = Result()
     _check(lib().louvain_run(h, ctypes.byref(p), labels_ptr, int(labels_on_device), ctypes.byref(out)), h)
+    return out
+
+
+def louvain_run_noalloc(n, nnz, offsets, cols, weights, p: Params, labels_ptr=None, flags=0,
+                        hip_stream=None) -> Result:
+    """The allocation-free run: offsets, cols, weights (or None) and labels_ptr
+    are device pointers (ints); nothing is allocated on the device."""
+    out = Result()
+    _check(lib().louvain_run_noalloc(int(n), int(nnz), offsets, cols, weights, int(flags), ctypes.byref(p),
+                                     labels_ptr, _stream_ptr(hip_stream), ctypes.byref(out)))
     return out
 
 
