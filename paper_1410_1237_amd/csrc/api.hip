@@ -462,7 +462,10 @@ void prof_collect(G *g, const lv::SweepStats *host_stats, int wb)
                 if (!((p.stat_slot >> b) & 1) || slot_done[b]) continue;
                 const lv::SweepStats &s = host_stats[b];
                 const bool hub = b >= 9;
-                if (!hub || !hub_pass2) {
+                // hub entries: gathered by pass 1, or from singletons (no pass 1)
+                // scanned by the pass-2 launch itself
+                const bool entries_here = !hub || (p.singleton ? hub_pass2 : !hub_pass2);
+                if (entries_here) {
                     r.bytes += ((p.singleton ? 4.0 : 8.0) + wb) * (double)s.entries;
                     r.entries += (double)s.entries;
                 }

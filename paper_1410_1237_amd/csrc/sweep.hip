@@ -159,6 +159,45 @@ __device__ __forceinline__ int64_t gather_row(const SweepArgs &a, int32_t i, int
     return wself;
 }
 
+// A sweep from the singleton partition (the first of every phase): the
+// entries [first, end) of vertex i taken at `stride` are each a candidate of
+// their own, C(j) = j with e_{i->j} = w_ij (columns are unique) and a_j = k_j;
+// updates the lane's best (G, -j), its self-loop weight and its count of
+// distinct candidates.  The degrees of GATHER_K entries are read together.
+template <int WK, typename GT>
+__device__ __forceinline__ void singleton_row(const SweepArgs &a, int32_t i, int64_t ki, int64_t two_m, int64_t first,
+                                              int64_t end, int stride, Best<GT> &best, int64_t &wself,
+                                              int64_t &distinct)
+{
+    for (int64_t e0 = first; e0 < end; e0 += (int64_t)GATHER_K * stride) {
+        int32_t j[GATHER_K];
+        int64_t w[GATHER_K], kj[GATHER_K];
+#pragma unroll
+        for (int k = 0; k < GATHER_K; ++k) {
+            const int64_t e = e0 + (int64_t)k * stride;
+            j[k] = -1;
+            w[k] = 0;
+            if (e < end) {
+                j[k] = a.g.col[e];
+                w[k] = WLoad<WK>::at(a.g.w, e);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < GATHER_K; ++k) kj[k] = (j[k] >= 0 && j[k] != i) ? a.a[j[k]] : 0;
+#pragma unroll
+        for (int k = 0; k < GATHER_K; ++k) {
+            if (j[k] < 0) continue;
+            if (j[k] == i) {
+                wself += w[k];
+                continue;
+            }
+            ++distinct;
+            Best<GT> cand{(GT)two_m * (GT)w[k] - (GT)ki * (GT)kj[k], j[k], w[k]};
+            if (better(cand, best)) best = cand;
+        }
+    }
+}
+
 // One block-tile of a degree bin: VPB = BLOCK / LPV vertices, LPV lanes each,
 // hash tables of 2^shift slots per vertex in LDS.
 template <int LPV, int WK, typename GT>
@@ -176,14 +215,14 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const BinRange &b
     const int64_t S = (int64_t)1 << shift;
     int32_t *tkey = (int32_t *)smem + grp * S;
     VT *tval = (VT *)(smem + (size_t)VPB * S * sizeof(int32_t)) + grp * S;
-    for (int64_t s = lane; s < S; s += LPV) {
-        tkey[s] = -1;
-        tval[s] = 0;
-    }
+    if (!a.singleton) // a sweep from the singleton partition needs no table
+        for (int64_t s = lane; s < S; s += LPV) {
+            tkey[s] = -1;
+            tval[s] = 0;
+        }
     if (threadIdx.x < 5) bstat[threadIdx.x] = 0;
     __syncthreads();
 
-    // gather: e_{i->c} per neighbouring community (Eq. 1), self-loop apart
     int64_t beg = 0, end = 0, wself = 0;
     int32_t A = 0;
     if (valid) {
@@ -191,14 +230,20 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const BinRange &b
         end = a.g.off[i + 1];
         A = a.comm_prev[i];
     }
+    const int64_t ki = valid ? a.k[i] : 0;
+    Best<GT> best{0, -1, 0};
+    int64_t eA = 0, distinct = 0;
+    if (a.singleton) {
+        // every vertex is alone: each non-self neighbour j is a distinct
+        // candidate community with e = w_ij and a_j = k_j, and e_A = 0
+        if (valid) singleton_row<WK, GT>(a, i, ki, two_m, beg + lane, end, LPV, best, wself, distinct);
+    } else {
+    // gather: e_{i->c} per neighbouring community (Eq. 1), self-loop apart
     if (valid) wself = gather_row<WK, VT>(a, i, beg + lane, end, LPV, tkey, tval, shift);
     __syncthreads();
 
     // gains over the distinct communities (Eq. 4 scaled by 2m^2), best by
     // (G, -c); the community degrees of GATHER_K slots are read together
-    const int64_t ki = valid ? a.k[i] : 0;
-    Best<GT> best{0, -1, 0};
-    int64_t eA = 0, distinct = 0;
     for (int64_t s0 = lane; s0 < S; s0 += (int64_t)GATHER_K * LPV) {
         int32_t c[GATHER_K];
         int64_t ac[GATHER_K];
@@ -221,6 +266,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const BinRange &b
             Best<GT> cand{(GT)two_m * (GT)e - (GT)ki * (GT)ac[k], c[k], e};
             if (better(cand, best)) best = cand;
         }
+    }
     }
 
     // reduce over the LPV lanes of the vertex
@@ -539,6 +585,66 @@ template <typename GT> __device__ __forceinline__ int32_t hub_decide(const Sweep
     return dest;
 }
 
+// Hub rows in a sweep from the singleton partition: every neighbour is a
+// community of its own, so nothing is aggregated and pass 1 is not run.
+// One block per (hub, bucket) scans the bucket's equal slice of the hub's
+// row and writes the slice's best (G, -j) and counts in the bucket record
+// that the decision reads; the slice holding the self-loop stores it at the
+// hub's first bucket.
+template <int WK, typename GT>
+__global__ __launch_bounds__(HUB_BLOCK2) void k_hub_first(SweepArgs a, HubArgs h)
+{
+    __shared__ Best<GT> sb[HUB_BLOCK2 / 64];
+    __shared__ int64_t se[HUB_BLOCK2 / 64][2];
+    const int64_t q = h.bucket0 + blockIdx.x;
+    const HubBucket bk = h.buckets[q];
+    const int32_t v = bk.v;
+    if (!sweeping(a, v)) return; // uniform over the block
+    const int64_t beg = a.g.off[v], d = a.g.off[v + 1] - beg;
+    const int64_t lo = beg + d * bk.b / bk.P, hi = beg + d * (bk.b + 1) / bk.P;
+    const int64_t two_m = two_m_of(a, v), kv = a.k[v];
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    Best<GT> best{0, -1, 0};
+    int64_t wself = 0, distinct = 0;
+    singleton_row<WK, GT>(a, v, kv, two_m, lo + tid, hi, HUB_BLOCK2, best, wself, distinct);
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        Best<GT> o;
+        o.g = shfl_xor_t(best.g, m, 64);
+        o.c = shfl_xor_t(best.c, m, 64);
+        o.e = shfl_xor_t(best.e, m, 64);
+        if (better(o, best)) best = o;
+        wself += shfl_xor_t(wself, m, 64);
+        distinct += shfl_xor_t(distinct, m, 64);
+    }
+    if (lane == 0) {
+        sb[wid] = best;
+        se[wid][0] = wself;
+        se[wid][1] = distinct;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < HUB_BLOCK2 / 64; ++w) {
+            if (better(sb[w], best)) best = sb[w];
+            wself += se[w][0];
+            distinct += se[w][1];
+        }
+        int64_t *rec = h.part + HUB_REC * q;
+        const i128 g = (i128)best.g;
+        const int32_t A = a.comm_prev[v];
+        rec[0] = (int64_t)(uint64_t)(u128)g;
+        rec[1] = (int64_t)(g >> 64);
+        rec[2] = (int64_t)best.c;
+        rec[3] = best.e;
+        rec[4] = 0; // e_A: no neighbour shares the hub's one-vertex community
+        rec[5] = distinct;
+        rec[6] = best.c >= 0 ? a.size[best.c] : 0;
+        rec[7] = a.a[A];
+        rec[8] = a.size[A];
+        if (wself) h.self[q - bk.b] = wself;
+    }
+}
+
 // one wavefront per hub
 template <typename GT> __global__ __launch_bounds__(BLOCK) void k_hub_decide(SweepArgs a, HubArgs h)
 {
@@ -798,7 +904,7 @@ bool sweep_large(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, b
         blocks += (f.bins[b].count + BLOCK / f.lanes[b] - 1) / (BLOCK / f.lanes[b]);
     }
     f.hub_block0 = blocks;
-    if (h.e > h.s) blocks += h.n_chunks;
+    if (h.e > h.s && !a.singleton) blocks += h.n_chunks; // from singletons the hubs need no pass 1
     if (blocks == 0) return false;
     fused<false>(a, f, h, blocks, wide, narrow, st);
     return true;
@@ -812,7 +918,7 @@ bool sweep_all(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, boo
         blocks += (f.bins[b].count + BLOCK / f.lanes[b] - 1) / (BLOCK / f.lanes[b]);
     }
     f.hub_block0 = blocks;
-    if (h.e > h.s) blocks += h.n_chunks;
+    if (h.e > h.s && !a.singleton) blocks += h.n_chunks;
     if (blocks == 0) return false;
     fused<true>(a, f, h, blocks, wide, narrow, st);
     return true;
@@ -824,6 +930,23 @@ bool sweep_hub_agg(const SweepArgs &a, const HubArgs &h, bool wide, bool narrow,
     const unsigned g = (unsigned)h.n_buckets;
     unsigned gd = grid_for(h.e - h.s, BLOCK / 64);
     if (gd > 1024) gd = 1024;
+    if (a.singleton) {
+        // from singletons: the buckets' slices are scanned directly
+#define LV_FIRST(GT)                                                                                                   \
+        switch (a.g.wk) {                                                                                              \
+        case W_UNIT: k_hub_first<W_UNIT, GT><<<g, HUB_BLOCK2, 0, st>>>(a, h); break;                                  \
+        case W_I32: k_hub_first<W_I32, GT><<<g, HUB_BLOCK2, 0, st>>>(a, h); break;                                    \
+        default: k_hub_first<W_I64, GT><<<g, HUB_BLOCK2, 0, st>>>(a, h); break;                                       \
+        }                                                                                                              \
+        if (decide) k_hub_decide<GT><<<gd, BLOCK, 0, st>>>(a, h);
+        if (wide) {
+            LV_FIRST(i128)
+        } else {
+            LV_FIRST(int64_t)
+        }
+#undef LV_FIRST
+        return true;
+    }
     if (wide) {
         if (narrow) k_hub_agg<i128, uint32_t><<<g, HUB_BLOCK2, 0, st>>>(a, h);
         else k_hub_agg<i128, unsigned long long><<<g, HUB_BLOCK2, 0, st>>>(a, h);

@@ -308,6 +308,23 @@ def test_run_balanced_coloring(L, O):
         compare_run(res, O.run(g, oracle_params(d)), f"{g.name} {d}")
 
 
+def test_clique_beyond_4096_colours(L, O):
+    """A clique of 4,200 vertices needs 4,200 colours: the last vertices to
+    be coloured see all of the first 4,096 colours taken by higher-priority
+    neighbours, which sends their long rows past the 4,096-bit bitmap to the
+    64-colour-window continuation.  Colours equal the oracle's greedy ones."""
+    n = 4200
+    full = np.tile(np.arange(n, dtype=np.int32), (n, 1))
+    cols = full[~np.eye(n, dtype=bool)]                  # row-major, ascending within each row
+    off = np.arange(n + 1, dtype=np.int64) * (n - 1)
+    g = SG.CSR(n=n, offsets=off, cols=np.ascontiguousarray(cols), weights=None, name="clique_4200")
+    gs = L.Graph.from_csr(g, validate=False)
+    st = O.state(g)
+    assert gs.color() == st.color() == n
+    assert np.array_equal(gs.colors(), st.get("color"))
+    gs.close()
+
+
 def test_run_sbm_1000(L, O):
     g = GG.sbm_1000()
     res = L.Graph.from_csr(g).run(L.params())
