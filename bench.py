@@ -28,6 +28,7 @@ import hashlib
 import json
 import os
 import platform
+import subprocess
 import sys
 import time
 
@@ -415,6 +416,22 @@ def main():
         print(json.dumps(bench_served(args)))
         return
 
+    # the batched (4,096 SBMs) and served (job mix) forms first, each in a
+    # child process of its own (a fresh device and allocator state), each with
+    # its one-at-a-time reference and the oracle's check of every output
+    forms = None
+    if not args.no_forms:
+        def child(form):
+            cmd = [sys.executable, os.path.abspath(__file__), "--form", form, "--steps", "3", "--warmup", "1",
+                   "--cpu-seconds", str(args.cpu_seconds)]
+            if args.no_cpu_baseline:
+                cmd.append("--no-cpu-baseline")
+            r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
+            if r.returncode != 0:
+                raise SystemExit(f"bench.py --form {form} failed with status {r.returncode}")
+            return json.loads(r.stdout.strip().splitlines()[-1])
+        forms = (child("batched"), child("served"))
+
     import numpy as np
     import torch
     from paper_1410_1237_amd import louvain as L
@@ -550,19 +567,12 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.heuristics)
         out["cpu_baseline"]["gpu_over_cpu"] = round(gteps / out["cpu_baseline"]["value"], 1)
-    if not args.no_forms:
-        # the batched (4,096 SBMs) and served (job mix) forms, each with its
-        # one-at-a-time reference and the oracle's check of every output
-        del off, col, w, labels
-        torch.cuda.empty_cache()
-        fa = argparse.Namespace(**vars(args))
-        fa.steps, fa.warmup = 3, 1
-        bt = bench_batched(fa)
+    if forms:
+        bt, sv = forms
         out["batched"] = {"graphs_per_s": bt["value"], "ms_per_batch": bt["ms_per_step"], "config": bt["config"],
                           "one_at_a_time_graphs_per_s": bt["one_at_a_time"]["value"],
                           "batched_over_one_at_a_time": bt["one_at_a_time"]["batched_over_one_at_a_time"],
                           "oracle_checked_graphs": bt["oracle_checked_graphs"], "cpu_baseline": bt["cpu_baseline"]}
-        sv = bench_served(fa)
         out["served"] = {"graphs_per_s": sv["value"], "capacity_graphs_per_s": sv["config"]["capacity_per_s"],
                          "rate_per_s": sv["config"]["rate_per_s"], "latency_ms": sv["latency_ms"],
                          "config": sv["config"], "one_at_a_time_graphs_per_s": sv["one_at_a_time"]["value"],
