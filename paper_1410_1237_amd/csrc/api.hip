@@ -230,8 +230,9 @@ struct louvain_graph_s {
     int64_t lookahead_entries = 0; // of those, by look-ahead sweeps whose moves were discarded
 
     // coloring
-    int32_t *color = nullptr, *jp_cnt = nullptr, *front_a = nullptr, *front_b = nullptr, *counters = nullptr;
-    int32_t *jp_chunk = nullptr;            // two chunk lists
+    int32_t *color = nullptr, *jp_cnt = nullptr, *counters = nullptr;
+    int64_t *jp_light = nullptr;            // two light frontier lists of n 16-byte entries
+    int64_t *jp_chunk = nullptr;            // two chunk lists of 32-byte entries
     uint64_t *jp_bm = nullptr;              // colour bitmaps of long rows (kept zero)
     unsigned long long *bal_closed = nullptr; // closed-colour bitmap of the balanced colouring (64 words)
     int64_t jp_chunk_cap = 0, jp_bm_cap = 0;
@@ -1011,7 +1012,7 @@ louvain_status do_color(G *g, uint64_t seed)
         louvain_status s;
         if (pairs > g->jp_chunk_cap) {
             release_buffer(g, g->jp_chunk);
-            if ((s = alloc(g, &g->jp_chunk, 4 * pairs))) return s;
+            if ((s = alloc(g, &g->jp_chunk, 8 * pairs))) return s;
             g->jp_chunk_cap = pairs;
         }
         if (words > g->jp_bm_cap) {
@@ -1024,13 +1025,12 @@ louvain_status do_color(G *g, uint64_t seed)
         c.color = g->color;
         c.cnt = g->jp_cnt;
         c.long_id = g->jp_cnt + n;
-        c.lng[0] = g->jp_cnt + 2 * n;
-        c.lng[1] = g->jp_cnt + 3 * n;
-        c.light[0] = g->front_a;
-        c.light[1] = g->front_b;
+        c.done = g->jp_cnt + 2 * n;
+        c.light[0] = g->jp_light;
+        c.light[1] = g->jp_light + 2 * n;
         c.counters = g->counters;
         c.chunk[0] = g->jp_chunk;
-        c.chunk[1] = g->jp_chunk + 2 * g->jp_chunk_cap;
+        c.chunk[1] = g->jp_chunk + 4 * g->jp_chunk_cap;
         c.bm = (unsigned long long *)g->jp_bm;
         g->num_colors = lv::color_jp(g->cur, seed, c, g->scratch, g->st);
         if (g->num_colors < 0) return hip_fail(g, hipGetLastError(), "coloring (copy or wait on the stream)");
@@ -1063,7 +1063,7 @@ louvain_status do_balance(G *g, uint64_t seed, int64_t *moved_out)
     b.prop = g->jp_cnt + n;
     b.taken = g->jp_cnt + 2 * n;
     b.before = g->jp_cnt + 3 * n;
-    b.size = g->front_a;
+    b.size = (int32_t *)g->jp_light; // ncolors <= n
     b.closed = g->bal_closed;
     b.keys = g->keys;
     b.keys_alt = g->keys_alt;
@@ -1281,8 +1281,7 @@ louvain_status alloc_buffers(G *g, int64_t n, int64_t nnz, bool weighted)
     if ((s = alloc(g, &g->k, n)) || (s = alloc(g, &g->a, n)) || (s = alloc(g, &g->comm_prev, n)) ||
         (s = alloc(g, &g->comm_next, n)) || (s = alloc(g, &g->comm_save, n)) || (s = alloc(g, &g->size, n)) ||
         (s = alloc(g, &g->orig_map, n)) ||
-        (s = alloc(g, &g->color, n)) || (s = alloc(g, &g->jp_cnt, 5 * n)) || (s = alloc(g, &g->front_a, n)) ||
-        (s = alloc(g, &g->front_b, n)) || (s = alloc(g, &g->counters, 16)) || (s = alloc(g, &g->keys, big)) ||
+        (s = alloc(g, &g->color, n)) || (s = alloc(g, &g->jp_cnt, 5 * n)) || (s = alloc(g, &g->jp_light, 4 * n)) || (s = alloc(g, &g->counters, 16)) || (s = alloc(g, &g->keys, big)) ||
         (s = alloc(g, &g->keys_alt, big)) || (s = alloc(g, &g->vals, big)) || (s = alloc(g, &g->vals_alt, big)) ||
         (s = alloc(g, &g->run, big)) || (s = alloc(g, &g->bin_verts, n)) || (s = alloc(g, &g->cpre, n + 1)) ||
         (s = alloc(g, &g->bpre, n + 1)) || (s = alloc(g, &g->xpre, n + 1)) || (s = alloc(g, &g->flag, n + 1)) ||

@@ -9,15 +9,21 @@
 // colouring a vertex decrements its lower-priority neighbours and those
 // reaching zero form the next round's frontier.  The number of rounds is the
 // longest priority-descending path, so a round must be short rather than
-// wide.  One launch per round: one wavefront colours a frontier vertex with a
-// row of up to JP_LIGHT entries (64-colour register windows); longer rows are
-// cut into JP_CHUNK-entry chunks, one workgroup each, which OR the colours of
-// their higher-priority neighbours (below 4096) into the vertex's bitmap in
-// HBM and do their decrements, so a round takes about as long as one chunk.
-// A small second launch turns each long row's bitmap into its colour.
-// Frontier sizes live in a device ring indexed by round, so rounds are
-// launched in batches without host synchronisation: round r reads slot r,
-// counts the next frontier into slot r+1 and clears slot r+2.
+// wide: one launch per round, and inside it as few dependent memory accesses
+// as possible.  One wavefront colours a frontier vertex with a row of up to
+// JP_LIGHT entries: every lane loads its (up to four) entries at once, then
+// the colours and decrements of all of them, then pushes them with one
+// counter update per wave; the colours taken go into a 4096-bit LDS bitmap
+// of the wave, so the first free one is found without another pass over the
+// row (late vertices of a skewed graph see hundreds of colours).  Longer rows are cut into JP_CHUNK-entry chunks,
+// one workgroup each, which OR the colours of their higher-priority
+// neighbours (below 4096) into the vertex's bitmap in HBM and do their
+// decrements; the workgroup that finishes the last chunk of a row turns the
+// bitmap into the vertex's colour.  The next round is the first to read any
+// colour written in this one.  Frontier sizes live in a device ring indexed
+// by round, so rounds are launched in batches without host synchronisation:
+// round r reads slot r, counts the next frontier into slot r+1 and clears
+// slot r+2.
 #include "lv.h"
 
 #include <vector>
@@ -29,8 +35,10 @@ constexpr int64_t JP_CHUNK = 1024;        // entries of a long row per workgroup
 constexpr int JP_BM_WORDS = 64;           // 64 x 64 = 4096 colours in a long row's bitmap
 constexpr unsigned JP_LIGHT_BLOCKS = 512; // 2048 waves, grid-stride over the light frontier
 constexpr unsigned JP_CHUNK_BLOCKS = 1024;
-constexpr unsigned JP_FINAL_BLOCKS = 64;
 constexpr int64_t JP_RING = 4;            // slots of 3 counts: light, long vertices, chunks
+constexpr int JP_LIGHT_ITEMS = (int)(JP_LIGHT / 64); // entries per lane of a light row
+constexpr int JP_CHUNK_ITEMS = (int)(JP_CHUNK / BLOCK); // entries per thread of a chunk
+static_assert(JP_LIGHT % 64 == 0 && JP_CHUNK % BLOCK == 0, "whole items per lane");
 
 __device__ __forceinline__ uint64_t jp_priority(uint64_t seed, int64_t v)
 {
@@ -98,48 +106,81 @@ __global__ __launch_bounds__(BLOCK) void k_jp_long_flags(const int64_t *off, int
         flag[v] = off[v + 1] - off[v] > JP_LIGHT ? 1 : 0;
 }
 
+// frontier entries carry their rows, so that a round's first dependent read
+// is the row itself: a light vertex with its row [b, b + d), and chunk j of
+// the long row [rb, rb + d) of v
+struct JpItem {
+    int64_t b;
+    int32_t v, d;
+};
+struct JpChunk {
+    int64_t rb;
+    int32_t v, d, j, pad[3];
+};
+static_assert(sizeof(JpItem) == 16 && sizeof(JpChunk) == 32, "one or two 16-byte loads per entry");
+
 // frontier lists of one round
 struct JpLists {
-    int32_t *light; // vertices
-    int32_t *lng;   // long vertices (coloured after the round)
-    int32_t *chunk; // (vertex, chunk index) pairs of the long vertices
+    JpItem *light;
+    JpChunk *chunk;
 };
 
-// appends u (where push) to the next frontier; called by every active lane
-// of the wave together: one counter update per wave for the light list
-__device__ __forceinline__ void jp_push(const Csr &g, bool push, int32_t u, const JpLists &out, int32_t *counts)
+// appends the u[j] with ready[j] (rows [ub, ub + ud)) to the next frontier;
+// called by all 64 lanes of a wave together.  The light ones take one
+// counter update per wave, a long one adds its chunks (counts: light
+// vertices, long vertices, chunks)
+template <int K>
+__device__ __forceinline__ void jp_push(const bool (&ready)[K], const int32_t (&u)[K], const int64_t (&ub)[K],
+                                        const int64_t (&ud)[K], const JpLists &out, int32_t *counts)
 {
-    int64_t d = 0;
-    if (push) d = g.off[u + 1] - g.off[u];
-    const bool light = push && d <= JP_LIGHT;
     const int lane = threadIdx.x & 63;
-    const unsigned long long m = __ballot(light);
-    if (m) {
-        const int leader = __ffsll(m) - 1;
-        int32_t base = 0;
-        if (lane == leader) base = atomicAdd(&counts[0], __popcll(m));
-        base = __shfl(base, leader, 64);
-        if (light) out.light[base + __popcll(m & ((1ull << lane) - 1))] = u;
+    const unsigned long long below = (1ull << lane) - 1;
+    unsigned long long m[K];
+    int32_t total = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        m[j] = __ballot(ready[j] && ud[j] <= JP_LIGHT);
+        total += __popcll(m[j]);
     }
-    if (push && !light) {
-        out.lng[atomicAdd(&counts[1], 1)] = u;
-        const int32_t nch = (int32_t)((d + JP_CHUNK - 1) / JP_CHUNK);
-        const int32_t c0 = atomicAdd(&counts[2], nch);
-        for (int32_t j = 0; j < nch; ++j) {
-            out.chunk[2 * (int64_t)(c0 + j)] = u;
-            out.chunk[2 * (int64_t)(c0 + j) + 1] = j;
+    if (total) {
+        int32_t base = 0;
+        if (lane == 0) base = atomicAdd(&counts[0], total);
+        base = __shfl(base, 0, 64);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if ((m[j] >> lane) & 1) out.light[base + __popcll(m[j] & below)] = JpItem{ub[j], u[j], (int32_t)ud[j]};
+            base += __popcll(m[j]);
         }
     }
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (ready[j] && ud[j] > JP_LIGHT) {
+            atomicAdd(&counts[1], 1);
+            const int32_t nch = (int32_t)((ud[j] + JP_CHUNK - 1) / JP_CHUNK);
+            const int32_t c0 = atomicAdd(&counts[2], nch);
+            for (int32_t q = 0; q < nch; ++q) out.chunk[c0 + q] = JpChunk{ub[j], u[j], (int32_t)ud[j], q, {0, 0, 0}};
+        }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_jp_start(Csr g, const int32_t *cnt, int32_t *color, JpLists out,
                                                     int32_t *ring)
 {
-    for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < g.n; v += (int64_t)gridDim.x * BLOCK) {
-        const int64_t b = g.off[v], e = g.off[v + 1];
-        const bool alone = (e == b) || (e - b == 1 && g.col[b] == v);
-        color[v] = alone ? 0 : -1;
-        jp_push(g, !alone && cnt[v] == 0, (int32_t)v, out, ring);
+    // the loop runs while any lane of the block has a vertex, so that every
+    // wave pushes with all of its lanes
+    const int64_t n_up = (g.n + BLOCK - 1) / BLOCK * BLOCK;
+    for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n_up; v += (int64_t)gridDim.x * BLOCK) {
+        bool ready[1] = {false};
+        int32_t u[1] = {(int32_t)v};
+        int64_t ub[1] = {0}, ud[1] = {0};
+        if (v < g.n) {
+            const int64_t b = g.off[v], e = g.off[v + 1];
+            const bool alone = (e == b) || (e - b == 1 && g.col[b] == v);
+            color[v] = alone ? 0 : -1;
+            ready[0] = !alone && cnt[v] == 0;
+            ub[0] = b;
+            ud[0] = e - b;
+        }
+        jp_push(ready, u, ub, ud, out, ring);
     }
 }
 
@@ -173,107 +214,150 @@ __device__ __forceinline__ int32_t jp_wave_mex(const Csr &g, uint64_t seed, int3
     }
 }
 
+// K entries per thread at stride S from x0 (sentinel v past e): the colours
+// of the higher-priority neighbours (cu, -1 for the others) and the
+// decrements of the lower-priority ones (ready: the decrement reached zero,
+// with the row [ub, ub + ud) of such a neighbour).  Loads and atomics of
+// the K entries are issued together.
+template <int K, int S>
+__device__ __forceinline__ void jp_entries(const Csr &g, uint64_t seed, int32_t v, uint64_t pv, int64_t x0,
+                                           int64_t e, const int32_t *color, int32_t *cnt, int32_t (&u)[K],
+                                           int32_t (&cu)[K], bool (&ready)[K], int64_t (&ub)[K], int64_t (&ud)[K])
+{
+    bool hi[K], lo[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int64_t x = x0 + (int64_t)j * S;
+        u[j] = x < e ? g.col[x] : v;
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const bool other = u[j] != v;
+        hi[j] = other && jp_priority(seed, u[j]) > pv;
+        lo[j] = other && !hi[j];
+    }
+    int32_t old[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) cu[j] = hi[j] ? color[u[j]] : -1;
+#pragma unroll
+    for (int j = 0; j < K; ++j) old[j] = lo[j] ? atomicSub(&cnt[u[j]], 1) : 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) ready[j] = lo[j] && old[j] == 1;
+#pragma unroll
+    for (int j = 0; j < K; ++j) ub[j] = ready[j] ? g.off[u[j]] : 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) ud[j] = ready[j] ? g.off[u[j] + 1] - ub[j] : 0;
+}
+
 // one round: light vertices by wavefronts (blocks [0, JP_LIGHT_BLOCKS)),
-// chunks of long rows by workgroups (the other blocks)
+// chunks of long rows by workgroups (the other blocks).  done[long_id[v]]
+// counts the finished chunks of v; the workgroup of the last one colours v
+// from the bitmap (clearing bitmap and count for the next colouring).  The
+// first entry of a wave or block is read beside the frontier size (cap_*:
+// list capacities; an entry past the size is read but not used).
 __global__ __launch_bounds__(BLOCK) void k_jp_round(Csr g, uint64_t seed, JpLists in, JpLists out, int32_t *ring,
-                                                    int64_t r, int32_t *color, int32_t *cnt, const int32_t *long_id,
+                                                    int64_t r, int64_t cap_light, int64_t cap_chunk, int32_t *color,
+                                                    int32_t *cnt, const int32_t *long_id, int32_t *done,
                                                     unsigned long long *bm)
 {
     __shared__ unsigned long long s_bm[JP_BM_WORDS];
+    __shared__ unsigned long long s_wbm[BLOCK / 64][JP_BM_WORDS];
+    __shared__ int32_t s_last;
     const int32_t *cur = ring + 3 * (r % JP_RING);
     int32_t *next = ring + 3 * ((r + 1) % JP_RING);
     if (blockIdx.x == 0 && threadIdx.x < 3) ring[3 * ((r + 2) % JP_RING) + threadIdx.x] = 0;
     const int lane = threadIdx.x & 63;
     if (blockIdx.x < JP_LIGHT_BLOCKS) {
-        const int64_t nf = cur[0];
-        const int64_t wave = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+        const int64_t f0 = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
         const int64_t nwaves = (int64_t)JP_LIGHT_BLOCKS * (BLOCK / 64);
-        for (int64_t f = wave; f < nf; f += nwaves) {
-            const int32_t v = in.light[f];
-            const int64_t b = g.off[v], e = g.off[v + 1];
+        JpItem it = f0 < cap_light ? in.light[f0] : JpItem{0, 0, 0};
+        unsigned long long *wbm = s_wbm[threadIdx.x >> 6]; // this wave's bitmap of colours below 4096
+        wbm[lane] = 0;
+        const int64_t nf = cur[0];
+        for (int64_t f = f0; f < nf; f += nwaves) {
+            if (f != f0) it = in.light[f];
+            const int32_t v = it.v;
+            const int64_t b = it.b, e = it.b + it.d;
             const uint64_t pv = jp_priority(seed, v);
-            // one pass over the row: colours below 64 of the higher-priority
-            // neighbours, decrements of the lower-priority ones (their pushes
-            // are for the next round, which is the first to read v's colour)
-            unsigned long long used = 0;
-            for (int64_t x = b + lane; x < e; x += 64) {
-                const int32_t u = g.col[x];
-                bool ready = false;
-                if (u != v) {
-                    if (jp_priority(seed, u) > pv) {
-                        const int32_t cu = color[u];
-                        if (cu >= 0 && cu < 64) used |= 1ull << cu;
-                    } else {
-                        ready = atomicSub(&cnt[u], 1) == 1;
-                    }
-                }
-                jp_push(g, ready, u, out, next);
+            // the row in one pass: colours below 4096 of the higher-priority
+            // neighbours into the wave's LDS bitmap, decrements of the
+            // lower-priority ones (their pushes are for the next round, which
+            // is the first to read v's colour)
+            int32_t u[JP_LIGHT_ITEMS], cu[JP_LIGHT_ITEMS];
+            bool ready[JP_LIGHT_ITEMS];
+            int64_t ub[JP_LIGHT_ITEMS], ud[JP_LIGHT_ITEMS];
+            jp_entries<JP_LIGHT_ITEMS, 64>(g, seed, v, pv, b + lane, e, color, cnt, u, cu, ready, ub, ud);
+#pragma unroll
+            for (int j = 0; j < JP_LIGHT_ITEMS; ++j)
+                if (cu[j] >= 0 && cu[j] < JP_BM_WORDS * 64) atomicOr(&wbm[cu[j] >> 6], 1ull << (cu[j] & 63));
+            jp_push(ready, u, ub, ud, out, next);
+            // a wave's LDS operations complete in order: the word read here
+            // holds every lane's bits
+            const unsigned long long word = wbm[lane];
+            wbm[lane] = 0;
+            const unsigned long long open = __ballot(word != ~0ull);
+            int32_t c;
+            if (open) {
+                const int l = __ffsll(open) - 1;
+                c = l * 64 + __ffsll(~__shfl(word, l, 64)) - 1;
+            } else {
+                c = jp_wave_mex(g, seed, v, pv, b, e, color, JP_BM_WORDS * 64);
             }
-            used = wave_or(used);
-            const int32_t c = used != ~0ull ? __ffsll(~used) - 1 : jp_wave_mex(g, seed, v, pv, b, e, color, 64);
             if (lane == 0) color[v] = c;
         }
         return;
     }
+    const int64_t q0 = blockIdx.x - JP_LIGHT_BLOCKS;
+    JpChunk ch = q0 < cap_chunk ? in.chunk[q0] : JpChunk{0, 0, 0, 0, {0, 0, 0}};
     const int64_t nc = cur[2];
-    for (int64_t q = blockIdx.x - JP_LIGHT_BLOCKS; q < nc; q += gridDim.x - JP_LIGHT_BLOCKS) {
-        const int32_t v = in.chunk[2 * q], j = in.chunk[2 * q + 1];
-        const int64_t b = g.off[v] + (int64_t)j * JP_CHUNK;
-        const int64_t e = min(g.off[v + 1], b + JP_CHUNK);
+    for (int64_t q = q0; q < nc; q += gridDim.x - JP_LIGHT_BLOCKS) {
+        if (q != q0) ch = in.chunk[q];
+        const int32_t v = ch.v;
+        const int64_t rb = ch.rb, re = ch.rb + ch.d;
+        const int64_t b = rb + (int64_t)ch.j * JP_CHUNK;
+        const int64_t e = min(re, b + JP_CHUNK);
+        const int32_t nch = (int32_t)(((int64_t)ch.d + JP_CHUNK - 1) / JP_CHUNK);
+        const int32_t lid = long_id[v];
         const uint64_t pv = jp_priority(seed, v);
         if (threadIdx.x < JP_BM_WORDS) s_bm[threadIdx.x] = 0;
         __syncthreads();
-        // decrements first (every lane of a wave takes part in the push),
-        // colours of the higher-priority neighbours into the LDS bitmap
-        for (int64_t x0 = b; x0 < e; x0 += BLOCK) {
-            const int64_t x = x0 + threadIdx.x;
-            bool ready = false;
-            int32_t u = 0;
-            if (x < e) {
-                u = g.col[x];
-                if (u != v) {
-                    if (jp_priority(seed, u) > pv) {
-                        const int32_t cu = color[u];
-                        if (cu < JP_BM_WORDS * 64) atomicOr(&s_bm[cu >> 6], 1ull << (cu & 63));
-                    } else {
-                        ready = atomicSub(&cnt[u], 1) == 1;
-                    }
-                }
-            }
-            jp_push(g, ready, u, out, next);
-        }
+        int32_t u[JP_CHUNK_ITEMS], cu[JP_CHUNK_ITEMS];
+        bool ready[JP_CHUNK_ITEMS];
+        int64_t ub[JP_CHUNK_ITEMS], ud[JP_CHUNK_ITEMS];
+        jp_entries<JP_CHUNK_ITEMS, BLOCK>(g, seed, v, pv, b + threadIdx.x, e, color, cnt, u, cu, ready, ub, ud);
+#pragma unroll
+        for (int i = 0; i < JP_CHUNK_ITEMS; ++i)
+            if (cu[i] >= 0 && cu[i] < JP_BM_WORDS * 64) atomicOr(&s_bm[cu[i] >> 6], 1ull << (cu[i] & 63));
+        jp_push(ready, u, ub, ud, out, next);
         __syncthreads();
         if (threadIdx.x < JP_BM_WORDS && s_bm[threadIdx.x])
-            atomicOr(&bm[(int64_t)long_id[v] * JP_BM_WORDS + threadIdx.x], s_bm[threadIdx.x]);
+            atomicOr(&bm[(int64_t)lid * JP_BM_WORDS + threadIdx.x], s_bm[threadIdx.x]);
+        __threadfence();
         __syncthreads();
-    }
-}
-
-// colours of the round's long vertices from their bitmaps (one wavefront
-// each); a full bitmap (4096 colours taken) continues by 64-colour windows
-__global__ __launch_bounds__(BLOCK) void k_jp_final(Csr g, uint64_t seed, const int32_t *lng, const int32_t *ring,
-                                                    int64_t r, int32_t *color, const int32_t *long_id,
-                                                    unsigned long long *bm)
-{
-    static_assert(JP_BM_WORDS == 64, "one bitmap word per lane");
-    const int64_t nl = ring[3 * (r % JP_RING) + 1];
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
-    for (int64_t f = wave; f < nl; f += (int64_t)gridDim.x * (BLOCK / 64)) {
-        const int32_t v = lng[f];
-        unsigned long long *w = bm + (int64_t)long_id[v] * JP_BM_WORDS;
-        const unsigned long long word = w[lane];
-        w[lane] = 0; // clean for the next colouring
-        const unsigned long long open = __ballot(word != ~0ull);
-        int32_t c;
-        if (open) {
-            const int l = __ffsll(open) - 1;
-            const unsigned long long wl = __shfl(word, l, 64);
-            c = l * 64 + __ffsll(~wl) - 1;
-        } else {
-            c = jp_wave_mex(g, seed, v, jp_priority(seed, v), g.off[v], g.off[v + 1], color, JP_BM_WORDS * 64);
+        if (threadIdx.x == 0) s_last = atomicAdd(&done[lid], 1) == nch - 1;
+        __syncthreads();
+        if (s_last && threadIdx.x < 64) {
+            // every chunk of v has ORed its colours in: the first free colour
+            // of the bitmap (read and cleared at once), or past 4096 by
+            // 64-colour windows over the row when all of those are taken
+            static_assert(JP_BM_WORDS == 64, "one bitmap word per lane");
+            __threadfence();
+            const unsigned long long word = atomicExch(&bm[(int64_t)lid * JP_BM_WORDS + lane], 0ull);
+            const unsigned long long open = __ballot(word != ~0ull);
+            int32_t c;
+            if (open) {
+                const int l = __ffsll(open) - 1;
+                const unsigned long long wl = __shfl(word, l, 64);
+                c = l * 64 + __ffsll(~wl) - 1;
+            } else {
+                c = jp_wave_mex(g, seed, v, pv, rb, re, color, JP_BM_WORDS * 64);
+            }
+            if (lane == 0) {
+                color[v] = c;
+                done[lid] = 0;
+            }
         }
-        if (lane == 0) color[v] = c;
+        __syncthreads();
     }
 }
 
@@ -311,16 +395,17 @@ int32_t color_jp(const Csr &g, uint64_t seed, const ColorBufs &c, Scratch &s, hi
     k_jp_long_flags<<<gv, BLOCK, 0, st>>>(g.off, g.n, c.long_id);
     scan_i32_to_i32(c.long_id, c.long_id, g.n, s.scalar, s, st);
     if (g.nnz > 0) k_jp_count<<<grid_for(g.nnz, ETILE), BLOCK, 0, st>>>(g, seed, c.cnt);
-    JpLists lists[2] = {{c.light[0], c.lng[0], c.chunk[0]}, {c.light[1], c.lng[1], c.chunk[1]}};
+    fill<int32_t>(c.done, 0, g.n, st);
+    const int64_t cap_chunk = color_chunk_pairs(g);
+    JpLists lists[2] = {{(JpItem *)c.light[0], (JpChunk *)c.chunk[0]}, {(JpItem *)c.light[1], (JpChunk *)c.chunk[1]}};
     k_jp_start<<<gv, BLOCK, 0, st>>>(g, c.cnt, c.color, lists[0], ring);
     int64_t r = 0;     // next round to launch
     int64_t batch = 4; // rounds launched per host check, doubled up to 256
     for (;;) {
         for (int64_t i = 0; i < batch; ++i, ++r) {
             const JpLists &in = lists[r & 1], &out = lists[(r + 1) & 1];
-            k_jp_round<<<JP_LIGHT_BLOCKS + JP_CHUNK_BLOCKS, BLOCK, 0, st>>>(g, seed, in, out, ring, r, c.color, c.cnt,
-                                                                           c.long_id, c.bm);
-            k_jp_final<<<JP_FINAL_BLOCKS, BLOCK, 0, st>>>(g, seed, in.lng, ring, r, c.color, c.long_id, c.bm);
+            k_jp_round<<<JP_LIGHT_BLOCKS + JP_CHUNK_BLOCKS, BLOCK, 0, st>>>(
+                g, seed, in, out, ring, r, g.n, cap_chunk, c.color, c.cnt, c.long_id, c.done, c.bm);
         }
         int32_t nf[3] = {0, 0, 0};
         if (hipMemcpyAsync(nf, ring + 3 * (r % JP_RING), 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
@@ -328,6 +413,7 @@ int32_t color_jp(const Csr &g, uint64_t seed, const ColorBufs &c, Scratch &s, hi
             hipStreamSynchronize(st) != hipSuccess)
             return -1;
         if (nf[0] == 0 && nf[1] == 0 && nf[2] == 0) break;
+        if (r > g.n + 256) return -1; // a round colours at least one vertex: cannot happen
         if (batch < 256) batch *= 2;
     }
     int32_t *mx_slot = ring + 3 * JP_RING;

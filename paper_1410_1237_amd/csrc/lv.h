@@ -72,14 +72,40 @@ struct TileRows {
     bool cached;
 };
 
+// row_of by all 64 lanes of a wavefront: each step probes 64 offsets evenly
+// inside (lo, hi) at once and keeps the bracket between the last probe at
+// or below e and the next one, so a search over n rows takes about
+// log64(n) dependent loads instead of log2(n).  Same precondition and result
+// as row_of; every lane returns the row.
+__device__ __forceinline__ int64_t wave_row_of(const int64_t *off, int64_t lo, int64_t hi, int64_t e)
+{
+    const int lane = threadIdx.x & 63;
+    while (hi - lo > 1) {
+        const int64_t p = lo + 1 + ((hi - lo - 1) * lane) / 64; // in [lo + 1, hi - 1], nondecreasing in lane
+        const unsigned long long m = __ballot(off[p] <= e);    // offsets are sorted: lanes 0..j set
+        if (m == 0) {
+            hi = __shfl(p, 0, 64);
+        } else {
+            const int j = 63 - __clzll((long long)m);
+            const int64_t pj = __shfl(p, j, 64);
+            const int64_t pn = __shfl(p, j < 63 ? j + 1 : 63, 64);
+            lo = pj;
+            if (j < 63) hi = pn;
+        }
+    }
+    return lo;
+}
+
 __device__ __forceinline__ TileRows tile_rows(const int64_t *off, int64_t n, int64_t e0, int64_t e1, int64_t *s_off,
                                               int64_t *s_meta)
 {
-    if (threadIdx.x == 0) {
-        int64_t lo = row_of(off, 0, n, e0);
-        int64_t hi = row_of(off, lo, n, e1);
-        s_meta[0] = lo;
-        s_meta[1] = hi;
+    if (threadIdx.x < 64) {
+        const int64_t lo = wave_row_of(off, 0, n, e0);
+        const int64_t hi = wave_row_of(off, lo, n, e1);
+        if (threadIdx.x == 0) {
+            s_meta[0] = lo;
+            s_meta[1] = hi;
+        }
     }
     __syncthreads();
     TileRows t;
@@ -408,9 +434,9 @@ struct ColorBufs {
     int32_t *cnt;            // n: uncoloured higher-priority neighbours
     int32_t *long_id;        // n: rank among the rows longer than the light limit
     int32_t *counters;       // 16: frontier-size ring and the colour maximum
-    int32_t *light[2];       // n each: light frontier lists (ping-pong)
-    int32_t *lng[2];         // n each: long-row frontier lists
-    int32_t *chunk[2];       // 2 x color_chunk_pairs each: (vertex, chunk) pairs
+    void *light[2];          // n entries of 16 bytes each: light frontier lists (ping-pong)
+    int32_t *done;           // n: finished chunks per long row (by rank), cleared by the colouring
+    void *chunk[2];          // color_chunk_pairs entries of 32 bytes each: chunks of long rows
     unsigned long long *bm;  // color_bitmap_words, zero: colour bitmaps of long rows (left zero)
 };
 int64_t color_bitmap_words(const Csr &g);

@@ -55,7 +55,7 @@ struct Job {
 uint64_t job_bytes(int64_t n, int64_t nnz)
 {
     const uint64_t big = (uint64_t)(nnz > n ? nnz : n) + 1;
-    return 3ull * 8 * (n + 1) + 3ull * 4 * nnz + 2ull * 8 * nnz + 4ull * nnz + 5ull * 8 * big + 120ull * n;
+    return 3ull * 8 * (n + 1) + 3ull * 4 * nnz + 2ull * 8 * nnz + 4ull * nnz + 5ull * 8 * big + 144ull * n;
 }
 
 } // namespace
