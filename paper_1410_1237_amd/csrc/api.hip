@@ -233,7 +233,7 @@ struct louvain_graph_s {
     int32_t *color = nullptr, *jp_cnt = nullptr, *counters = nullptr;
     int64_t *jp_light = nullptr;            // two light frontier lists of n 16-byte entries
     int64_t *jp_chunk = nullptr;            // two chunk lists of 32-byte entries
-    uint64_t *jp_bm = nullptr;              // colour bitmaps of long rows (kept zero)
+    uint64_t *jp_bm = nullptr;              // colour bitmaps of long rows (cleared by each colouring)
     unsigned long long *bal_closed = nullptr; // closed-colour bitmap of the balanced colouring (64 words)
     int64_t jp_chunk_cap = 0, jp_bm_cap = 0;
     int32_t num_colors = 0;
@@ -1019,13 +1019,11 @@ louvain_status do_color(G *g, uint64_t seed)
             release_buffer(g, g->jp_bm);
             if ((s = alloc(g, &g->jp_bm, words))) return s;
             g->jp_bm_cap = words;
-            lv::fill<uint64_t>(g->jp_bm, 0, words, g->st);
         }
         lv::ColorBufs c;
         c.color = g->color;
         c.cnt = g->jp_cnt;
         c.long_id = g->jp_cnt + n;
-        c.done = g->jp_cnt + 2 * n;
         c.light[0] = g->jp_light;
         c.light[1] = g->jp_light + 2 * n;
         c.counters = g->counters;

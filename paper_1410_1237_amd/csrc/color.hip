@@ -12,18 +12,21 @@
 // wide: one launch per round, and inside it as few dependent memory accesses
 // as possible.  One wavefront colours a frontier vertex with a row of up to
 // JP_LIGHT entries: every lane loads its (up to four) entries at once, then
-// the colours and decrements of all of them, then pushes them with one
-// counter update per wave; the colours taken go into a 4096-bit LDS bitmap
-// of the wave, so the first free one is found without another pass over the
-// row (late vertices of a skewed graph see hundreds of colours).  Longer rows are cut into JP_CHUNK-entry chunks,
-// one workgroup each, which OR the colours of their higher-priority
-// neighbours (below 4096) into the vertex's bitmap in HBM and do their
-// decrements; the workgroup that finishes the last chunk of a row turns the
-// bitmap into the vertex's colour.  The next round is the first to read any
-// colour written in this one.  Frontier sizes live in a device ring indexed
-// by round, so rounds are launched in batches without host synchronisation:
-// round r reads slot r, counts the next frontier into slot r+1 and clears
-// slot r+2.
+// the colours and decrements of all of them, ORs the colours into a 4096-bit
+// LDS bitmap of the wave (late vertices of a skewed graph see hundreds of
+// colours) and pushes the ready neighbours with one counter update per wave.
+// A longer row never gathers its neighbours' colours: every vertex, once
+// coloured, ORs its colour into the 4096-bit HBM bitmap of each
+// lower-priority long neighbour while decrementing it, so when a long row is
+// ready its bitmap already holds the colours of all its higher-priority
+// neighbours.  Such a row is cut into JP_CHUNK-entry chunks, one workgroup
+// each; every chunk's workgroup reads the row's bitmap, takes the first free
+// colour and does its chunk's decrements and ORs, with no merge between the
+// workgroups.  The next round is the first to read any colour or bitmap bit
+// written in this one (vertices of one round are never adjacent).  Frontier
+// sizes live in a device ring indexed by round, so rounds are launched in
+// batches without host synchronisation: round r reads slot r, counts the
+// next frontier into slot r+1 and clears slot r+2.
 #include "lv.h"
 
 #include <vector>
@@ -104,6 +107,20 @@ __global__ __launch_bounds__(BLOCK) void k_jp_long_flags(const int64_t *off, int
 {
     for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK)
         flag[v] = off[v + 1] - off[v] > JP_LIGHT ? 1 : 0;
+}
+
+// long_id: the rank of a long row, -1 for a light one
+__global__ __launch_bounds__(BLOCK) void k_jp_light_ids(const int64_t *off, int64_t n, int32_t *long_id)
+{
+    for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n; v += (int64_t)gridDim.x * BLOCK)
+        if (off[v + 1] - off[v] <= JP_LIGHT) long_id[v] = -1;
+}
+
+// clears the bitmaps of the *count long rows
+__global__ __launch_bounds__(BLOCK) void k_jp_clear_bitmaps(unsigned long long *bm, const int64_t *count)
+{
+    const int64_t words = *count * JP_BM_WORDS;
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < words; i += (int64_t)gridDim.x * BLOCK) bm[i] = 0;
 }
 
 // frontier entries carry their rows, so that a round's first dependent read
@@ -215,14 +232,16 @@ __device__ __forceinline__ int32_t jp_wave_mex(const Csr &g, uint64_t seed, int3
 }
 
 // K entries per thread at stride S from x0 (sentinel v past e): the colours
-// of the higher-priority neighbours (cu, -1 for the others) and the
-// decrements of the lower-priority ones (ready: the decrement reached zero,
-// with the row [ub, ub + ud) of such a neighbour).  Loads and atomics of
+// of the higher-priority neighbours (cu, -1 for the others; read only if HI)
+// and the decrements of the lower-priority ones (ready: the decrement reached
+// zero, with the row [ub, ub + ud) of such a neighbour; lu: the long-row rank
+// of a lower-priority neighbour, -1 for the others).  Loads and atomics of
 // the K entries are issued together.
-template <int K, int S>
+template <int K, int S, bool HI>
 __device__ __forceinline__ void jp_entries(const Csr &g, uint64_t seed, int32_t v, uint64_t pv, int64_t x0,
-                                           int64_t e, const int32_t *color, int32_t *cnt, int32_t (&u)[K],
-                                           int32_t (&cu)[K], bool (&ready)[K], int64_t (&ub)[K], int64_t (&ud)[K])
+                                           int64_t e, const int32_t *color, int32_t *cnt, const int32_t *long_id,
+                                           int32_t (&u)[K], int32_t (&cu)[K], bool (&ready)[K], int64_t (&ub)[K],
+                                           int64_t (&ud)[K], int32_t (&lu)[K])
 {
     bool hi[K], lo[K];
 #pragma unroll
@@ -238,9 +257,11 @@ __device__ __forceinline__ void jp_entries(const Csr &g, uint64_t seed, int32_t 
     }
     int32_t old[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) cu[j] = hi[j] ? color[u[j]] : -1;
+    for (int j = 0; j < K; ++j) cu[j] = (HI && hi[j]) ? color[u[j]] : -1;
 #pragma unroll
     for (int j = 0; j < K; ++j) old[j] = lo[j] ? atomicSub(&cnt[u[j]], 1) : 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) lu[j] = lo[j] ? long_id[u[j]] : -1;
 #pragma unroll
     for (int j = 0; j < K; ++j) ready[j] = lo[j] && old[j] == 1;
 #pragma unroll
@@ -249,20 +270,27 @@ __device__ __forceinline__ void jp_entries(const Csr &g, uint64_t seed, int32_t 
     for (int j = 0; j < K; ++j) ud[j] = ready[j] ? g.off[u[j] + 1] - ub[j] : 0;
 }
 
+// colour c of a vertex into the bitmaps of its lower-priority long neighbours
+template <int K>
+__device__ __forceinline__ void jp_mark(unsigned long long *bm, const int32_t (&lu)[K], int32_t c)
+{
+    if (c >= JP_BM_WORDS * 64) return;
+    const unsigned long long bit = 1ull << (c & 63);
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (lu[j] >= 0) atomicOr(&bm[(int64_t)lu[j] * JP_BM_WORDS + (c >> 6)], bit);
+}
+
 // one round: light vertices by wavefronts (blocks [0, JP_LIGHT_BLOCKS)),
-// chunks of long rows by workgroups (the other blocks).  done[long_id[v]]
-// counts the finished chunks of v; the workgroup of the last one colours v
-// from the bitmap (clearing bitmap and count for the next colouring).  The
-// first entry of a wave or block is read beside the frontier size (cap_*:
-// list capacities; an entry past the size is read but not used).
+// chunks of long rows by workgroups (the other blocks).  The first entry of
+// a wave or block is read beside the frontier size (cap_*: list capacities;
+// an entry past the size is read but not used).
 __global__ __launch_bounds__(BLOCK) void k_jp_round(Csr g, uint64_t seed, JpLists in, JpLists out, int32_t *ring,
                                                     int64_t r, int64_t cap_light, int64_t cap_chunk, int32_t *color,
-                                                    int32_t *cnt, const int32_t *long_id, int32_t *done,
-                                                    unsigned long long *bm)
+                                                    int32_t *cnt, const int32_t *long_id, unsigned long long *bm)
 {
-    __shared__ unsigned long long s_bm[JP_BM_WORDS];
     __shared__ unsigned long long s_wbm[BLOCK / 64][JP_BM_WORDS];
-    __shared__ int32_t s_last;
+    __shared__ int32_t s_c;
     const int32_t *cur = ring + 3 * (r % JP_RING);
     int32_t *next = ring + 3 * ((r + 1) % JP_RING);
     if (blockIdx.x == 0 && threadIdx.x < 3) ring[3 * ((r + 2) % JP_RING) + threadIdx.x] = 0;
@@ -279,14 +307,15 @@ __global__ __launch_bounds__(BLOCK) void k_jp_round(Csr g, uint64_t seed, JpList
             const int32_t v = it.v;
             const int64_t b = it.b, e = it.b + it.d;
             const uint64_t pv = jp_priority(seed, v);
-            // the row in one pass: colours below 4096 of the higher-priority
-            // neighbours into the wave's LDS bitmap, decrements of the
-            // lower-priority ones (their pushes are for the next round, which
-            // is the first to read v's colour)
-            int32_t u[JP_LIGHT_ITEMS], cu[JP_LIGHT_ITEMS];
+            // the row in one pass: colours of the higher-priority neighbours
+            // into the wave's LDS bitmap, decrements of the lower-priority
+            // ones (their pushes are for the next round, the first to read
+            // v's colour), then v's colour into the long ones' bitmaps
+            int32_t u[JP_LIGHT_ITEMS], cu[JP_LIGHT_ITEMS], lu[JP_LIGHT_ITEMS];
             bool ready[JP_LIGHT_ITEMS];
             int64_t ub[JP_LIGHT_ITEMS], ud[JP_LIGHT_ITEMS];
-            jp_entries<JP_LIGHT_ITEMS, 64>(g, seed, v, pv, b + lane, e, color, cnt, u, cu, ready, ub, ud);
+            jp_entries<JP_LIGHT_ITEMS, 64, true>(g, seed, v, pv, b + lane, e, color, cnt, long_id, u, cu, ready, ub,
+                                                 ud, lu);
 #pragma unroll
             for (int j = 0; j < JP_LIGHT_ITEMS; ++j)
                 if (cu[j] >= 0 && cu[j] < JP_BM_WORDS * 64) atomicOr(&wbm[cu[j] >> 6], 1ull << (cu[j] & 63));
@@ -304,6 +333,7 @@ __global__ __launch_bounds__(BLOCK) void k_jp_round(Csr g, uint64_t seed, JpList
                 c = jp_wave_mex(g, seed, v, pv, b, e, color, JP_BM_WORDS * 64);
             }
             if (lane == 0) color[v] = c;
+            jp_mark(bm, lu, c);
         }
         return;
     }
@@ -316,48 +346,34 @@ __global__ __launch_bounds__(BLOCK) void k_jp_round(Csr g, uint64_t seed, JpList
         const int64_t rb = ch.rb, re = ch.rb + ch.d;
         const int64_t b = rb + (int64_t)ch.j * JP_CHUNK;
         const int64_t e = min(re, b + JP_CHUNK);
-        const int32_t nch = (int32_t)(((int64_t)ch.d + JP_CHUNK - 1) / JP_CHUNK);
-        const int32_t lid = long_id[v];
         const uint64_t pv = jp_priority(seed, v);
-        if (threadIdx.x < JP_BM_WORDS) s_bm[threadIdx.x] = 0;
-        __syncthreads();
-        int32_t u[JP_CHUNK_ITEMS], cu[JP_CHUNK_ITEMS];
-        bool ready[JP_CHUNK_ITEMS];
-        int64_t ub[JP_CHUNK_ITEMS], ud[JP_CHUNK_ITEMS];
-        jp_entries<JP_CHUNK_ITEMS, BLOCK>(g, seed, v, pv, b + threadIdx.x, e, color, cnt, u, cu, ready, ub, ud);
-#pragma unroll
-        for (int i = 0; i < JP_CHUNK_ITEMS; ++i)
-            if (cu[i] >= 0 && cu[i] < JP_BM_WORDS * 64) atomicOr(&s_bm[cu[i] >> 6], 1ull << (cu[i] & 63));
-        jp_push(ready, u, ub, ud, out, next);
-        __syncthreads();
-        if (threadIdx.x < JP_BM_WORDS && s_bm[threadIdx.x])
-            atomicOr(&bm[(int64_t)lid * JP_BM_WORDS + threadIdx.x], s_bm[threadIdx.x]);
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) s_last = atomicAdd(&done[lid], 1) == nch - 1;
-        __syncthreads();
-        if (s_last && threadIdx.x < 64) {
-            // every chunk of v has ORed its colours in: the first free colour
-            // of the bitmap (read and cleared at once), or past 4096 by
-            // 64-colour windows over the row when all of those are taken
+        if (threadIdx.x < 64) {
+            // v's colour: the first free bit of its bitmap, which holds the
+            // colours below 4096 of all its higher-priority neighbours; past
+            // 4096 by 64-colour windows over the row when all are taken
             static_assert(JP_BM_WORDS == 64, "one bitmap word per lane");
-            __threadfence();
-            const unsigned long long word = atomicExch(&bm[(int64_t)lid * JP_BM_WORDS + lane], 0ull);
+            const unsigned long long word = bm[(int64_t)long_id[v] * JP_BM_WORDS + lane];
             const unsigned long long open = __ballot(word != ~0ull);
             int32_t c;
             if (open) {
                 const int l = __ffsll(open) - 1;
-                const unsigned long long wl = __shfl(word, l, 64);
-                c = l * 64 + __ffsll(~wl) - 1;
+                c = l * 64 + __ffsll(~__shfl(word, l, 64)) - 1;
             } else {
                 c = jp_wave_mex(g, seed, v, pv, rb, re, color, JP_BM_WORDS * 64);
             }
-            if (lane == 0) {
-                color[v] = c;
-                done[lid] = 0;
-            }
+            if (lane == 0) s_c = c;
         }
+        int32_t u[JP_CHUNK_ITEMS], cu[JP_CHUNK_ITEMS], lu[JP_CHUNK_ITEMS];
+        bool ready[JP_CHUNK_ITEMS];
+        int64_t ub[JP_CHUNK_ITEMS], ud[JP_CHUNK_ITEMS];
+        jp_entries<JP_CHUNK_ITEMS, BLOCK, false>(g, seed, v, pv, b + threadIdx.x, e, color, cnt, long_id, u, cu,
+                                                 ready, ub, ud, lu);
+        jp_push(ready, u, ub, ud, out, next);
         __syncthreads();
+        const int32_t c = s_c;
+        if (ch.j == 0 && threadIdx.x == 0) color[v] = c;
+        jp_mark(bm, lu, c);
+        __syncthreads(); // s_c is rewritten by the next chunk
     }
 }
 
@@ -394,8 +410,9 @@ int32_t color_jp(const Csr &g, uint64_t seed, const ColorBufs &c, Scratch &s, hi
     if (gv > 4096) gv = 4096;
     k_jp_long_flags<<<gv, BLOCK, 0, st>>>(g.off, g.n, c.long_id);
     scan_i32_to_i32(c.long_id, c.long_id, g.n, s.scalar, s, st);
+    k_jp_light_ids<<<gv, BLOCK, 0, st>>>(g.off, g.n, c.long_id);
+    k_jp_clear_bitmaps<<<1024, BLOCK, 0, st>>>(c.bm, s.scalar);
     if (g.nnz > 0) k_jp_count<<<grid_for(g.nnz, ETILE), BLOCK, 0, st>>>(g, seed, c.cnt);
-    fill<int32_t>(c.done, 0, g.n, st);
     const int64_t cap_chunk = color_chunk_pairs(g);
     JpLists lists[2] = {{(JpItem *)c.light[0], (JpChunk *)c.chunk[0]}, {(JpItem *)c.light[1], (JpChunk *)c.chunk[1]}};
     k_jp_start<<<gv, BLOCK, 0, st>>>(g, c.cnt, c.color, lists[0], ring);
@@ -405,7 +422,7 @@ int32_t color_jp(const Csr &g, uint64_t seed, const ColorBufs &c, Scratch &s, hi
         for (int64_t i = 0; i < batch; ++i, ++r) {
             const JpLists &in = lists[r & 1], &out = lists[(r + 1) & 1];
             k_jp_round<<<JP_LIGHT_BLOCKS + JP_CHUNK_BLOCKS, BLOCK, 0, st>>>(
-                g, seed, in, out, ring, r, g.n, cap_chunk, c.color, c.cnt, c.long_id, c.done, c.bm);
+                g, seed, in, out, ring, r, g.n, cap_chunk, c.color, c.cnt, c.long_id, c.bm);
         }
         int32_t nf[3] = {0, 0, 0};
         if (hipMemcpyAsync(nf, ring + 3 * (r % JP_RING), 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st) !=

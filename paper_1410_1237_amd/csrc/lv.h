@@ -435,9 +435,8 @@ struct ColorBufs {
     int32_t *long_id;        // n: rank among the rows longer than the light limit
     int32_t *counters;       // 16: frontier-size ring and the colour maximum
     void *light[2];          // n entries of 16 bytes each: light frontier lists (ping-pong)
-    int32_t *done;           // n: finished chunks per long row (by rank), cleared by the colouring
     void *chunk[2];          // color_chunk_pairs entries of 32 bytes each: chunks of long rows
-    unsigned long long *bm;  // color_bitmap_words, zero: colour bitmaps of long rows (left zero)
+    unsigned long long *bm;  // color_bitmap_words: colour bitmaps of long rows
 };
 int64_t color_bitmap_words(const Csr &g);
 int64_t color_chunk_pairs(const Csr &g);
