@@ -249,7 +249,7 @@ void louvain_destroy(louvain_graph_t g);
  *     be NULL).  *out (may be NULL): as louvain_run; its phase and iter arrays
  *     stay valid until the next louvain_run_noalloc call of the same thread.
  * The result equals louvain_init_csr + louvain_run on the same input.  A graph
- * whose handle buffers (about 72 bytes per CSR entry plus 136 per vertex)
+ * whose handle buffers (about 72 bytes per CSR entry plus 160 per vertex)
  * exceed the scratch is refused up front with LOUVAIN_E_INVALID_ARG; buffers
  * sized during the run (hub pair lists, colouring bitmaps) that no longer fit
  * end it with LOUVAIN_E_OOM.  Graphs of up to 65,536 vertices and 524,288 CSR

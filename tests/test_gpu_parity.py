@@ -325,6 +325,58 @@ def test_clique_beyond_4096_colours(L, O):
     gs.close()
 
 
+def boundary_graph(seed):
+    """Rows at the colouring's length limits: vertices of degree exactly 256
+    and 257 (light/long), 1024/1025 and 2048/2049 (one/two/three chunks),
+    a clique of 150 light rows (colours past 64 in a wavefront's bitmap), a
+    clique of 300 long rows (long rows adjacent to long rows in both
+    priority directions) with 100 light vertices tied to 200 of its members
+    each (light rows seeing ~200 colours, long rows with light higher- and
+    lower-priority neighbours), and random edges."""
+    rng = np.random.default_rng(seed)
+    n = 6000
+    edges = set()
+
+    def add(u, v):
+        if u != v:
+            edges.add((min(u, v), max(u, v)))
+
+    for h, d in enumerate((256, 257, 1024, 1025, 2048, 2049, 3000)):
+        for v in rng.choice(np.arange(10, n), size=d, replace=False):
+            add(h, int(v))
+    for a in range(10, 160):
+        for b in range(a + 1, 160):
+            add(a, b)
+    for a in range(200, 500):
+        for b in range(a + 1, 500):
+            add(a, b)
+    for v in range(600, 700):
+        for u in rng.choice(np.arange(200, 500), size=200, replace=False):
+            add(v, int(u))
+    while len(edges) < 140000:
+        u, v = (int(x) for x in rng.integers(10, n, 2))
+        add(u, v)
+    return SG.from_edges(n, sorted(edges), None, name=f"boundary_graph_{seed}")
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_colouring_row_length_boundaries(L, O, seed):
+    g = boundary_graph(seed)
+    deg = np.diff(g.offsets)
+    assert list(deg[:7]) == [256, 257, 1024, 1025, 2048, 2049, 3000]
+    gs = L.Graph.from_csr(g)
+    st = O.state(g)
+    for colouring in range(2):
+        # the second colouring (another seed) reuses the bitmaps and lists
+        seed_c = L.DEFAULT_SEED + colouring
+        assert gs.color(seed_c) == st.color(seed_c)
+        assert np.array_equal(gs.colors(), st.get("color")), f"colours, seed {seed_c}"
+    gs.close()
+    d = dict(vf=0, color=1, color_cutoff=1)
+    res = L.Graph.from_csr(g).run(L.params(**d))
+    compare_run(res, O.run(g, oracle_params(d)), g.name)
+
+
 def test_run_sbm_1000(L, O):
     g = GG.sbm_1000()
     res = L.Graph.from_csr(g).run(L.params())
