@@ -182,17 +182,39 @@ void scan_tagged_weights(const int32_t *a, int32_t tag, const void *w, int wk, i
 }
 
 // ---- radix sort -------------------------------------------------------------
+// Digit counts of one tile.  The tile's keys are loaded before any is
+// counted; the lanes of a wave that share a digit are found with ballots and
+// only the first of them adds their number, so the LDS counters see one
+// update per distinct digit of a round (the high digits of the rebuild's
+// keys, C(u), are shared by whole runs of keys, which serialized per-key
+// atomics on one counter).
 __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint64_t *keys, int64_t n, int shift, int64_t *hist,
                                                       int64_t nb)
 {
     __shared__ int32_t h[256];
+    const int lane = threadIdx.x & 63;
     h[threadIdx.x] = 0;
-    __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RADIX_TILE;
-#pragma unroll 4
+    uint64_t kr[RADIX_ITEMS];
+#pragma unroll
     for (int r = 0; r < RADIX_ITEMS; ++r) {
-        int64_t i = base + r * BLOCK + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+        const int64_t i = base + r * BLOCK + threadIdx.x;
+        kr[r] = i < n ? keys[i] : 0;
+    }
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int r = 0; r < RADIX_ITEMS; ++r) {
+        const bool valid = base + r * BLOCK + threadIdx.x < n;
+        const int d = (int)((kr[r] >> shift) & 255);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int bit = (d >> b) & 1;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        if (valid && (peers & lt_mask) == 0) atomicAdd(&h[d], __popcll(peers));
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
