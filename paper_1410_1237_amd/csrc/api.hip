@@ -236,6 +236,7 @@ struct louvain_graph_s {
     uint64_t *jp_bm = nullptr;              // colour bitmaps of long rows (cleared by each colouring)
     unsigned long long *bal_closed = nullptr; // closed-colour bitmap of the balanced colouring (64 words)
     int64_t jp_chunk_cap = 0, jp_bm_cap = 0;
+    int64_t keys_words = 0;                 // capacity of keys / keys_alt
     int32_t num_colors = 0;
     bool colored = false;
     bool singleton = false; // state is the singleton partition (no commit since init_state)
@@ -943,7 +944,7 @@ louvain_status colored_iteration(G *g, int singlet, SweepSum &sum, lv::SweepStat
 louvain_status coarsen_current(G *g, const int32_t *comm, int64_t &n_new, bool vf = false)
 {
     const int dst = g->cur_buf == 0 ? 1 : 0;
-    lv::CoarsenBufs b{g->flag, g->new_id, g->keys, g->keys_alt, g->vals, g->vals_alt, g->run};
+    lv::CoarsenBufs b{g->flag, g->new_id, g->keys, g->keys_alt, g->vals, g->vals_alt, g->run, g->keys_words};
     int64_t nnz_new = 0;
     {
         ProfScope ps(g, PR_COARSEN, 0, (double)g->cur.nnz);
@@ -1269,6 +1270,7 @@ louvain_status alloc_buffers(G *g, int64_t n, int64_t nnz, bool weighted)
 {
     louvain_status s;
     const int64_t big = (nnz > n ? nnz : n) + 1;
+    g->keys_words = big;
     if ((s = alloc(g, &g->off0, n + 1)) || (s = alloc(g, &g->col0, nnz)) || (s = alloc(g, &g->k0, n)) ||
         (weighted && (s = alloc(g, &g->w0, nnz))))
         return s;

@@ -589,8 +589,30 @@ constexpr int32_t VF_SELF = -3;   // the row's own self-loop
 
 // wself[u]: u's own self-loop; aself[u]: the absorbed vertices' self-loops
 // (zero unless a chain round absorbs vertices that carry one)
+// kept-vertex bitmap of a vertex-following map: bit v & 63 of word v >> 6
+// is set for a kept vertex, and kpre[w] counts the kept vertices before word
+// w, so a kept vertex's new id is kpre[v >> 6] + the set bits below it; the
+// two arrays (12 bytes per 64 vertices) stay in L2 where cmap (4 bytes per
+// vertex) would be a line fetch per entry.  One wavefront per word.
+__global__ __launch_bounds__(BLOCK) void k_keep_bits(const int32_t *flag, const int32_t *new_id, int64_t n,
+                                                     uint64_t *kbits, int32_t *kpre)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (n + 63) / 64;
+    for (int64_t w = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6; w < nw;
+         w += ((int64_t)gridDim.x * BLOCK) >> 6) {
+        const int64_t v = w * 64 + lane;
+        const uint64_t m = __ballot(v < n && flag[v] != 0);
+        if (lane == 0) {
+            kbits[w] = m;
+            kpre[w] = new_id[w * 64];
+        }
+    }
+}
+
 template <int WK>
-__global__ __launch_bounds__(BLOCK) void k_vf_entries(Csr g, const int32_t *map, const int32_t *cmap, int32_t *A,
+__global__ __launch_bounds__(BLOCK) void k_vf_entries(Csr g, const int32_t *map, const int32_t *cmap,
+                                                      const uint64_t *kbits, const int32_t *kpre, int32_t *A,
                                                       int64_t *wself, int64_t *aself)
 {
     __shared__ int64_t s_off[ROWCAP + 1];
@@ -614,7 +636,15 @@ __global__ __launch_bounds__(BLOCK) void k_vf_entries(Csr g, const int32_t *map,
             wself[u] = WLoad<WK>::at(g.w, e);
             continue;
         }
-        const int32_t cv = cmap[v];
+        // the neighbour's new id: from the kept-vertex bitmap when it is kept,
+        // else (an absorbed vertex) from the map
+        int32_t cv;
+        if (kbits) {
+            const uint64_t word = kbits[v >> 6];
+            cv = ((word >> (v & 63)) & 1) ? kpre[v >> 6] + __popcll(word & ((1ull << (v & 63)) - 1)) : cmap[v];
+        } else {
+            cv = cmap[v];
+        }
         A[e] = cv == cmap[u] ? VF_INSIDE : cv;
     }
 }
@@ -730,17 +760,29 @@ hipError_t coarsen_vf(const Csr &g, const int32_t *map, const int64_t *k_in, int
         *nnz_new = 0;
         return hipGetLastError();
     }
-    int32_t *cmap = b.flag; // free after the renumbering scan
-    k_cmap<<<gv, BLOCK, 0, st>>>(map, b.new_id, n, cmap);
+    // the kept-vertex bitmap and word prefixes behind A in the keys buffer
+    // when they fit there (A takes half a word per entry); else every
+    // neighbour's id comes from cmap
     int32_t *A = (int32_t *)b.keys;
+    const int64_t nw = (n + 63) / 64, a_words = (nnz + 1) / 2 + 1;
+    uint64_t *kbits = nullptr;
+    int32_t *kpre = nullptr;
+    if (a_words + nw + (nw + 1) / 2 <= b.keys_words) {
+        kbits = b.keys + a_words;
+        kpre = (int32_t *)(kbits + nw);
+        const int64_t gbw = (nw * 64 + BLOCK - 1) / BLOCK;
+        k_keep_bits<<<(unsigned)(gbw < 65536 ? gbw : 65536), BLOCK, 0, st>>>(b.flag, b.new_id, n, kbits, kpre);
+    }
+    int32_t *cmap = b.flag; // free after the renumbering scan and the bitmap
+    k_cmap<<<gv, BLOCK, 0, st>>>(map, b.new_id, n, cmap);
     int64_t *run = b.vals_alt, *pin = b.vals, *wself = b.run, *kt = (int64_t *)b.keys_alt;
     fill<int64_t>(wself, 0, n, st);
     fill<int64_t>(kt, 0, n, st); // absorbed self-loops first, then the community degrees
     const unsigned ge = grid_for(nnz, ETILE);
     switch (g.wk) {
-    case W_UNIT: k_vf_entries<W_UNIT><<<ge, BLOCK, 0, st>>>(g, map, cmap, A, wself, kt); break;
-    case W_I32: k_vf_entries<W_I32><<<ge, BLOCK, 0, st>>>(g, map, cmap, A, wself, kt); break;
-    default: k_vf_entries<W_I64><<<ge, BLOCK, 0, st>>>(g, map, cmap, A, wself, kt); break;
+    case W_UNIT: k_vf_entries<W_UNIT><<<ge, BLOCK, 0, st>>>(g, map, cmap, kbits, kpre, A, wself, kt); break;
+    case W_I32: k_vf_entries<W_I32><<<ge, BLOCK, 0, st>>>(g, map, cmap, kbits, kpre, A, wself, kt); break;
+    default: k_vf_entries<W_I64><<<ge, BLOCK, 0, st>>>(g, map, cmap, kbits, kpre, A, wself, kt); break;
     }
     scan_nonneg(A, run, nnz, run + nnz, s, st);
     scan_tagged_weights(A, VF_INSIDE, g.w, g.wk, pin, nnz, pin + nnz, s, st);

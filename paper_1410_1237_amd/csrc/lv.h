@@ -213,6 +213,7 @@ struct CoarsenBufs {
     uint64_t *keys, *keys_alt;
     int64_t *vals, *vals_alt;
     int64_t *run;        // nnz (run id of each sorted entry)
+    int64_t keys_words;  // capacity of keys (and keys_alt) in 64-bit words
 };
 // builds the community graph of g under comm into (off_out, col_out, w_out)
 // with its weighted degrees k_out and stats = {2m, max degree, self-loop
