@@ -1175,7 +1175,9 @@ void commit_hubs(const SweepArgs &a, const HubArgs &h, const int32_t *list, int6
     // the class's hubs are its last positions
     const int64_t nhub = (h.e > h.s) ? h.e - h.s : 0;
     const int64_t nplain = count - nhub;
-    unsigned nb = grid_for(nplain > 0 ? nplain : 1, BLOCK * 4);
+    // one vertex per thread: a commit is a short chain of dependent reads
+    // and atomics, and a class is small
+    unsigned nb = grid_for(nplain > 0 ? nplain : 1, BLOCK);
     if (nb > 65536) nb = 65536;
     unsigned nh = nhub ? grid_for(nhub, BLOCK / 64) : 0;
     if (nh > 1024) nh = 1024;
