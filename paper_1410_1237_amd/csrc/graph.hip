@@ -410,23 +410,100 @@ __global__ __launch_bounds__(BLOCK) void k_cmap(const int32_t *comm, const int32
         cmap[v] = new_id[comm[v]];
 }
 
-template <int WK, bool HV>
-__global__ __launch_bounds__(BLOCK) void k_coarse_keys(Csr g, const int32_t *cmap, int bits, uint64_t *keys,
-                                                       int64_t *vals)
+// The rebuild's (C(u) << bits | C(v), w) pairs, summed per key inside each
+// tile of PAIR_TILE consecutive entries before the sort: after a phase most
+// neighbours of a row (and of the rows around it) fall into a few
+// communities, so a tile holds far fewer distinct keys than entries (about a
+// sixth on R-MAT after its first phase), and the radix sort and everything
+// after it run over the tile sums.  Equal keys of different tiles stay
+// separate here and are summed with the runs after the sort (integer sums,
+// so the coarse graph does not depend on the order in which tiles append).
+// Each tile sums in an LDS table with twice as many slots as entries (linear
+// probing, ~0 marks a free slot: keys are below 2^62), then appends its
+// distinct keys behind an atomic counter.
+constexpr int PAIR_ITEMS = 4;
+constexpr int PAIR_TILE = BLOCK * PAIR_ITEMS;
+constexpr int PAIR_SLOTS = 2 * PAIR_TILE;
+constexpr int PAIR_SHIFT = 64 - 11; // log2(PAIR_SLOTS) = 11
+static_assert(PAIR_SLOTS == 1 << 11, "table index bits");
+constexpr uint64_t PAIR_FREE = ~0ull;
+
+template <int WK>
+__global__ __launch_bounds__(BLOCK) void k_coarse_pairs(Csr g, const int32_t *cmap, int bits, uint64_t *keys,
+                                                        int64_t *vals, unsigned long long *count)
 {
     __shared__ int64_t s_off[ROWCAP + 1];
     __shared__ int64_t s_meta[2];
-    const int64_t e0 = (int64_t)blockIdx.x * ETILE;
-    const int64_t e1 = min(e0 + ETILE, g.nnz) - 1;
-    TileRows t = tile_rows(g.off, g.n, e0, e1, s_off, s_meta);
-    for (int r = 0; r < EITEMS; ++r) {
-        const int64_t e = e0 + r * BLOCK + threadIdx.x;
-        if (e > e1) break;
-        const int64_t u = tile_row(t, g.off, s_off, e);
-        const uint64_t cu = (uint32_t)cmap[u];
-        const uint64_t cv = (uint32_t)cmap[g.col[e]];
-        keys[e] = (cu << bits) | cv;
-        if (HV) vals[e] = WLoad<WK>::at(g.w, e);
+    __shared__ uint64_t s_key[PAIR_SLOTS];
+    __shared__ int64_t s_w[PAIR_SLOTS];
+    __shared__ int32_t s_wsum[BLOCK / 64];
+    __shared__ unsigned long long s_base;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (int j = tid; j < PAIR_SLOTS; j += BLOCK) {
+        s_key[j] = PAIR_FREE;
+        s_w[j] = 0;
+    }
+    const int64_t e0 = (int64_t)blockIdx.x * PAIR_TILE;
+    const int64_t e1 = min(e0 + PAIR_TILE, g.nnz) - 1;
+    TileRows t = tile_rows(g.off, g.n, e0, e1, s_off, s_meta); // ends with a block barrier
+    // the tile's keys, every gather issued before any insertion
+    uint64_t key[PAIR_ITEMS];
+    int64_t w[PAIR_ITEMS];
+#pragma unroll
+    for (int r = 0; r < PAIR_ITEMS; ++r) {
+        const int64_t e = e0 + r * BLOCK + tid;
+        key[r] = PAIR_FREE;
+        w[r] = 0;
+        if (e <= e1) {
+            const int64_t u = tile_row(t, g.off, s_off, e);
+            key[r] = ((uint64_t)(uint32_t)cmap[u] << bits) | (uint64_t)(uint32_t)cmap[g.col[e]];
+            w[r] = WLoad<WK>::at(g.w, e);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < PAIR_ITEMS; ++r) {
+        if (key[r] == PAIR_FREE) continue;
+        uint32_t slot = (uint32_t)((key[r] * 0x9E3779B97F4A7C15ull) >> PAIR_SHIFT);
+        for (;;) {
+            uint64_t cur = s_key[slot];
+            if (cur == PAIR_FREE) cur = atomicCAS((unsigned long long *)&s_key[slot], PAIR_FREE, key[r]);
+            if (cur == PAIR_FREE || cur == key[r]) {
+                atomicAdd((unsigned long long *)&s_w[slot], (unsigned long long)w[r]);
+                break;
+            }
+            slot = (slot + 1) & (PAIR_SLOTS - 1);
+        }
+    }
+    __syncthreads();
+    // append: thread tid owns the slots [tid * SPT, (tid + 1) * SPT)
+    constexpr int SPT = PAIR_SLOTS / BLOCK;
+    int32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) c += s_key[tid * SPT + i] != PAIR_FREE;
+    int32_t inc = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) s_wsum[wid] = inc;
+    __syncthreads();
+    int32_t pre = inc - c, total = 0;
+#pragma unroll
+    for (int v = 0; v < BLOCK / 64; ++v) {
+        if (v < wid) pre += s_wsum[v];
+        total += s_wsum[v];
+    }
+    if (tid == 0) s_base = atomicAdd(count, (unsigned long long)total);
+    __syncthreads();
+    int64_t pos = (int64_t)s_base + pre;
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) {
+        const uint64_t k = s_key[tid * SPT + i];
+        if (k == PAIR_FREE) continue;
+        keys[pos] = k;
+        vals[pos] = s_w[tid * SPT + i];
+        ++pos;
     }
 }
 
@@ -523,29 +600,30 @@ hipError_t coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t
         return hipGetLastError();
     }
     const int bits = bits_for(nn > 1 ? nn : 2);
-    const bool hv = g.wk != W_UNIT;
     int32_t *cmap = b.flag; // free after the renumbering scan
     k_cmap<<<gv, BLOCK, 0, st>>>(comm, b.new_id, n, cmap);
-    unsigned ge = grid_for(nnz, ETILE);
+    // tile-summed pairs (np of them) into keys / vals
+    fill<int64_t>(s.scalar, 0, 1, st);
+    const unsigned ge = grid_for(nnz, PAIR_TILE);
+    unsigned long long *cnt = (unsigned long long *)s.scalar;
     switch (g.wk) {
-    case W_UNIT: k_coarse_keys<W_UNIT, false><<<ge, BLOCK, 0, st>>>(g, cmap, bits, b.keys, nullptr); break;
-    case W_I32: k_coarse_keys<W_I32, true><<<ge, BLOCK, 0, st>>>(g, cmap, bits, b.keys, b.vals); break;
-    default: k_coarse_keys<W_I64, true><<<ge, BLOCK, 0, st>>>(g, cmap, bits, b.keys, b.vals); break;
+    case W_UNIT: k_coarse_pairs<W_UNIT><<<ge, BLOCK, 0, st>>>(g, cmap, bits, b.keys, b.vals, cnt); break;
+    case W_I32: k_coarse_pairs<W_I32><<<ge, BLOCK, 0, st>>>(g, cmap, bits, b.keys, b.vals, cnt); break;
+    default: k_coarse_pairs<W_I64><<<ge, BLOCK, 0, st>>>(g, cmap, bits, b.keys, b.vals, cnt); break;
     }
-    radix_sort(b.keys, b.keys_alt, hv ? b.vals : nullptr, b.vals_alt, nnz, 2 * bits, s, st);
-    scan_heads(b.keys, b.run, nnz, s.scalar, s, st);
+    int64_t np = 0;
+    if (const hipError_t e = read_back(&np, s.scalar, st)) return e;
+    radix_sort(b.keys, b.keys_alt, b.vals, b.vals_alt, np, 2 * bits, s, st);
+    scan_heads(b.keys, b.run, np, s.scalar, s, st);
     int64_t nruns = 0;
     if (const hipError_t e = read_back(&nruns, s.scalar, st)) return e;
-    int64_t *rstart = b.vals_alt; // free after the sort; nnz + 1 entries
-    unsigned gr = grid_for(nnz, BLOCK * 4);
+    int64_t *rstart = b.vals_alt; // free after the sort; np + 1 entries
+    unsigned gr = grid_for(np, BLOCK * 4);
     if (gr > 65536) gr = 65536;
-    k_runs<<<gr, BLOCK, 0, st>>>(b.keys, b.run, nnz, bits, rstart, col_out);
-    fill<int64_t>(rstart + nruns, nnz, 1, st);
-    int64_t *pref = nullptr;
-    if (hv) {
-        pref = (int64_t *)b.keys_alt; // exclusive prefix of the sorted weights, nnz + 1 entries
-        scan_i64(b.vals, pref, nnz, pref + nnz, s, st);
-    }
+    k_runs<<<gr, BLOCK, 0, st>>>(b.keys, b.run, np, bits, rstart, col_out);
+    fill<int64_t>(rstart + nruns, np, 1, st);
+    int64_t *pref = (int64_t *)b.keys_alt; // exclusive prefix of the sorted weights, np + 1 entries
+    scan_i64(b.vals, pref, np, pref + np, s, st);
     unsigned gw = grid_for(nruns, BLOCK * 4);
     if (gw > 65536) gw = 65536;
     rep_clear(s.rep, st);
@@ -564,12 +642,8 @@ hipError_t coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t
         if (gm > 4096) gm = 4096;
         k_max<<<gm, BLOCK, 0, st>>>(k_out, nn, stats + 1);
     }
-    if (pref) {
-        if (const hipError_t e = hipMemcpyAsync(stats, pref + nnz, sizeof(int64_t), hipMemcpyDeviceToDevice, st))
-            return e;
-    } else {
-        fill<int64_t>(stats, nnz, 1, st);
-    }
+    if (const hipError_t e = hipMemcpyAsync(stats, pref + np, sizeof(int64_t), hipMemcpyDeviceToDevice, st))
+        return e;
     rep_fold(s.rep, 1, stats + 2, st);
     return hipGetLastError();
 }
