@@ -151,6 +151,33 @@ __global__ __launch_bounds__(BLOCK) void k_degrees(Csr g, int64_t *k, int64_t *r
     }
 }
 
+// unit weights, no column check: k_v is the row length, and the columns of
+// a row are strictly ascending, so its self-loop is found by a binary search
+// of the row for v (a thread per row; 2m and the self-loop count into the
+// replicated counters 0 and 2)
+__global__ __launch_bounds__(BLOCK) void k_degrees_unit(Csr g, int64_t *k, int64_t *rep)
+{
+    __shared__ int64_t s_red[BLOCK / 64];
+    int64_t tot = 0, self = 0;
+    for (int64_t v = (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < g.n; v += (int64_t)gridDim.x * BLOCK) {
+        int64_t lo = g.off[v], hi = g.off[v + 1];
+        k[v] = hi - lo;
+        tot += hi - lo;
+        while (lo < hi) { // first column >= v
+            const int64_t mid = (lo + hi) >> 1;
+            if (g.col[mid] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < g.off[v + 1] && g.col[lo] == v) ++self;
+    }
+    tot = block_total(tot, s_red);
+    self = block_total(self, s_red);
+    if (threadIdx.x == 0) {
+        rep_add(rep, 0, tot);
+        rep_add(rep, 2, self);
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void k_max(const int64_t *k, int64_t n, int64_t *out)
 {
     __shared__ int64_t s[BLOCK / 64];
@@ -201,7 +228,11 @@ void degrees(const Csr &g, int64_t *k, int64_t *stats, Scratch &s, hipStream_t s
     fill<int64_t>(k, 0, g.n, st);
     fill<int64_t>(stats, 0, 3, st);
     rep_clear(s.rep, st);
-    if (g.nnz > 0) {
+    if (g.nnz > 0 && g.wk == W_UNIT && !range_flag) {
+        unsigned gn = grid_for(g.n, BLOCK * 4);
+        if (gn > 65536) gn = 65536;
+        k_degrees_unit<<<gn, BLOCK, 0, st>>>(g, k, s.rep);
+    } else if (g.nnz > 0) {
         unsigned ge = grid_for(g.nnz, ETILE);
         switch (g.wk) {
         case W_UNIT: k_degrees<W_UNIT><<<ge, BLOCK, 0, st>>>(g, k, s.rep, range_flag); break;
@@ -410,6 +441,29 @@ __global__ __launch_bounds__(BLOCK) void k_cmap(const int32_t *comm, const int32
         cmap[v] = new_id[comm[v]];
 }
 
+// The rebuild's keys, one per CSR entry (the sort's input when the tile sums
+// below would not shrink it: keys only for unit weights, whose run lengths
+// are the weights)
+template <int WK, bool HV>
+__global__ __launch_bounds__(BLOCK) void k_coarse_keys(Csr g, const int32_t *cmap, int bits, uint64_t *keys,
+                                                       int64_t *vals)
+{
+    __shared__ int64_t s_off[ROWCAP + 1];
+    __shared__ int64_t s_meta[2];
+    const int64_t e0 = (int64_t)blockIdx.x * ETILE;
+    const int64_t e1 = min(e0 + ETILE, g.nnz) - 1;
+    TileRows t = tile_rows(g.off, g.n, e0, e1, s_off, s_meta);
+    for (int r = 0; r < EITEMS; ++r) {
+        const int64_t e = e0 + r * BLOCK + threadIdx.x;
+        if (e > e1) break;
+        const int64_t u = tile_row(t, g.off, s_off, e);
+        const uint64_t cu = (uint32_t)cmap[u];
+        const uint64_t cv = (uint32_t)cmap[g.col[e]];
+        keys[e] = (cu << bits) | cv;
+        if (HV) vals[e] = WLoad<WK>::at(g.w, e);
+    }
+}
+
 // The rebuild's (C(u) << bits | C(v), w) pairs, summed per key inside each
 // tile of PAIR_TILE consecutive entries before the sort: after a phase most
 // neighbours of a row (and of the rows around it) fall into a few
@@ -577,7 +631,7 @@ static int bits_for(int64_t n)
 
 hipError_t coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_orig, CoarsenBufs &b,
                    int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *k_out, int64_t *stats, int64_t *n_new,
-                   int64_t *nnz_new, Scratch &s, hipStream_t st)
+                   int64_t *nnz_new, Scratch &s, hipStream_t st, bool tile_sums)
 {
     fill<int64_t>(stats, 0, 3, st);
     const int64_t n = g.n, nnz = g.nnz;
@@ -602,18 +656,30 @@ hipError_t coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t
     const int bits = bits_for(nn > 1 ? nn : 2);
     int32_t *cmap = b.flag; // free after the renumbering scan
     k_cmap<<<gv, BLOCK, 0, st>>>(comm, b.new_id, n, cmap);
-    // tile-summed pairs (np of them) into keys / vals
-    fill<int64_t>(s.scalar, 0, 1, st);
-    const unsigned ge = grid_for(nnz, PAIR_TILE);
-    unsigned long long *cnt = (unsigned long long *)s.scalar;
-    switch (g.wk) {
-    case W_UNIT: k_coarse_pairs<W_UNIT><<<ge, BLOCK, 0, st>>>(g, cmap, bits, b.keys, b.vals, cnt); break;
-    case W_I32: k_coarse_pairs<W_I32><<<ge, BLOCK, 0, st>>>(g, cmap, bits, b.keys, b.vals, cnt); break;
-    default: k_coarse_pairs<W_I64><<<ge, BLOCK, 0, st>>>(g, cmap, bits, b.keys, b.vals, cnt); break;
+    // the sort's np (key, weight) pairs: tile sums, or one per entry (keys
+    // only for unit weights: hv false, weights are run lengths)
+    int64_t np = nnz;
+    bool hv = true;
+    if (tile_sums) {
+        fill<int64_t>(s.scalar, 0, 1, st);
+        const unsigned gp = grid_for(nnz, PAIR_TILE);
+        unsigned long long *cnt = (unsigned long long *)s.scalar;
+        switch (g.wk) {
+        case W_UNIT: k_coarse_pairs<W_UNIT><<<gp, BLOCK, 0, st>>>(g, cmap, bits, b.keys, b.vals, cnt); break;
+        case W_I32: k_coarse_pairs<W_I32><<<gp, BLOCK, 0, st>>>(g, cmap, bits, b.keys, b.vals, cnt); break;
+        default: k_coarse_pairs<W_I64><<<gp, BLOCK, 0, st>>>(g, cmap, bits, b.keys, b.vals, cnt); break;
+        }
+        if (const hipError_t e = read_back(&np, s.scalar, st)) return e;
+    } else {
+        hv = g.wk != W_UNIT;
+        const unsigned ge = grid_for(nnz, ETILE);
+        switch (g.wk) {
+        case W_UNIT: k_coarse_keys<W_UNIT, false><<<ge, BLOCK, 0, st>>>(g, cmap, bits, b.keys, nullptr); break;
+        case W_I32: k_coarse_keys<W_I32, true><<<ge, BLOCK, 0, st>>>(g, cmap, bits, b.keys, b.vals); break;
+        default: k_coarse_keys<W_I64, true><<<ge, BLOCK, 0, st>>>(g, cmap, bits, b.keys, b.vals); break;
+        }
     }
-    int64_t np = 0;
-    if (const hipError_t e = read_back(&np, s.scalar, st)) return e;
-    radix_sort(b.keys, b.keys_alt, b.vals, b.vals_alt, np, 2 * bits, s, st);
+    radix_sort(b.keys, b.keys_alt, hv ? b.vals : nullptr, b.vals_alt, np, 2 * bits, s, st);
     scan_heads(b.keys, b.run, np, s.scalar, s, st);
     int64_t nruns = 0;
     if (const hipError_t e = read_back(&nruns, s.scalar, st)) return e;
@@ -622,8 +688,11 @@ hipError_t coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t
     if (gr > 65536) gr = 65536;
     k_runs<<<gr, BLOCK, 0, st>>>(b.keys, b.run, np, bits, rstart, col_out);
     fill<int64_t>(rstart + nruns, np, 1, st);
-    int64_t *pref = (int64_t *)b.keys_alt; // exclusive prefix of the sorted weights, np + 1 entries
-    scan_i64(b.vals, pref, np, pref + np, s, st);
+    int64_t *pref = nullptr;
+    if (hv) {
+        pref = (int64_t *)b.keys_alt; // exclusive prefix of the sorted weights, np + 1 entries
+        scan_i64(b.vals, pref, np, pref + np, s, st);
+    }
     unsigned gw = grid_for(nruns, BLOCK * 4);
     if (gw > 65536) gw = 65536;
     rep_clear(s.rep, st);
@@ -642,8 +711,12 @@ hipError_t coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t
         if (gm > 4096) gm = 4096;
         k_max<<<gm, BLOCK, 0, st>>>(k_out, nn, stats + 1);
     }
-    if (const hipError_t e = hipMemcpyAsync(stats, pref + np, sizeof(int64_t), hipMemcpyDeviceToDevice, st))
-        return e;
+    if (pref) {
+        if (const hipError_t e = hipMemcpyAsync(stats, pref + np, sizeof(int64_t), hipMemcpyDeviceToDevice, st))
+            return e;
+    } else {
+        fill<int64_t>(stats, np, 1, st);
+    }
     rep_fold(s.rep, 1, stats + 2, st);
     return hipGetLastError();
 }

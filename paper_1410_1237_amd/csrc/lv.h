@@ -229,7 +229,10 @@ hipError_t coarsen_vf(const Csr &g, const int32_t *map, const int64_t *k_in, int
                       int64_t *stats, int64_t *n_new, int64_t *nnz_new, Scratch &s, hipStream_t st);
 hipError_t coarsen(const Csr &g, const int32_t *comm, int32_t *orig_map, int64_t n_orig, CoarsenBufs &b,
                    int64_t *off_out, int32_t *col_out, int64_t *w_out, int64_t *k_out, int64_t *stats, int64_t *n_new,
-                   int64_t *nnz_new, Scratch &s, hipStream_t st);
+                   int64_t *nnz_new, Scratch &s, hipStream_t st, bool tile_sums);
+// tile_sums: sum the (C(u), C(v)) pairs per tile of entries before the sort
+// (pays when the partition folds many entries onto few pairs; the output is
+// the same either way)
 // expands weights of g to int64
 void weights_i64(const Csr &g, int64_t *w_out, hipStream_t st);
 

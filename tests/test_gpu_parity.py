@@ -500,6 +500,20 @@ def test_graph_capture_modes(L, O, mode, monkeypatch):
         compare_run(res, O.run(g, oracle.Params(**p)), f"graphs={mode} {g.name}")
 
 
+@pytest.mark.parametrize("mode", ["0", "1"])
+def test_rebuild_tile_sums_modes(L, O, mode, monkeypatch):
+    """The rebuild with its pairs summed per tile before the sort (1) and with
+    one key per entry (0) give the oracle's coarse graphs, step by step and
+    over whole runs, for unit and weighted graphs."""
+    monkeypatch.setenv("LOUVAIN_TILE_SUMS", mode)
+    for g in (GG.sbm_1000(), GG.rmat(12, 8, seed=5), GG.rmat(13, 16, wmax=100, seed=6), hub_graph()):
+        print(f"[parity] tile_sums={mode} {g.name} n={g.n}", flush=True)
+        _steps(L, O, g, colored=False, vf=False, phases=3, iters=4)
+        for d in (dict(), dict(vf=1, color=1, color_cutoff=1)):
+            res = L.Graph.from_csr(g).run(L.params(**d))
+            compare_run(res, O.run(g, oracle.Params(**d)), f"tile_sums={mode} {g.name} {d}")
+
+
 def test_autotune_does_not_change_results(L, O, monkeypatch):
     """Lanes per vertex chosen by the tuner (a graph with bins above the
     tuning size) versus the defaults: identical runs, equal to the oracle."""
