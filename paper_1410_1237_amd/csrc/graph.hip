@@ -151,10 +151,22 @@ __global__ __launch_bounds__(BLOCK) void k_degrees(Csr g, int64_t *k, int64_t *r
     }
 }
 
-// unit weights, no column check: k_v is the row length, and the columns of
+// flag = 2 if a column lies outside [0, n)
+__global__ __launch_bounds__(BLOCK) void k_col_range(const int32_t *col, int64_t nnz, int64_t n, int32_t *flag)
+{
+    bool bad = false;
+    for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * BLOCK) {
+        const int32_t c = col[e];
+        bad |= c < 0 || c >= n;
+    }
+    if (bad) atomicCAS(flag, 0, 2);
+}
+
+// unit weights: k_v is the row length, and the columns of
 // a row are strictly ascending, so its self-loop is found by a binary search
 // of the row for v (a thread per row; 2m and the self-loop count into the
-// replicated counters 0 and 2)
+// replicated counters 0 and 2).  No column is used as an index, so this is
+// safe before the column check has run.
 __global__ __launch_bounds__(BLOCK) void k_degrees_unit(Csr g, int64_t *k, int64_t *rep)
 {
     __shared__ int64_t s_red[BLOCK / 64];
@@ -228,7 +240,12 @@ void degrees(const Csr &g, int64_t *k, int64_t *stats, Scratch &s, hipStream_t s
     fill<int64_t>(k, 0, g.n, st);
     fill<int64_t>(stats, 0, 3, st);
     rep_clear(s.rep, st);
-    if (g.nnz > 0 && g.wk == W_UNIT && !range_flag) {
+    if (g.nnz > 0 && g.wk == W_UNIT) {
+        if (range_flag) { // the column check, a stream over the columns
+            unsigned gc = grid_for(g.nnz, BLOCK * 16);
+            if (gc > 65536) gc = 65536;
+            k_col_range<<<gc, BLOCK, 0, st>>>(g.col, g.nnz, g.n, range_flag);
+        }
         unsigned gn = grid_for(g.n, BLOCK * 4);
         if (gn > 65536) gn = 65536;
         k_degrees_unit<<<gn, BLOCK, 0, st>>>(g, k, s.rep);
