@@ -383,6 +383,15 @@ int64_t radix_partials_needed(int64_t n)
 }
 
 // hist region after the scan partials in s.part: s.part[hist_base ...]
+__global__ __launch_bounds__(BLOCK) void k_copy_back(const uint64_t *src_k, uint64_t *keys, const int64_t *src_v,
+                                                     int64_t *vals, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLOCK) {
+        keys[i] = src_k[i];
+        if (src_v) vals[i] = src_v[i];
+    }
+}
+
 void radix_sort(uint64_t *keys, uint64_t *keys_alt, int64_t *vals, int64_t *vals_alt, int64_t n, int bits,
                 Scratch &s, hipStream_t st)
 {
@@ -405,8 +414,11 @@ void radix_sort(uint64_t *keys, uint64_t *keys_alt, int64_t *vals, int64_t *vals
         int64_t *tv = src_v; src_v = dst_v; dst_v = tv;
     }
     if (src_k != keys) {
-        hipMemcpyAsync(keys, src_k, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, st);
-        if (vals) hipMemcpyAsync(vals, src_v, n * sizeof(int64_t), hipMemcpyDeviceToDevice, st);
+        // an odd number of passes ends in the alternate buffers: copied back
+        // by a kernel, so that a failure shows in the caller's launch check
+        unsigned gc = grid_for(n, BLOCK * 8);
+        if (gc > 65536) gc = 65536;
+        k_copy_back<<<gc, BLOCK, 0, st>>>(src_k, keys, vals ? src_v : nullptr, vals, n);
     }
 }
 
