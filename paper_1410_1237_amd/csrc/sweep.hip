@@ -1104,29 +1104,78 @@ void gather_i64(const int64_t *src, const int64_t *idx, int64_t n, int64_t *out,
 }
 
 // ---- community totals (Eq. 2) for movers ------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_commit(const int32_t *verts, int64_t count, int32_t *comm_prev,
-                                                  const int32_t *comm_next, const int64_t *k, int64_t *a,
-                                                  int32_t *size)
+// The moves of one workgroup's BLOCK vertices (positions t of the list),
+// their community degree and size changes summed per community in LDS before
+// the device atomics: a community that many movers enter or leave (a hub's)
+// takes one update per workgroup instead of one per mover.  Called by the
+// whole block; integer sums, so the result does not depend on the grouping.
+constexpr int COMMIT_SLOTS = 4 * BLOCK; // two keys per mover: at most half full
+struct CommitLds {
+    int32_t key[COMMIT_SLOTS];
+    long long da[COMMIT_SLOTS];
+    int32_t dn[COMMIT_SLOTS];
+};
+
+__device__ __forceinline__ void commit_lds_add(CommitLds &L, int32_t c, long long da, int32_t dn)
 {
-    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < count; t += (int64_t)gridDim.x * BLOCK) {
+    uint32_t slot = ((uint32_t)c * 2654435761u) & (COMMIT_SLOTS - 1);
+    for (;;) {
+        int32_t cur = L.key[slot];
+        if (cur == -1) cur = atomicCAS(&L.key[slot], -1, c);
+        if (cur == -1 || cur == c) {
+            atomicAdd((unsigned long long *)&L.da[slot], (unsigned long long)da);
+            atomicAdd(&L.dn[slot], dn);
+            return;
+        }
+        slot = (slot + 1) & (COMMIT_SLOTS - 1);
+    }
+}
+
+__device__ __forceinline__ void commit_tile(const int32_t *verts, int64_t t, int64_t count, int32_t *comm_prev,
+                                            const int32_t *comm_next, const int64_t *k, int64_t *a, int32_t *size,
+                                            CommitLds &L)
+{
+    static_assert((COMMIT_SLOTS & (COMMIT_SLOTS - 1)) == 0, "power-of-two table");
+    for (int j = threadIdx.x; j < COMMIT_SLOTS; j += BLOCK) {
+        L.key[j] = -1;
+        L.da[j] = 0;
+        L.dn[j] = 0;
+    }
+    __syncthreads();
+    if (t < count) {
         const int32_t i = verts ? verts[t] : (int32_t)t;
         const int32_t A = comm_prev[i], B = comm_next[i];
         if (A != B) {
             const int64_t ki = k[i];
-            atomicAdd((unsigned long long *)&a[A], (unsigned long long)(-ki));
-            atomicAdd((unsigned long long *)&a[B], (unsigned long long)ki);
-            atomicSub(&size[A], 1);
-            atomicAdd(&size[B], 1);
+            commit_lds_add(L, A, -ki, -1);
+            commit_lds_add(L, B, ki, 1);
             comm_prev[i] = B;
         }
     }
+    __syncthreads();
+    for (int j = threadIdx.x; j < COMMIT_SLOTS; j += BLOCK) {
+        const int32_t c = L.key[j];
+        if (c < 0) continue;
+        if (L.da[j]) atomicAdd((unsigned long long *)&a[c], (unsigned long long)L.da[j]);
+        if (L.dn[j]) atomicAdd(&size[c], L.dn[j]);
+    }
+    __syncthreads(); // the table is cleared for the next tile
+}
+
+__global__ __launch_bounds__(BLOCK) void k_commit(const int32_t *verts, int64_t count, int32_t *comm_prev,
+                                                  const int32_t *comm_next, const int64_t *k, int64_t *a,
+                                                  int32_t *size)
+{
+    __shared__ CommitLds L;
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < count; base += (int64_t)gridDim.x * BLOCK)
+        commit_tile(verts, base + threadIdx.x, count, comm_prev, comm_next, k, a, size, L);
 }
 
 void commit(const int32_t *verts, int64_t count, int32_t *comm_prev, const int32_t *comm_next, const int64_t *k,
             int64_t *a, int32_t *size, hipStream_t st)
 {
     if (count <= 0) return;
-    unsigned gc = grid_for(count, BLOCK * 4);
+    unsigned gc = grid_for(count, BLOCK);
     if (gc > 65536) gc = 65536;
     k_commit<<<gc, BLOCK, 0, st>>>(verts, count, comm_prev, comm_next, k, a, size);
 }
@@ -1155,10 +1204,9 @@ __global__ __launch_bounds__(BLOCK) void k_commit_hubs(SweepArgs a, HubArgs h, c
     int64_t *ca = const_cast<int64_t *>(a.a);
     int32_t *size = const_cast<int32_t *>(a.size);
     if (blockIdx.x < nb) {
-        for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < nplain; t += (int64_t)nb * BLOCK) {
-            const int32_t i = list[t];
-            commit_one(i, a.comm_next[i], comm_prev, a.k, ca, size);
-        }
+        __shared__ CommitLds L;
+        for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < nplain; base += (int64_t)nb * BLOCK)
+            commit_tile(list, base + threadIdx.x, nplain, comm_prev, a.comm_next, a.k, ca, size, L);
         return;
     }
     const int64_t nw = (int64_t)(gridDim.x - nb) * (BLOCK / 64);
