@@ -398,9 +398,9 @@ louvain_status sync(G *g)
 
 // ---- profiling ----------------------------------------------------------------
 const char *kNames[] = {"sweep_small_bins1to5", "sweep_large_bins6to8_hub_partition", "sweep_all_bins_small_group",
-                        "sweep_hub_aggregate_decide", "commit", "coarsen", "color"};
+                        "sweep_hub_aggregate_decide", "commit", "coarsen", "color", "sweep_pack_communities"};
 enum { PR_SMALL = 0, PR_LARGE = 1, PR_ALL = 2, PR_HUB_AGG = 3, PR_COMMIT = 4, PR_COARSEN = 5, PR_COLOR = 6,
-       PR_COUNT = 7 };
+       PR_PACK = 7, PR_COUNT = 8 };
 constexpr double SMALL_GROUP = 65536; // vertices: one fused launch below this
 
 hipEvent_t take_event(G *g)
@@ -719,10 +719,12 @@ lv::SweepArgs sweep_args(G *g, int singlet)
     return a;
 }
 
-// decide_hubs = false: the hub decisions are left to the commit of the group
-void sweep_group(G *g, int group, int singlet, bool decide_hubs = true)
+// decide_hubs = false: the hub decisions are left to the commit of the group.
+// plain: a synchronous sweep of every vertex (no colour classes), whose
+// community totals stay fixed during the launches
+void sweep_group(G *g, int group, int singlet, bool decide_hubs = true, bool plain = false)
 {
-    const lv::SweepArgs a = sweep_args(g, singlet);
+    lv::SweepArgs a = sweep_args(g, singlet);
     const bool wide = wide_gains(g);
     const bool narrow = g->kmax <= (int64_t)UINT32_MAX; // hub sums e <= k_i fit 32 bits
     lv::FusedBins f;
@@ -742,6 +744,14 @@ void sweep_group(G *g, int group, int singlet, bool decide_hubs = true)
         ProfScope ps(g, PR_ALL, cnt_small + cnt_large, 0, 0x7fe);
         lv::sweep_all(a, f, h, wide, narrow, g->st);
     } else {
+        if (plain && !g->singleton && !g->b_gid && !wide && g->two_m <= (int64_t)UINT32_MAX) {
+            // each vertex's community and that community's total, side by
+            // side, so that the rows of bins 1..8 read both in one gather
+            // (keys_alt is free between the binning and the rebuild)
+            ProfScope ps(g, PR_PACK, 20.0 * (double)g->cur.n, 0);
+            lv::pack_communities(g->comm_prev, g->a, g->cur.n, g->keys_alt, g->st);
+            a.cpack = g->keys_alt;
+        }
         {
             ProfScope ps(g, PR_SMALL, cnt_small, 0, 0x3e);
             lv::sweep_small(a, f, wide, g->st);
@@ -1149,7 +1159,7 @@ louvain_status run_phase_plain(G *g, const louvain_params *p, louvain_ratio th, 
     int t_end = 0;
     for (int s_idx = 1;; ++s_idx) {
         lv::clear_stats(g->stats, lv::NBINS * lv::STAT_REP, g->st);
-        sweep_group(g, 0, p->singlet_rule);
+        sweep_group(g, 0, p->singlet_rule, true, true);
         SweepSum sum;
         if ((s = read_stats(g, sum, host))) return s;
         prof_collect(g, host, wbytes(g->cur));
@@ -1530,7 +1540,7 @@ louvain_status louvain_sweep(louvain_graph_t g, const louvain_params *p, louvain
         if ((s = colored_iteration(g, p->singlet_rule, sum, host))) return s;
     } else {
         lv::clear_stats(g->stats, lv::NBINS * lv::STAT_REP, g->st);
-        sweep_group(g, 0, p->singlet_rule);
+        sweep_group(g, 0, p->singlet_rule, true, true);
         if ((s = read_stats(g, sum, host))) return s;
         prof_collect(g, host, wbytes(g->cur));
         commit_all(g);

@@ -283,6 +283,12 @@ struct SweepArgs {
     int64_t two_m = 0;
     int singlet = 1;
     int singleton = 0;              // every community is its own vertex (comm_prev[j] == j)
+    // (C(j), a_C(j)) of every vertex, C in the low and a in the high 32 bits,
+    // or null.  Set only where the totals cannot change during the launch (a
+    // plain sweep) and 2m < 2^32 (so a_c and every e_{i->c} fit 32 bits):
+    // the rows of bins 1..8 then read a neighbour's community and its total
+    // in one gather.
+    const uint64_t *cpack = nullptr;
     SweepStats *stats = nullptr;
     // batched graphs (gid == null for a single graph): per-vertex graph id,
     // per-graph 2m, per-graph "sweeping" flag and per-graph stats (8 int64
@@ -372,6 +378,8 @@ constexpr int kLaneChoices[9][4] = {{0}, {4, 8, 0}, {8, 4, 16, 0}, {16, 8, 32, 0
 // large: bins 6..8 plus hub pass 1; all: bins 1..8 plus hub pass 1 (small
 // groups); then hub pass 2 and, in a launch of its own, the hub decisions
 // (stats in a.stats).
+// out[j] = C(j) | a_C(j) << 32 for the packed gathers (SweepArgs::cpack)
+void pack_communities(const int32_t *comm, const int64_t *a, int64_t n, uint64_t *out, hipStream_t st);
 bool sweep_small(const SweepArgs &a, FusedBins f, bool wide, hipStream_t st);
 bool sweep_large(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, bool narrow, hipStream_t st);
 bool sweep_all(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, bool narrow, hipStream_t st);

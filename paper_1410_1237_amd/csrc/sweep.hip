@@ -94,9 +94,10 @@ __device__ __forceinline__ void flush_graph_stats(const SweepArgs &a, int grp, b
 }
 
 // adds w to community c's slot of an open-addressed LDS table of 2^shift
-// slots (linear probing; -1 marks a free slot)
+// slots (linear probing; -1 marks a free slot); the lane that claims the
+// slot adds `first` as well
 template <typename VT>
-__device__ __forceinline__ void table_add(int32_t *tkey, VT *tval, int shift, int32_t c, VT w)
+__device__ __forceinline__ void table_add(int32_t *tkey, VT *tval, int shift, int32_t c, VT w, VT first = 0)
 {
     const uint32_t mask = (1u << shift) - 1;
     uint32_t h = slot_hash(c, shift);
@@ -109,7 +110,7 @@ __device__ __forceinline__ void table_add(int32_t *tkey, VT *tval, int shift, in
         if (cur == -1) {
             cur = atomicCAS(&tkey[h], -1, c);
             if (cur == -1 || cur == c) {
-                atomicAdd(&tval[h], w);
+                atomicAdd(&tval[h], cur == -1 ? w + first : w);
                 return;
             }
         }
@@ -124,10 +125,13 @@ constexpr int GATHER_K = 4;
 
 // Gathers the entries [beg, end) of vertex i, taken by a lane at stride
 // `stride` from `first`, into the table; returns the self-loop weight seen.
-template <int WK, typename VT>
+// PK: the communities come packed with their totals (SweepArgs::cpack), and a
+// slot holds e_{i->c} in its low and a_c in its high 32 bits.
+template <int WK, typename VT, bool PK = false>
 __device__ __forceinline__ int64_t gather_row(const SweepArgs &a, int32_t i, int64_t first, int64_t end, int stride,
                                               int32_t *tkey, VT *tval, int shift)
 {
+    static_assert(!PK || sizeof(VT) == 8, "a packed slot holds e and a_c");
     int64_t wself = 0;
     for (int64_t e0 = first; e0 < end; e0 += (int64_t)GATHER_K * stride) {
         int32_t c[GATHER_K];
@@ -147,14 +151,24 @@ __device__ __forceinline__ int64_t gather_row(const SweepArgs &a, int32_t i, int
                 }
             }
         }
-        if (!a.singleton) {
+        if constexpr (PK) {
+            uint64_t p[GATHER_K];
+#pragma unroll
+            for (int k = 0; k < GATHER_K; ++k) p[k] = c[k] >= 0 ? a.cpack[c[k]] : 0;
 #pragma unroll
             for (int k = 0; k < GATHER_K; ++k)
-                if (c[k] >= 0) c[k] = a.comm_prev[c[k]];
-        }
+                if (c[k] >= 0)
+                    table_add<VT>(tkey, tval, shift, (int32_t)(uint32_t)p[k], (VT)w[k], (VT)(p[k] & ~0xffffffffull));
+        } else {
+            if (!a.singleton) {
 #pragma unroll
-        for (int k = 0; k < GATHER_K; ++k)
-            if (c[k] >= 0) table_add<VT>(tkey, tval, shift, c[k], (VT)w[k]);
+                for (int k = 0; k < GATHER_K; ++k)
+                    if (c[k] >= 0) c[k] = a.comm_prev[c[k]];
+            }
+#pragma unroll
+            for (int k = 0; k < GATHER_K; ++k)
+                if (c[k] >= 0) table_add<VT>(tkey, tval, shift, c[k], (VT)w[k]);
+        }
     }
     return wself;
 }
@@ -200,11 +214,11 @@ __device__ __forceinline__ void singleton_row(const SweepArgs &a, int32_t i, int
 
 // One block-tile of a degree bin: VPB = BLOCK / LPV vertices, LPV lanes each,
 // hash tables of 2^shift slots per vertex in LDS.
-template <int LPV, int WK, typename GT>
+template <int LPV, int WK, typename GT, bool PK>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const BinRange &br, int64_t tile, int shift,
                                            unsigned char *smem, unsigned long long *bstat)
 {
-    typedef typename std::conditional<WK == W_UNIT, uint32_t, unsigned long long>::type VT;
+    typedef typename std::conditional<WK == W_UNIT && !PK, uint32_t, unsigned long long>::type VT;
     constexpr int VPB = BLOCK / LPV;
     const int grp = threadIdx.x / LPV, lane = threadIdx.x % LPV;
     const int64_t vidx = tile * VPB + grp;
@@ -239,7 +253,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const BinRange &b
         if (valid) singleton_row<WK, GT>(a, i, ki, two_m, beg + lane, end, LPV, best, wself, distinct);
     } else {
     // gather: e_{i->c} per neighbouring community (Eq. 1), self-loop apart
-    if (valid) wself = gather_row<WK, VT>(a, i, beg + lane, end, LPV, tkey, tval, shift);
+    if (valid) wself = gather_row<WK, VT, PK>(a, i, beg + lane, end, LPV, tkey, tval, shift);
     __syncthreads();
 
     // gains over the distinct communities (Eq. 4 scaled by 2m^2), best by
@@ -252,12 +266,21 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const BinRange &b
             const int64_t s = s0 + (int64_t)k * LPV;
             c[k] = s < S ? tkey[s] : -1;
         }
+        if constexpr (!PK) {
 #pragma unroll
-        for (int k = 0; k < GATHER_K; ++k) ac[k] = (c[k] >= 0 && c[k] != A) ? a.a[c[k]] : 0;
+            for (int k = 0; k < GATHER_K; ++k) ac[k] = (c[k] >= 0 && c[k] != A) ? a.a[c[k]] : 0;
+        }
 #pragma unroll
         for (int k = 0; k < GATHER_K; ++k) {
             if (c[k] < 0) continue;
-            const int64_t e = (int64_t)tval[s0 + (int64_t)k * LPV];
+            int64_t e;
+            if constexpr (PK) {
+                const uint64_t tv = (uint64_t)tval[s0 + (int64_t)k * LPV];
+                e = (int64_t)(tv & 0xffffffffull);
+                ac[k] = (int64_t)(tv >> 32);
+            } else {
+                e = (int64_t)tval[s0 + (int64_t)k * LPV];
+            }
             ++distinct;
             if (c[k] == A) {
                 eA = e;
@@ -457,7 +480,7 @@ __device__ __forceinline__ void hub_part_tile(const SweepArgs &a, const HubArgs 
 // one tile of bin b with the bin's lanes per vertex (a launch-time choice
 // among kLaneChoices[b]); every (bin, lanes) pair is its own instance, so the
 // table size stays a compile-time constant.  LO..HI: the bins the launch has.
-template <int WK, typename GT, int LO, int HI>
+template <int WK, typename GT, int LO, int HI, bool PK = false>
 __device__ __forceinline__ void bin_tile(const SweepArgs &a, const FusedBins &f, int b, int64_t tile,
                                          unsigned char *smem, unsigned long long *bstat)
 {
@@ -465,7 +488,7 @@ __device__ __forceinline__ void bin_tile(const SweepArgs &a, const FusedBins &f,
     const int l = f.lanes[b];
 #define LV_TILE(B, L, SH)                                                                                              \
     if ((B) >= LO && (B) <= HI && b == (B) && l == (L)) {                                                             \
-        sweep_tile<L, WK, GT>(a, br, tile, SH, smem, bstat);                                                           \
+        sweep_tile<L, WK, GT, PK>(a, br, tile, SH, smem, bstat);                                                       \
         return;                                                                                                        \
     }
     LV_TILE(1, 4, 3) LV_TILE(1, 8, 3)
@@ -482,7 +505,7 @@ __device__ __forceinline__ void bin_tile(const SweepArgs &a, const FusedBins &f,
 // Fused launches: blocks are assigned to bins by block ranges.
 //  small: bins 1..5 (4..64 lanes per vertex, 512 LDS slots per block)
 //  large: bins 6..8 (64 or 256 lanes per vertex, up to 4096 slots) and hub pass 1
-template <int WK, typename GT>
+template <int WK, typename GT, bool PK>
 __global__ __launch_bounds__(BLOCK) void k_sweep_small(SweepArgs a, FusedBins f)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -490,10 +513,10 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_small(SweepArgs a, FusedBins f)
     const int64_t blk = blockIdx.x;
     int b = 1;
     while (b < 5 && blk >= f.bins[b + 1].block0) ++b;
-    bin_tile<WK, GT, 1, 5>(a, f, b, blk - f.bins[b].block0, smem, bstat);
+    bin_tile<WK, GT, 1, 5, PK>(a, f, b, blk - f.bins[b].block0, smem, bstat);
 }
 
-template <int WK, typename GT, typename VT>
+template <int WK, typename GT, typename VT, bool PK>
 __global__ __launch_bounds__(BLOCK) void k_sweep_large(SweepArgs a, FusedBins f, HubArgs h)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -505,7 +528,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_large(SweepArgs a, FusedBins f,
     }
     int b = 6;
     while (b < 8 && blk >= f.bins[b + 1].block0) ++b;
-    bin_tile<WK, GT, 6, 8>(a, f, b, blk - f.bins[b].block0, smem, bstat);
+    bin_tile<WK, GT, 6, 8, PK>(a, f, b, blk - f.bins[b].block0, smem, bstat);
 }
 
 template <int WK, typename GT, typename VT>
@@ -820,52 +843,57 @@ __global__ __launch_bounds__(HUB_BLOCK2) void k_hub_agg(SweepArgs a, HubArgs h)
 }
 
 // ---- host launchers --------------------------------------------------------
+// bytes of a table slot: community + e (+ a_c when packed)
+static size_t slot_bytes(int wk, bool pk) { return wk == W_UNIT && !pk ? 8 : 12; }
+
 // LDS of bins 1..5 of a launch: vertices per block x table slots x slot bytes
-static size_t small_lds(const FusedBins &f, int wk)
+static size_t small_lds(const FusedBins &f, int wk, bool pk)
 {
     size_t m = 0;
     for (int b = 1; b <= 5; ++b) {
         const size_t v = (size_t)(BLOCK / f.lanes[b]) << kBinShift[b];
         if (v > m) m = v;
     }
-    return m * (wk == W_UNIT ? 8 : 12);
+    return m * slot_bytes(wk, pk);
 }
 
-template <typename GT> static void small_t(const SweepArgs &a, const FusedBins &f, int64_t blocks, hipStream_t st)
+template <typename GT, bool PK>
+static void small_t(const SweepArgs &a, const FusedBins &f, int64_t blocks, hipStream_t st)
 {
-    const size_t lds = small_lds(f, a.g.wk);
+    const size_t lds = small_lds(f, a.g.wk, PK);
     switch (a.g.wk) {
-    case W_UNIT: k_sweep_small<W_UNIT, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f); break;
-    case W_I32: k_sweep_small<W_I32, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f); break;
-    default: k_sweep_small<W_I64, GT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f); break;
+    case W_UNIT: k_sweep_small<W_UNIT, GT, PK><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f); break;
+    case W_I32: k_sweep_small<W_I32, GT, PK><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f); break;
+    default: k_sweep_small<W_I64, GT, PK><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f); break;
     }
 }
 
 // dynamic LDS of a fused launch with bins up to 8 and hub pass 1
-template <int WK, typename VT> static size_t fused_lds(const FusedBins &f)
+template <int WK, typename VT> static size_t fused_lds(const FusedBins &f, bool pk)
 {
     size_t m = hub_part_lds<VT>();
     for (int b = 1; b <= 8; ++b) {
-        const size_t v = ((size_t)(BLOCK / f.lanes[b]) << kBinShift[b]) * (WK == W_UNIT ? 8 : 12);
+        const size_t v = ((size_t)(BLOCK / f.lanes[b]) << kBinShift[b]) * slot_bytes(WK, pk);
         if (v > m) m = v;
     }
     return m;
 }
 
-template <bool ALL, int WK, typename GT, typename VT>
+template <bool ALL, int WK, typename GT, typename VT, bool PK>
 static void fused_launch(const SweepArgs &a, const FusedBins &f, const HubArgs &h, int64_t blocks, hipStream_t st)
 {
-    if (ALL) k_sweep_all<WK, GT, VT><<<(unsigned)blocks, BLOCK, fused_lds<WK, VT>(f), st>>>(a, f, h);
-    else k_sweep_large<WK, GT, VT><<<(unsigned)blocks, BLOCK, fused_lds<WK, VT>(f), st>>>(a, f, h);
+    const size_t lds = fused_lds<WK, VT>(f, PK);
+    if constexpr (ALL) k_sweep_all<WK, GT, VT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h);
+    else k_sweep_large<WK, GT, VT, PK><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h);
 }
 
-template <bool ALL, typename GT, typename VT>
+template <bool ALL, typename GT, typename VT, bool PK = false>
 static void fused_t(const SweepArgs &a, const FusedBins &f, const HubArgs &h, int64_t blocks, hipStream_t st)
 {
     switch (a.g.wk) {
-    case W_UNIT: fused_launch<ALL, W_UNIT, GT, VT>(a, f, h, blocks, st); break;
-    case W_I32: fused_launch<ALL, W_I32, GT, VT>(a, f, h, blocks, st); break;
-    default: fused_launch<ALL, W_I64, GT, VT>(a, f, h, blocks, st); break;
+    case W_UNIT: fused_launch<ALL, W_UNIT, GT, VT, PK>(a, f, h, blocks, st); break;
+    case W_I32: fused_launch<ALL, W_I32, GT, VT, PK>(a, f, h, blocks, st); break;
+    default: fused_launch<ALL, W_I64, GT, VT, PK>(a, f, h, blocks, st); break;
     }
 }
 
@@ -883,6 +911,30 @@ static void fused(const SweepArgs &a, const FusedBins &f, const HubArgs &h, int6
 }
 
 
+// the packed instances: a plain sweep whose 2m fits 32 bits (then the gains
+// fit int64 and hub sums fit 32 bits)
+static bool packed(const SweepArgs &a, bool wide)
+{
+    return a.cpack && !a.singleton && !a.gid && !wide && a.two_m <= (int64_t)UINT32_MAX;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_pack_communities(const int32_t *comm, const int64_t *a, int64_t n,
+                                                            uint64_t *out)
+{
+    for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < n; j += (int64_t)gridDim.x * BLOCK) {
+        const int32_t c = comm[j];
+        out[j] = (uint64_t)(uint32_t)c | ((uint64_t)a[c] << 32);
+    }
+}
+
+void pack_communities(const int32_t *comm, const int64_t *a, int64_t n, uint64_t *out, hipStream_t st)
+{
+    if (n <= 0) return;
+    unsigned gb = grid_for(n, BLOCK * 4);
+    if (gb > 65536) gb = 65536;
+    k_pack_communities<<<gb, BLOCK, 0, st>>>(comm, a, n, out);
+}
+
 bool sweep_small(const SweepArgs &a, FusedBins f, bool wide, hipStream_t st)
 {
     int64_t blocks = 0;
@@ -891,8 +943,9 @@ bool sweep_small(const SweepArgs &a, FusedBins f, bool wide, hipStream_t st)
         blocks += (f.bins[b].count + BLOCK / f.lanes[b] - 1) / (BLOCK / f.lanes[b]);
     }
     if (blocks == 0) return false;
-    if (wide) small_t<i128>(a, f, blocks, st);
-    else small_t<int64_t>(a, f, blocks, st);
+    if (packed(a, wide)) small_t<int64_t, true>(a, f, blocks, st);
+    else if (wide) small_t<i128, false>(a, f, blocks, st);
+    else small_t<int64_t, false>(a, f, blocks, st);
     return true;
 }
 
@@ -906,7 +959,8 @@ bool sweep_large(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, b
     f.hub_block0 = blocks;
     if (h.e > h.s && !a.singleton) blocks += h.n_chunks; // from singletons the hubs need no pass 1
     if (blocks == 0) return false;
-    fused<false>(a, f, h, blocks, wide, narrow, st);
+    if (packed(a, wide) && narrow) fused_t<false, int64_t, uint32_t, true>(a, f, h, blocks, st);
+    else fused<false>(a, f, h, blocks, wide, narrow, st);
     return true;
 }
 

@@ -572,6 +572,22 @@ def test_long_empty_row_gaps(L, O):
         compare_run(res, O.run(g, oracle_params(d)), f"{g.name} {d}")
 
 
+@pytest.mark.parametrize("case", range(3))
+def test_plain_sweeps_above_one_launch_group(L, O, case):
+    """Graphs of more than 65,536 vertices sweep through the separate small-
+    and large-bin launches, where a plain sweep reads each neighbour's
+    community together with that community's total (packed beside it before
+    the sweep): unit and weighted R-MAT (scale 17) and a graph with a hub row
+    of 20,000 entries, stepped iteration by iteration and run to the end."""
+    g = [GG.rmat(17, 8, seed=7), GG.rmat(17, 8, wmax=100, seed=8),
+         hub_graph(seed=13, hub_deg=20000, extra=100000, n=80000)][case]
+    assert g.n > 65536
+    _steps(L, O, g, colored=False, vf=(case == 1), phases=2, iters=4)
+    with L.Graph.from_csr(g) as gs:
+        res = gs.run(L.params())
+    compare_run(res, O.run(g, oracle_params(dict())), g.name)
+
+
 def test_gain_bound_cases(L, O):
     """The best community need not be one of the largest edge weight: vertex 0
     (self-loop 10) has weight 3 to the heavy star centre 1 and weight 1 to the
