@@ -397,10 +397,11 @@ louvain_status sync(G *g)
 }
 
 // ---- profiling ----------------------------------------------------------------
-const char *kNames[] = {"sweep_small_bins1to5", "sweep_large_bins6to8_hub_partition", "sweep_all_bins_small_group",
-                        "sweep_hub_aggregate_decide", "commit", "coarsen", "color", "sweep_pack_communities"};
+const char *kNames[] = {"sweep_small_bins1to5", "sweep_large_bins6to7_hub_partition", "sweep_all_bins_small_group",
+                        "sweep_hub_aggregate_decide", "commit", "coarsen", "color", "sweep_pack_communities",
+                        "sweep_bin8"};
 enum { PR_SMALL = 0, PR_LARGE = 1, PR_ALL = 2, PR_HUB_AGG = 3, PR_COMMIT = 4, PR_COARSEN = 5, PR_COLOR = 6,
-       PR_PACK = 7, PR_COUNT = 8 };
+       PR_PACK = 7, PR_BIN8 = 8, PR_COUNT = 9 };
 constexpr double SMALL_GROUP = 65536; // vertices: one fused launch below this
 
 hipEvent_t take_event(G *g)
@@ -756,7 +757,12 @@ void sweep_group(G *g, int group, int singlet, bool decide_hubs = true, bool pla
             ProfScope ps(g, PR_SMALL, cnt_small, 0, 0x3e);
             lv::sweep_small(a, f, wide, g->st);
         }
-        ProfScope ps(g, PR_LARGE, cnt_large, 0, 0x7c0);
+        const double cnt8 = (double)f.bins[8].count;
+        if (cnt8 > 0) {
+            ProfScope ps(g, PR_BIN8, cnt8, 0, 0x100);
+            lv::sweep_bin8(a, f, wide, narrow, g->st);
+        }
+        ProfScope ps(g, PR_LARGE, cnt_large - cnt8, 0, 0x6c0);
         lv::sweep_large(a, f, h, wide, narrow, g->st);
     }
     if (h.e > h.s) {

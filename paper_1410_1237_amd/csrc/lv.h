@@ -373,15 +373,16 @@ constexpr int kBinShift[9] = {0, 3, 4, 5, 6, 7, 9, 11, 12};
 constexpr int kLaneChoices[9][4] = {{0}, {4, 8, 0}, {8, 4, 16, 0}, {16, 8, 32, 0}, {32, 16, 64, 0},
                                     {64, 32, 0},     {64, 256, 0}, {256, 0},     {256, 0}};
 
-// Fused sweep launches (wide = 128-bit gains, narrow = hub sums fit 32
-// bits); each returns false when it had nothing to launch.  small: bins 1..5;
-// large: bins 6..8 plus hub pass 1; all: bins 1..8 plus hub pass 1 (small
-// groups); then hub pass 2 and, in a launch of its own, the hub decisions
-// (stats in a.stats).
 // out[j] = C(j) | a_C(j) << 32 for the packed gathers (SweepArgs::cpack)
 void pack_communities(const int32_t *comm, const int64_t *a, int64_t n, uint64_t *out, hipStream_t st);
+// Fused sweep launches (wide = 128-bit gains, narrow = hub sums fit 32
+// bits); each returns false when it had nothing to launch.  small: bins 1..5;
+// large: bins 6..7 plus hub pass 1; bin8: bin 8 alone; all: bins 1..8 plus
+// hub pass 1 (small groups); then hub pass 2 and, in a launch of its own, the
+// hub decisions (stats in a.stats).
 bool sweep_small(const SweepArgs &a, FusedBins f, bool wide, hipStream_t st);
 bool sweep_large(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, bool narrow, hipStream_t st);
+bool sweep_bin8(const SweepArgs &a, const FusedBins &f, bool wide, bool narrow, hipStream_t st);
 bool sweep_all(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, bool narrow, hipStream_t st);
 // decide = false leaves the hub decisions to commit_hubs
 bool sweep_hub_agg(const SweepArgs &a, const HubArgs &h, bool wide, bool narrow, bool decide, hipStream_t st);

@@ -504,7 +504,10 @@ __device__ __forceinline__ void bin_tile(const SweepArgs &a, const FusedBins &f,
 
 // Fused launches: blocks are assigned to bins by block ranges.
 //  small: bins 1..5 (4..64 lanes per vertex, 512 LDS slots per block)
-//  large: bins 6..8 (64 or 256 lanes per vertex, up to 4096 slots) and hub pass 1
+//  large: bins 6..7 (64 or 256 lanes per vertex, up to 2048 slots) and hub pass 1
+//  bin 8: 256 lanes per vertex, 4096 slots, alone (its 48 KB tables would cap
+//         the large launch at three workgroups per CU; measured on R-MAT 24,
+//         the split took the plain sweeps' large launches from 6.7 to 4.8 ms)
 template <int WK, typename GT, bool PK>
 __global__ __launch_bounds__(BLOCK) void k_sweep_small(SweepArgs a, FusedBins f)
 {
@@ -526,9 +529,18 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_large(SweepArgs a, FusedBins f,
         hub_part_tile<WK, VT>(a, h, blk - f.hub_block0, smem);
         return;
     }
-    int b = 6;
-    while (b < 8 && blk >= f.bins[b + 1].block0) ++b;
-    bin_tile<WK, GT, 6, 8, PK>(a, f, b, blk - f.bins[b].block0, smem, bstat);
+    const int b = blk >= f.bins[7].block0 ? 7 : 6;
+    bin_tile<WK, GT, 6, 7, PK>(a, f, b, blk - f.bins[b].block0, smem, bstat);
+}
+
+// bin 8 alone (rows of 1,025-2,048 entries, 4,096-slot tables): its LDS
+// would otherwise set the occupancy of the large launch's other tiles
+template <int WK, typename GT, bool PK>
+__global__ __launch_bounds__(BLOCK) void k_sweep_bin8(SweepArgs a, FusedBins f)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ unsigned long long bstat[5];
+    bin_tile<WK, GT, 8, 8, PK>(a, f, 8, blockIdx.x, smem, bstat);
 }
 
 template <int WK, typename GT, typename VT>
@@ -869,20 +881,29 @@ static void small_t(const SweepArgs &a, const FusedBins &f, int64_t blocks, hipS
 }
 
 // dynamic LDS of a fused launch with bins up to 8 and hub pass 1
-template <int WK, typename VT> static size_t fused_lds(const FusedBins &f, bool pk)
+// dynamic LDS of a launch: the largest table among the bins lo..hi it has
+// vertices of, and hub pass 1 if it has hub tiles
+static size_t bins_lds(const FusedBins &f, int wk, bool pk, int lo, int hi)
 {
-    size_t m = hub_part_lds<VT>();
-    for (int b = 1; b <= 8; ++b) {
-        const size_t v = ((size_t)(BLOCK / f.lanes[b]) << kBinShift[b]) * slot_bytes(WK, pk);
+    size_t m = 0;
+    for (int b = lo; b <= hi; ++b) {
+        if (f.bins[b].count == 0) continue;
+        const size_t v = ((size_t)(BLOCK / f.lanes[b]) << kBinShift[b]) * slot_bytes(wk, pk);
         if (v > m) m = v;
     }
     return m;
 }
 
+template <int WK, typename VT> static size_t fused_lds(const FusedBins &f, bool pk, int hi, bool hubs)
+{
+    const size_t m = bins_lds(f, WK, pk, 1, hi);
+    return hubs && hub_part_lds<VT>() > m ? hub_part_lds<VT>() : m;
+}
+
 template <bool ALL, int WK, typename GT, typename VT, bool PK>
 static void fused_launch(const SweepArgs &a, const FusedBins &f, const HubArgs &h, int64_t blocks, hipStream_t st)
 {
-    const size_t lds = fused_lds<WK, VT>(f, PK);
+    const size_t lds = fused_lds<WK, VT>(f, PK, ALL ? 8 : 7, blocks > f.hub_block0);
     if constexpr (ALL) k_sweep_all<WK, GT, VT><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h);
     else k_sweep_large<WK, GT, VT, PK><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f, h);
 }
@@ -949,13 +970,36 @@ bool sweep_small(const SweepArgs &a, FusedBins f, bool wide, hipStream_t st)
     return true;
 }
 
+template <typename GT, bool PK>
+static void bin8_t(const SweepArgs &a, const FusedBins &f, int64_t blocks, hipStream_t st)
+{
+    const size_t lds = bins_lds(f, a.g.wk, PK, 8, 8);
+    switch (a.g.wk) {
+    case W_UNIT: k_sweep_bin8<W_UNIT, GT, PK><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f); break;
+    case W_I32: k_sweep_bin8<W_I32, GT, PK><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f); break;
+    default: k_sweep_bin8<W_I64, GT, PK><<<(unsigned)blocks, BLOCK, lds, st>>>(a, f); break;
+    }
+}
+
+bool sweep_bin8(const SweepArgs &a, const FusedBins &f, bool wide, bool narrow, hipStream_t st)
+{
+    const int64_t blocks = (f.bins[8].count + BLOCK / f.lanes[8] - 1) / (BLOCK / f.lanes[8]);
+    if (blocks == 0) return false;
+    if (packed(a, wide) && narrow) bin8_t<int64_t, true>(a, f, blocks, st);
+    else if (wide) bin8_t<i128, false>(a, f, blocks, st);
+    else bin8_t<int64_t, false>(a, f, blocks, st);
+    return true;
+}
+
 bool sweep_large(const SweepArgs &a, FusedBins f, const HubArgs &h, bool wide, bool narrow, hipStream_t st)
 {
     int64_t blocks = 0;
-    for (int b = 6; b <= 8; ++b) {
+    for (int b = 6; b <= 7; ++b) {
         f.bins[b].block0 = blocks;
         blocks += (f.bins[b].count + BLOCK / f.lanes[b] - 1) / (BLOCK / f.lanes[b]);
     }
+    f.bins[8].block0 = blocks; // bin 8 has a launch of its own
+    f.bins[8].count = 0;
     f.hub_block0 = blocks;
     if (h.e > h.s && !a.singleton) blocks += h.n_chunks; // from singletons the hubs need no pass 1
     if (blocks == 0) return false;

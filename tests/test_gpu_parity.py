@@ -584,8 +584,14 @@ def test_plain_sweeps_above_one_launch_group(L, O, case):
     assert g.n > 65536
     _steps(L, O, g, colored=False, vf=(case == 1), phases=2, iters=4)
     with L.Graph.from_csr(g) as gs:
+        gs.profile(True)
         res = gs.run(L.params())
+        recs = {r["name"]: r for r in gs.profile_records()}
     compare_run(res, O.run(g, oracle_params(dict())), g.name)
+    # every swept entry is charged to exactly one launch record
+    assert sum(r["entries"] for n, r in recs.items() if n.startswith("sweep")) == \
+        res.sweep_entries + res.lookahead_entries
+    assert recs["sweep_pack_communities"]["launches"] > 0
 
 
 def test_gain_bound_cases(L, O):
